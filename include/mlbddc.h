@@ -1,0 +1,209 @@
+/*
+ * mlbddc.h -- C ABI of the MI355X multilevel BDDC library.
+ *
+ * The library solves K u = f for a finite-element stiffness matrix K by
+ * preconditioned conjugate gradients on the reduced interface problem
+ * S^ u^ = g^ (Sistek, Mandel, Sousedik, Burda, "Parallel implementation of
+ * Multilevel BDDC", section 2), with the multilevel BDDC preconditioner of
+ * Algorithms 1 (set-up) and 2 (apply).  All numerical work runs in HIP
+ * kernels on one gfx950 device; host code only plans index structures.
+ *
+ * Conventions
+ *  - Every entry point returns an mlbddc_status: 0 on success, a negative
+ *    code on failure.  Nothing throws or aborts across the ABI.  After a
+ *    failure, mlbddc_last_error() describes it.
+ *  - "host" pointers are read during the call only; the library copies what
+ *    it keeps.  "device" pointers are borrowed for the call, must hold the
+ *    stated number of elements, and must not alias each other.
+ *  - All device work is ordered on the stream given to mlbddc_create (0 =
+ *    the null stream).  Calls return once the work is queued unless stated.
+ *  - A handle is not thread-safe.
+ *  - Vectors of free DOFs are numbered as follows: free nodes in increasing
+ *    node order, node components innermost (DOF = free_node * ndof + c).
+ *    Interface vectors are numbered by increasing free-DOF index.
+ */
+#ifndef MLBDDC_H
+#define MLBDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mlbddc_status;
+typedef struct mlbddc_handle_s* mlbddc_t;
+
+enum {
+  MLBDDC_OK = 0,
+  MLBDDC_E_ARG = -1,              /* invalid argument or inconsistent mesh / partition */
+  MLBDDC_E_HIP = -2,              /* a HIP runtime call failed */
+  MLBDDC_E_NOMEM = -3,            /* device or host allocation failed */
+  MLBDDC_E_STATE = -4,            /* call out of order (e.g. apply before setup) */
+  MLBDDC_E_NOT_SPD = -5,          /* non-positive pivot in a subdomain factorization */
+  MLBDDC_E_SINGULAR_CONSTRAINTS = -6, /* constrained local problem singular */
+  MLBDDC_E_NOT_CONVERGED = -7,    /* PCG reached max_iter; u holds the last iterate */
+  MLBDDC_E_BREAKDOWN = -8,        /* PCG breakdown: p^T S p <= 0 or not finite */
+  MLBDDC_E_NO_DEVICE = -9         /* no usable HIP device */
+};
+
+enum { MLBDDC_FP64 = 0, MLBDDC_MIXED = 1 };                  /* precision modes */
+enum { MLBDDC_CORNERS = 1, MLBDDC_EDGES = 2, MLBDDC_FACES = 4, MLBDDC_ALL_PRIMAL = 8 };
+enum { MLBDDC_W_STIFFNESS = 0, MLBDDC_W_MULTIPLICITY = 1 };  /* interface weights */
+enum { MLBDDC_POISSON_Q1 = 0, MLBDDC_ELASTICITY_HEX8 = 1 };  /* element kinds */
+
+typedef struct {
+  int32_t precision;   /* MLBDDC_FP64: every factor in FP64.  MLBDDC_MIXED: the
+                          preconditioner's local factors and solves in FP32; the
+                          interface operator S^, PCG vectors and dots, weights and
+                          the top coarse factor stay FP64. */
+  double rtol;         /* PCG stop: ||r^|| / ||g^|| < rtol (default 1e-8) */
+  int32_t max_iter;    /* default 1000 */
+  int32_t weights;     /* MLBDDC_W_* */
+  int32_t use_graph;   /* capture one PCG iteration as a HIP graph (1) or launch eagerly (0) */
+  int32_t panel_tiles; /* tile columns per factorization panel (0 = autotuned) */
+  int32_t device;      /* HIP device ordinal */
+} mlbddc_options;
+
+typedef struct {
+  int32_t dim;               /* 2 or 3 */
+  int32_t ndof_per_node;     /* 1 (Poisson) or dim (elasticity) */
+  int64_t n_nodes;
+  int64_t n_elems;
+  int32_t nodes_per_elem;    /* 4 (quadrilateral) or 8 (hexahedron) */
+  const int32_t* elem_nodes; /* host [n_elems * nodes_per_elem] */
+  const double* elem_matrix_ref; /* host [nd * nd], nd = nodes_per_elem * ndof_per_node;
+                                    unit-modulus element matrix K_e^0, DOFs node-major */
+  const double* elem_scale;  /* host [n_elems]: element modulus E_e (K_e = E_e K_e^0) */
+  const uint8_t* dirichlet_nodes; /* host [n_nodes]: 1 = all components fixed to zero */
+} mlbddc_mesh;
+
+typedef struct {
+  int32_t n_levels;             /* L >= 2: levels 1..L-1 are BDDC levels, level L the coarse problem */
+  const int32_t* elem_to_sub;   /* host [n_elems]: level-1 subdomain of every element, 0..N1-1 */
+  const int32_t* const* sub_to_parent; /* host [L-2] arrays: for l = 2..L-1, the level-l
+                                          subdomain of every level-(l-1) subdomain */
+  int32_t constraints;          /* MLBDDC_CORNERS | MLBDDC_EDGES | MLBDDC_FACES on every level, or
+                                   MLBDDC_ALL_PRIMAL (every interface node primal, level 1) */
+} mlbddc_partition;
+
+typedef struct {
+  int32_t iterations;  /* operator applications of PCG */
+  int32_t converged;
+  double rel_res;      /* final ||r^|| / ||g^|| (recursive residual) */
+  double lambda_min;   /* Lanczos estimates of the spectrum of M S^ */
+  double lambda_max;
+  double t_plan;       /* seconds: host planning in the last setup */
+  double t_setup_num;  /* seconds: numeric set-up (device) in the last setup/update */
+  double t_solve;      /* seconds: condensation + PCG + interior recovery */
+} mlbddc_stats;
+
+typedef struct {
+  mlbddc_status status;
+  int32_t level;       /* 1-based level of a factorization failure, else 0 */
+  int32_t subdomain;   /* subdomain of a factorization failure, else -1 */
+  int32_t column;      /* local column of a factorization failure, else -1 */
+  char message[256];
+} mlbddc_error;
+
+/* Text of a status code.  Never fails. */
+const char* mlbddc_status_string(mlbddc_status code);
+
+/* Default options (FP64, rtol 1e-8, max_iter 1000, stiffness weights, no graph). */
+void mlbddc_default_options(mlbddc_options* opt);
+
+/* Create a handle on options->device, ordering all work on `stream`
+ * (a hipStream_t passed as void*).  *h receives the handle. */
+mlbddc_status mlbddc_create(mlbddc_t* h, const mlbddc_options* opt, void* stream);
+
+/* Set-up (Algorithm 1): plan the levels from the mesh and partition on the
+ * host (interface classification into faces, edges and vertices; corner
+ * selection; constraint rows of C_i; weights E_i; pseudo-mesh of every next
+ * level), then on the device assemble the subdomain matrices K_i, factorize
+ * their interiors, form the local Schur complements, factorize the
+ * constrained local problems of Eq. (1), form the coarse bases Psi_i and the
+ * coarse matrices K_Ci, assemble the next level and recurse; factorize the
+ * top coarse matrix.  Synchronizes the stream.
+ * Errors: E_ARG (bad maps, empty subdomain, element in no subdomain),
+ * E_NOT_SPD (level, subdomain and column in mlbddc_last_error),
+ * E_SINGULAR_CONSTRAINTS, E_NOMEM, E_HIP. */
+mlbddc_status mlbddc_setup(mlbddc_t h, const mlbddc_mesh* mesh, const mlbddc_partition* part);
+
+/* Redo the numeric set-up with new element moduli (device [n_elems] FP64),
+ * keeping the planned structure.  Synchronizes the stream.  Errors as setup. */
+mlbddc_status mlbddc_update_coefficients(mlbddc_t h, const double* elem_scale_dev);
+
+/* Sizes after setup: free DOFs, level-1 interface size, coarse size of
+ * level `level` (1-based, 1..L-1), number of level-l subdomains. */
+int64_t mlbddc_num_dofs(mlbddc_t h);
+int64_t mlbddc_interface_size(mlbddc_t h);
+int64_t mlbddc_coarse_size(mlbddc_t h, int32_t level);
+int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level);
+
+/* z^ = M_BDDC r^ (one application of Algorithm 2) on the level-1 interface.
+ * r_dev, z_dev: device FP64 [interface_size].  Asynchronous.  E_STATE before setup. */
+mlbddc_status mlbddc_apply(mlbddc_t h, const double* r_dev, double* z_dev);
+
+/* y = S^ x, the interface Schur complement (section 2).  Device FP64
+ * [interface_size].  Asynchronous.  E_STATE before setup. */
+mlbddc_status mlbddc_apply_schur(mlbddc_t h, const double* x_dev, double* y_dev);
+
+/* Condensed right-hand side g^ = f_G - sum_i R_i^T K_GI K_II^{-1} f_I.
+ * f_dev: device FP64 [num_dofs]; g_dev: device FP64 [interface_size]. */
+mlbddc_status mlbddc_condense(mlbddc_t h, const double* f_dev, double* g_dev);
+
+/* Solve K u = f: condense, run BDDC-preconditioned CG on the interface from
+ * u^_0 = 0 (or the interface part of u0_dev when not NULL) until
+ * ||r^||/||g^|| < rtol, recover the interiors.  f_dev, u_dev, u0_dev: device
+ * FP64 [num_dofs].  Synchronizes the stream; fills *st when not NULL.
+ * Errors: E_NOT_CONVERGED (u holds the last iterate), E_BREAKDOWN, E_STATE. */
+mlbddc_status mlbddc_solve(mlbddc_t h, const double* f_dev, double* u_dev, const double* u0_dev,
+                           mlbddc_stats* st);
+
+/* out_e = E_e a_e^T K_e^0 b_e for free-DOF vectors a, b (device FP64
+ * [num_dofs]; fixed DOFs count as zero); out_dev: device FP64 [n_elems].
+ * With a = lambda (adjoint) and b = u this is the element sensitivity
+ * -dJ/dtheta_e of J = f^T u for E_e = exp(theta_e). */
+mlbddc_status mlbddc_element_energy(mlbddc_t h, const double* a_dev, const double* b_dev, double* out_dev);
+
+/* Copy a level's coarse matrix K_C (dense, row-major, coarse_size^2 FP64)
+ * to host memory; for tests. */
+mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* host_out);
+
+/* Release all device and host memory of the handle. */
+mlbddc_status mlbddc_destroy(mlbddc_t h);
+
+/* Description of the last failure on this handle (or of the last failed
+ * mlbddc_create when h is NULL). */
+mlbddc_status mlbddc_last_error(mlbddc_t h, mlbddc_error* info);
+
+/* ---------------------------------------------------------------------------
+ * Host-only helpers (no device needed).
+ * ------------------------------------------------------------------------- */
+
+/* Unit-modulus element matrix K_e^0 of a structured element of side h:
+ * kind MLBDDC_POISSON_Q1 (4 x 4, -Laplace, bilinear square) or
+ * MLBDDC_ELASTICITY_HEX8 (24 x 24, trilinear cube, isotropic with Poisson
+ * ratio nu, 2x2x2 Gauss rule).  out: host, row-major. */
+mlbddc_status mlbddc_element_matrix(int32_t kind, double h, double nu, double* out);
+
+/* Consistent nodal load of a constant source / body force on one element:
+ * out[node * ndof + c] = force[c] * volume / nodes. */
+mlbddc_status mlbddc_element_load(int32_t kind, double h, const double* force, double* out);
+
+/* Plan the decomposition on the host only and report its structure:
+ * counts[level-1][0..5] = {subdomains, interface DOFs, coarse DOFs, corners,
+ * edges, faces} for levels 1..L-1.  counts: host [(L-1) * 6]. */
+mlbddc_status mlbddc_plan_counts(const mlbddc_mesh* mesh, const mlbddc_partition* part, int64_t* counts);
+
+/* Level-1 plan details for tests: interface free-DOF list (host
+ * [interface_size]) and, for subdomain `sub`, its local interface DOFs as
+ * interface indices (host [n_gamma]) with their multiplicity weights.
+ * Pass NULL for outputs not wanted; *n_gamma receives the count. */
+mlbddc_status mlbddc_plan_interface(const mlbddc_mesh* mesh, const mlbddc_partition* part, int64_t* iface_dofs,
+                                    int32_t sub, int64_t* n_gamma, int64_t* sub_iface);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLBDDC_H */

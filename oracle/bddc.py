@@ -39,7 +39,7 @@ class MultilevelBDDC:
     """
 
     def __init__(self, w, n_levels: Optional[int] = None, constraints: Optional[Sequence[str]] = None,
-                 weights: str = "stiffness"):
+                 weights: str = "stiffness", structure_only: bool = False):
         L = w.n_levels if n_levels is None else n_levels
         if L < 2 or L - 2 > len(w.sub_to_parent):
             raise ValueError("not enough level groupings for the requested number of levels")
@@ -51,15 +51,17 @@ class MultilevelBDDC:
         node_to_free, n_free = dof_numbering(w)
         self.node_to_free, self.n_free = node_to_free, n_free
         blocks = level_one_blocks(w, Ke0, node_to_free)
-        levels: List[Level] = [Level(w.dim, w.ndof, n_free // w.ndof, blocks, constraints[0], weights)]
+        levels: List[Level] = [Level(w.dim, w.ndof, n_free // w.ndof, blocks, constraints[0], weights, structure_only)]
         for l in range(2, L):
             prev = levels[-1]
             parent = np.asarray(w.sub_to_parent[l - 2])
             el = prev.next_level_blocks()
             grouped = [[el[i] for i in np.nonzero(parent == p)[0]] for p in range(int(parent.max()) + 1)]
-            levels.append(Level(w.dim, w.ndof, prev.n_coarse_nodes, grouped, constraints[l - 1], weights))
+            levels.append(Level(w.dim, w.ndof, prev.n_coarse_nodes, grouped, constraints[l - 1], weights,
+                                structure_only))
         self.levels = levels
-        self.top_solve = dense_cholesky_solve(levels[-1].KC)
+        if not structure_only:
+            self.top_solve = dense_cholesky_solve(levels[-1].KC)
 
     # ----------------------------------------------------------------- apply
     def apply(self, r_hat: np.ndarray) -> np.ndarray:

@@ -79,7 +79,7 @@ class Level:
     """
 
     def __init__(self, dim: int, ndof: int, n_nodes: int, blocks: Sequence[List[Tuple[np.ndarray, np.ndarray]]],
-                 constraints: str = "cef", weights: str = "stiffness"):
+                 constraints: str = "cef", weights: str = "stiffness", structure_only: bool = False):
         self.dim, self.ndof, self.n_nodes = dim, ndof, n_nodes
         self.n_dofs = n_nodes * ndof
         self.n_sub = len(blocks)
@@ -187,6 +187,11 @@ class Level:
             self.D = [1.0 / mult[self.R[i]] for i in range(self.n_sub)]
         else:
             raise ValueError(weights)
+
+        if structure_only:
+            # index structure only (interface, globs, coarse numbering); no factorizations
+            self.KC_loc = [np.zeros((len(rc), len(rc))) for rc in self.RC]
+            return
 
         # --- interior factorizations (Algorithm 1: interior correction / Dirichlet problems)
         self.KII_lu, self.KIG, self.KGG = [], [], []

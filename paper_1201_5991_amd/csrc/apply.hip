@@ -1,0 +1,419 @@
+// Per-iteration kernels of the multilevel BDDC-PCG for gfx950: batched
+// tile-block matrix-vector products (the interface operator S^, the explicit
+// local BDDC operators and coarse bases), weighted gathers and atomic-free
+// segmented reductions for restriction / averaging (E_i^T and E_i), blocked
+// triangular solves for condensation and interior recovery, and the PCG
+// vector operations with device-resident scalars.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace mlbddc {
+
+namespace {
+
+// ---------------------------------------------------------------- tile mv
+// One workgroup per stored tile of the block: reads the tile once and forms
+// both A x_s (for the tile's row) and, for symmetric blocks, A^T x_r (for its
+// column); results go to a partial-sum array reduced by k_mv_reduce.
+template <typename TA, typename TX>
+__global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __restrict__ d, int nitems,
+                                                  const int64_t* __restrict__ prefix, const TA* __restrict__ A,
+                                                  const TX* __restrict__ x, TA* __restrict__ P) {
+  const int64_t bid = blockIdx.x;
+  int lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= bid) lo = mid; else hi = mid;
+  }
+  const MvDesc D = d[lo];
+  int64_t local = bid - prefix[lo];
+  int r, s;
+  if (mode == MV_SYM) {
+    // column-major unranking of the lower tiles of an nr x nr block
+    s = 0;
+    int64_t rem = local;
+    while (rem >= D.nr - s) { rem -= D.nr - s; ++s; }
+    r = s + (int)rem;
+  } else {
+    r = (int)(local % D.nr);
+    s = (int)(local / D.nr);
+  }
+  const int R = D.r0 + r, S = D.c0 + s;
+  const int t = threadIdx.x;
+  __shared__ TA red[16][TS];
+  const bool zero = D.env && S < D.env[R];
+  TA u_out = 0, v_part[4] = {0, 0, 0, 0};
+  const int a0 = 4 * (t & 15), g = t >> 4;
+  if (!zero) {
+    const TA* tile = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
+    const TX* xs = x + D.x_off + (int64_t)s * TS;
+    const TX* xr = x + D.x_off + (int64_t)(mode == MV_T ? r : r) * TS;
+    TA up[4] = {0, 0, 0, 0};
+    TA xra[4];
+    const bool need_v = (mode == MV_T) || (mode == MV_SYM && r != s);
+    const bool need_u = mode != MV_T;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xra[i] = need_v ? (TA)xr[a0 + i] : (TA)0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int b = g + 16 * m;
+      const TA* col = tile + b * TS + a0;
+      TA av[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = col[i];
+      const TA xb = need_u ? (TA)xs[b] : (TA)0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        up[i] += av[i] * xb;
+        v_part[m] += av[i] * xra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[g][a0 + i] = up[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[g][a0 + i] = 0;
+  }
+  // reduce v over the 16 lanes sharing g
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    for (int off = 8; off > 0; off >>= 1) v_part[m] += __shfl_xor(v_part[m], off, 16);
+  __syncthreads();
+  if (t < TS) {
+    TA acc = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += red[q][t];
+    u_out = acc;
+  }
+  TA* pbase = P + D.p_off;
+  if (mode == MV_SYM) {
+    if (t < TS) pbase[((int64_t)r * D.nr + s) * TS + t] = u_out;
+    if (r != s && (t & 15) == 0)
+      for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[m];
+  } else if (mode == MV_N) {
+    if (t < TS) pbase[((int64_t)r * D.nc + s) * TS + t] = u_out;
+  } else {
+    if ((t & 15) == 0)
+      for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[m];
+  }
+}
+
+template <typename TA, typename TY>
+__global__ void __launch_bounds__(64) k_mv_reduce(int mode, const MvDesc* __restrict__ d, const TA* __restrict__ P, TY* y,
+                                                  double alpha, int accumulate) {
+  const MvDesc D = d[blockIdx.y];
+  const int i = blockIdx.x;
+  const int nout = mode == MV_T ? D.nc : D.nr;
+  const int nsum = mode == MV_N ? D.nc : D.nr;
+  if (i >= nout) return;
+  const TA* p = P + D.p_off + (int64_t)i * nsum * TS + threadIdx.x;
+  double acc = 0.0;
+  for (int j = 0; j < nsum; ++j) acc += (double)p[(int64_t)j * TS];
+  TY* yy = y + D.y_off + (int64_t)i * TS + threadIdx.x;
+  double v = alpha * acc;
+  if (accumulate) v += (double)*yy;
+  *yy = (TY)v;
+}
+
+// --------------------------------------------------------- gather / scatter
+template <typename TI, typename TO>
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ idx, const double* __restrict__ w, const TI* __restrict__ in,
+                         TO* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = idx[i];
+    double v = j >= 0 ? (double)in[j] : 0.0;
+    if (w) v *= w[i];
+    out[i] = (TO)v;
+  }
+}
+
+template <typename TI>
+__global__ void k_seg_reduce(int64_t n, const int64_t* __restrict__ ptr, const int64_t* __restrict__ list,
+                             const double* __restrict__ w, const TI* __restrict__ in, double* __restrict__ out, double beta) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    double acc = beta != 0.0 ? beta * out[g] : 0.0;
+    for (int64_t j = ptr[g]; j < ptr[g + 1]; ++j) {
+      int64_t q = list[j];
+      acc += (w ? w[q] : 1.0) * (double)in[q];
+    }
+    out[g] = acc;
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* __restrict__ in, TO* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t j = idx[i];
+    if (j >= 0) out[j] = (TO)in[i];
+  }
+}
+
+// ------------------------------------------------------------------ trsv
+// (L v)_tile products inside one workgroup: out[a] -= sum_b L(a, b) v[b]
+__device__ inline void tile_mv_lds(const double* __restrict__ L, const double* __restrict__ v, double* __restrict__ red,
+                                   bool trans) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double acc = 0.0;
+  if (!trans) {
+    for (int b = w * 16; b < w * 16 + 16; ++b) acc += L[b * TS + lane] * v[b];
+    red[w * TS + lane] = acc;
+  } else {
+    // out[b] = sum_a L(a, b) v[a]: wave w handles b = w*16 .. +16, lane = a
+    for (int b = w * 16; b < w * 16 + 16; ++b) {
+      double p = L[b * TS + lane] * v[lane];
+      for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+      if (lane == 0) red[b] = p;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_trsv(int trans, const TrsvDesc* __restrict__ d, const double* __restrict__ A,
+                                              const double* __restrict__ Inv, double* v) {
+  const TrsvDesc D = d[blockIdx.x];
+  __shared__ double acc[TS], sv[TS], red[4 * TS];
+  const int t = threadIdx.x;
+  const double* base = A + D.a_off;
+  double* vv = v + D.v_off;
+  for (int step = 0; step < D.nti; ++step) {
+    const int k = trans ? D.nti - 1 - step : step;
+    if (t < TS) acc[t] = vv[(int64_t)k * TS + t];
+    __syncthreads();
+    if (!trans) {
+      for (int s = D.env ? D.env[k] : 0; s < k; ++s) {
+        if (t < TS) sv[t] = vv[(int64_t)s * TS + t];
+        __syncthreads();
+        tile_mv_lds(base + tile_index(k, s, D.a_nt) * TE, sv, red, false);
+        __syncthreads();
+        if (t < TS) acc[t] -= red[t] + red[TS + t] + red[2 * TS + t] + red[3 * TS + t];
+        __syncthreads();
+      }
+    } else {
+      for (int r = k + 1; r < D.nti; ++r) {
+        if (D.env && D.env[r] > k) continue;
+        if (t < TS) sv[t] = vv[(int64_t)r * TS + t];
+        __syncthreads();
+        tile_mv_lds(base + tile_index(r, k, D.a_nt) * TE, sv, red, true);
+        __syncthreads();
+        if (t < TS) acc[t] -= red[t];
+        __syncthreads();
+      }
+    }
+    // v_k = W acc (or W^T acc) with the stored inverse diagonal tile
+    const double* W = Inv + D.inv_off + (int64_t)k * TE;
+    if (!trans) {
+      tile_mv_lds(W, acc, red, false);
+      __syncthreads();
+      if (t < TS) vv[(int64_t)k * TS + t] = red[t] + red[TS + t] + red[2 * TS + t] + red[3 * TS + t];
+    } else {
+      tile_mv_lds(W, acc, red, true);
+      __syncthreads();
+      if (t < TS) vv[(int64_t)k * TS + t] = red[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- PCG
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(int nb, const double* __restrict__ partial, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_pcg_alpha(double* s, double* hist, int it) {
+  s[S_ALPHA] = s[S_RZ] / s[S_PQ];
+  if (hist) hist[2 * it] = s[S_ALPHA];
+}
+__global__ void k_pcg_beta(double* s, double* hist, int it) {
+  s[S_BETA] = s[S_RZNEW] / s[S_RZ];
+  s[S_RZ] = s[S_RZNEW];
+  if (hist) hist[2 * it + 1] = s[S_BETA];
+}
+__global__ void k_pcg_update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                                const double* __restrict__ q, const double* __restrict__ s) {
+  const double a = s[S_ALPHA];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    r[i] -= a * q[i];
+  }
+}
+__global__ void k_pcg_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ s) {
+  const double b = s[S_BETA];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + b * p[i];
+}
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = v;
+}
+
+__global__ void k_element_energy(int64_t ne, int nloc, const int32_t* __restrict__ edof, const double* __restrict__ K0,
+                                 const double* __restrict__ scale, const double* __restrict__ a, const double* __restrict__ b,
+                                 double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    double av[24], bv[24];
+    for (int i = 0; i < nloc; ++i) {
+      int32_t j = edof[e * nloc + i];
+      av[i] = j >= 0 ? a[j] : 0.0;
+      bv[i] = j >= 0 ? b[j] : 0.0;
+    }
+    double s = 0.0;
+    for (int i = 0; i < nloc; ++i) {
+      double t = 0.0;
+      for (int j = 0; j < nloc; ++j) t += K0[i * nloc + j] * bv[j];
+      s += av[i] * t;
+    }
+    out[e] = scale[e] * s;
+  }
+}
+
+template <typename T>
+__global__ void k_gather64(int64_t n, const int64_t* __restrict__ pos, const T* __restrict__ A, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (double)A[pos[i]];
+}
+__global__ void k_ratio(int64_t n, const double* __restrict__ d, const double* __restrict__ s, const int32_t* __restrict__ idx,
+                        double* __restrict__ w) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = idx[i] >= 0 ? d[i] / s[i] : 0.0;
+}
+__global__ void k_scatter_idx(int64_t n, const int32_t* __restrict__ idx, const double* __restrict__ in,
+                              double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[idx[i]] = in[i];
+}
+
+inline unsigned grid_for(int64_t n, int block = 256) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+}
+
+}  // namespace
+
+template <typename TA, typename TX, typename TY>
+void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles, const int64_t* tile_prefix,
+                    const TA* A, const TX* x, TY* y, double alpha, bool accumulate, TA* partials, int32_t max_out_tiles) {
+  if (nitems <= 0 || total_tiles <= 0) return;
+  hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
+                     partials);
+  hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(64), 0, st, mode, d,
+                     partials, y, alpha, accumulate ? 1 : 0);
+}
+
+template <typename TI, typename TO>
+void launch_gather(hipStream_t st, int64_t n, const int32_t* idx, const double* w, const TI* in, TO* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_gather<TI, TO>), dim3(grid_for(n)), dim3(256), 0, st, n, idx, w, in, out);
+}
+
+template <typename TI>
+void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
+                       double* out, double beta) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_seg_reduce<TI>), dim3(grid_for(n)), dim3(256), 0, st, n, ptr, list, w, in, out, beta);
+}
+
+template <typename TI, typename TO>
+void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_scatter<TI, TO>), dim3(grid_for(n)), dim3(256), 0, st, n, idx, in, out);
+}
+
+void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
+                 double* v) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(256), 0, st, transposed ? 1 : 0, d, A, Inv, v);
+}
+
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblocks), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, nblocks, partial, out);
+}
+
+void launch_pcg_alpha(hipStream_t st, double* s, double* hist, int it) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, st, s, hist, it);
+}
+void launch_pcg_beta(hipStream_t st, double* s, double* hist, int it) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s, hist, it);
+}
+void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q, const double* s) {
+  hipLaunchKernelGGL(k_pcg_update_xr, dim3(grid_for(n)), dim3(256), 0, st, n, x, r, p, q, s);
+}
+void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s) {
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(grid_for(n)), dim3(256), 0, st, n, p, z, s);
+}
+void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, n, a, x, b, y);
+}
+void launch_fill(hipStream_t st, int64_t n, double v, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, st, n, v, y);
+}
+void launch_element_energy(hipStream_t st, int64_t ne, int nloc, const int32_t* edof, const double* K0, const double* scale,
+                           const double* a, const double* b, double* out) {
+  if (ne <= 0) return;
+  hipLaunchKernelGGL(k_element_energy, dim3(grid_for(ne)), dim3(256), 0, st, ne, nloc, edof, K0, scale, a, b, out);
+}
+
+template <typename T>
+void launch_gather64(hipStream_t st, int64_t n, const int64_t* pos, const T* A, double* out) {
+  if (n > 0) hipLaunchKernelGGL(k_gather64<T>, dim3(grid_for(n)), dim3(256), 0, st, n, pos, A, out);
+}
+template void launch_gather64<float>(hipStream_t, int64_t, const int64_t*, const float*, double*);
+template void launch_gather64<double>(hipStream_t, int64_t, const int64_t*, const double*, double*);
+void launch_ratio(hipStream_t st, int64_t n, const double* d, const double* s, const int32_t* idx, double* w) {
+  if (n > 0) hipLaunchKernelGGL(k_ratio, dim3(grid_for(n)), dim3(256), 0, st, n, d, s, idx, w);
+}
+void launch_scatter_idx(hipStream_t st, int64_t n, const int32_t* idx, const double* in, double* out) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter_idx, dim3(grid_for(n)), dim3(256), 0, st, n, idx, in, out);
+}
+
+#define INST_MV(TA, TX, TY)                                                                                             \
+  template void launch_tile_mv<TA, TX, TY>(hipStream_t, int, const MvDesc*, int32_t, int64_t, const int64_t*, const TA*, \
+                                           const TX*, TY*, double, bool, TA*, int32_t);
+INST_MV(double, double, double)
+INST_MV(float, float, float)
+INST_MV(float, float, double)
+INST_MV(double, double, float)
+#undef INST_MV
+template void launch_gather<double, double>(hipStream_t, int64_t, const int32_t*, const double*, const double*, double*);
+template void launch_gather<double, float>(hipStream_t, int64_t, const int32_t*, const double*, const double*, float*);
+template void launch_gather<float, float>(hipStream_t, int64_t, const int32_t*, const double*, const float*, float*);
+template void launch_gather<float, double>(hipStream_t, int64_t, const int32_t*, const double*, const float*, double*);
+template void launch_seg_reduce<double>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const double*,
+                                        double*, double);
+template void launch_seg_reduce<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
+                                       double*, double);
+template void launch_scatter<double, double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
+template void launch_scatter<float, float>(hipStream_t, int64_t, const int32_t*, const float*, float*);
+template void launch_scatter<double, float>(hipStream_t, int64_t, const int32_t*, const double*, float*);
+template void launch_scatter<float, double>(hipStream_t, int64_t, const int32_t*, const float*, double*);
+
+}  // namespace mlbddc

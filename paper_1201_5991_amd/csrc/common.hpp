@@ -1,0 +1,55 @@
+// Shared definitions of the MI355X multilevel BDDC library: tile layout,
+// status plumbing and small host helpers.
+//
+// Every dense matrix in the library (subdomain matrices, augmented local
+// problems, coarse matrices) is stored "tile-packed lower": the matrix is cut
+// into 64x64 tiles, only tiles (r, s) with r >= s are stored, tiles are laid
+// out column after column (tile column s holds tiles s..nt-1), and each tile
+// is a contiguous 64x64 column-major block.  Diagonal tiles hold both
+// triangles.  A tile is one 32 KiB (FP64) or 16 KiB (FP32) coalesced burst.
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mlbddc.h"
+
+namespace mlbddc {
+
+constexpr int TS = 64;             // tile edge
+constexpr int TE = TS * TS;        // elements per tile
+
+// Offset (in tiles) of tile (r, s), r >= s, in a tile-packed lower matrix of nt x nt tiles.
+__host__ __device__ inline int64_t tile_col_start(int64_t s, int64_t nt) { return s * nt - s * (s - 1) / 2; }
+__host__ __device__ inline int64_t tile_index(int64_t r, int64_t s, int64_t nt) { return tile_col_start(s, nt) + (r - s); }
+__host__ __device__ inline int64_t packed_tiles(int64_t nt) { return nt * (nt + 1) / 2; }
+
+// Element offset of entry (p, q) (p/64 >= q/64 required) in a tile-packed matrix.
+__host__ __device__ inline int64_t packed_offset(int64_t p, int64_t q, int64_t nt) {
+  return tile_index(p / TS, q / TS, nt) * TE + (q % TS) * TS + (p % TS);
+}
+
+inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
+// Factorization task packing: item (24 bits), r (13), s (13), kf (13).
+__host__ __device__ inline uint64_t pack_task(uint64_t item, uint64_t r, uint64_t s, uint64_t kf) {
+  return item | (r << 24) | (s << 37) | (kf << 50);
+}
+__host__ __device__ inline int task_item(uint64_t t) { return (int)(t & 0xFFFFFFull); }
+__host__ __device__ inline int task_r(uint64_t t) { return (int)((t >> 24) & 0x1FFF); }
+__host__ __device__ inline int task_s(uint64_t t) { return (int)((t >> 37) & 0x1FFF); }
+__host__ __device__ inline int task_kf(uint64_t t) { return (int)((t >> 50) & 0x1FFF); }
+
+// Kinds of factorization steps (one launch each).
+enum LaunchKind { L_NEGATE = 0, L_INPANEL = 1, L_DIAG = 2, L_PANEL = 3, L_TRAIL = 4 };
+
+struct Error {
+  mlbddc_status status = MLBDDC_OK;
+  int level = 0, subdomain = -1, column = -1;
+  std::string message;
+};
+
+}  // namespace mlbddc

@@ -1,0 +1,125 @@
+// Device kernels of the MI355X multilevel BDDC library (declarations of the
+// host-side launchers).  All launchers are asynchronous on `stream`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace mlbddc {
+
+// ---------------------------------------------------------------- assembly
+// Add element matrices into tile-packed subdomain matrices.  Elements listed
+// in `elems` (one colour: no two share a subdomain DOF) are processed; element
+// e of subdomain el_sub[e] adds entry (a, c) of its matrix at local position
+// (el_local[ptr+a], el_local[ptr+c]).  The element matrix is
+// scale[e] * Kref (Kref != null) or ekc[ekc_off[e] ...] (row-major, nloc^2).
+template <typename T>
+void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr,
+                     const int32_t* el_local, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
+                     const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A);
+
+// Set entries A[row0+i][col0+i] = val for every segment (tile-packed matrices).
+struct DiagSeg { int64_t off; int32_t nt; int32_t row0, col0, count; double val; };
+template <typename T>
+void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t max_count, T* A);
+
+// ---------------------------------------------------------- factorization
+struct FactorArgs {
+  const uint64_t* tasks;
+  const int64_t* off;      // element offset of each item's matrix
+  const int32_t* nt;       // tiles per side of each item
+  const int64_t* inv_off;  // element offset of each item's inverse diagonal tiles
+  int32_t* err;            // [0] = failing item + 1, [1] = column
+};
+template <typename T>
+void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv);
+
+// ----------------------------------------------------- preconditioner set-up
+// Copy the interface block (tile rows/cols t0.. of the FP64 K matrices) into
+// the top-left block of the preconditioner matrices, converting to TP.
+struct CopyDesc { int64_t src_off; int32_t src_nt, src_t0; int64_t dst_off; int32_t dst_nt, nblk; };
+template <typename TK, typename TP>
+void launch_copy_block(hipStream_t st, const CopyDesc* d, int32_t nitems, int32_t max_blk, const TK* K, TP* P);
+
+// Add the constraint penalty rho_c c_c^T c_c to the S block and write the C rows.
+struct ConsDesc { int64_t kdiag_off; int32_t k_nt, k_g0; int64_t p_off; int32_t p_nt, c_row0; int32_t ptr0, ptr1; };
+template <typename TK, typename TP>
+void launch_constraints(hipStream_t st, const ConsDesc* d, int64_t nrows, const int32_t* cols, const TK* K, TP* P);
+
+// Coarse matrices K_Ci = Psi_i^T S_i Psi_i (FP64 result, dense ncp x ncp per item).
+struct KcDesc {
+  int64_t k_off; int32_t k_nt, k_g0;     // S: tile block starting at k_g0 in the K matrix (FP64)
+  int64_t p_off; int32_t p_nt, p_c0, p_d0; // Psi^T: tile rows p_c0.., tile cols p_d0.. in the preconditioner matrix
+  int32_t ntg, ntc;                      // tiles of the interface and of the coarse space
+  int64_t t_off;                         // scratch for S Psi: ntg x ntc tiles
+  int64_t kc_off;                        // output: ntc x ntc tiles
+};
+template <typename TK, typename TP>
+void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32_t max_ntg, int32_t max_ntc,
+                          const TK* K, const TP* P, double* Tscr, double* KC);
+// Compact K_C tiles into row-major nc x nc blocks.
+void launch_compact_kc(hipStream_t st, const int64_t* kc_off, const int32_t* ntc, const int32_t* nc, const int64_t* out_off,
+                       int32_t nitems, int32_t max_nc, const double* KC, double* out);
+
+// ------------------------------------------------------------------ apply
+// Batched tile-block matrix-vector products  y = alpha * op(A_blk) x (+ y).
+enum MvMode { MV_SYM = 0, MV_N = 1, MV_T = 2 };
+struct MvDesc {
+  int64_t a_off; int32_t a_nt;   // tile-packed matrix
+  int32_t r0, nr, c0, nc;        // block: tile rows r0..r0+nr-1, tile cols c0..c0+nc-1
+  int64_t x_off, y_off;          // vector offsets (x has nc*64 (N, SYM) or nr*64 (T) entries)
+  int64_t p_off;                 // partial-sum scratch offset (nr*nc*64 entries)
+  const int32_t* env;            // optional first nonzero tile column per row of A (global tile index) or null
+};
+template <typename TA, typename TX, typename TY>
+void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles,
+                    const int64_t* tile_prefix, const TA* A, const TX* x, TY* y, double alpha, bool accumulate,
+                    TA* partials, int32_t max_out_tiles);
+
+// out[i] = (w ? w[i] : 1) * in[idx[i]] (0 where idx < 0), converting types.
+template <typename TI, typename TO>
+void launch_gather(hipStream_t st, int64_t n, const int32_t* idx, const double* w, const TI* in, TO* out);
+// out[g] = beta*out[g] + sum_{j in ptr[g]..ptr[g+1]} (w ? w[list[j]] : 1) * in[list[j]]  (FP64 accumulation)
+template <typename TI>
+void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
+                       double* out, double beta);
+// out[idx[i]] = in[i] for idx >= 0 (a permutation scatter)
+template <typename TI, typename TO>
+void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out);
+
+// Blocked triangular solves with the interior factor of tile-packed FP64 K
+// matrices, one workgroup per item, using the stored inverse diagonal tiles.
+struct TrsvDesc { int64_t a_off; int32_t a_nt, nti; int64_t inv_off; int64_t v_off; const int32_t* env; };
+void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
+                 double* v);
+
+// ------------------------------------------------------------------- PCG
+// Deterministic dot product: partial sums per block then a single-block finish.
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out);
+constexpr int DOT_BLOCKS = 1024;
+
+// Scalars used by the PCG kernels (device array).
+enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_NSCAL = 8 };
+void launch_pcg_alpha(hipStream_t st, double* s, double* hist, int it);        // alpha = rz / pq
+void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
+                          const double* s);                                    // x += a p, r -= a q
+void launch_pcg_beta(hipStream_t st, double* s, double* hist, int it);         // beta = rznew / rz, rz = rznew
+void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s);  // p = z + beta p
+void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
+
+// Element energies out_e = E_e a_e^T K0 b_e (level-1 mesh).
+void launch_element_energy(hipStream_t st, int64_t ne, int nloc, const int32_t* edof, const double* K0,
+                           const double* scale, const double* a, const double* b, double* out);
+void launch_fill(hipStream_t st, int64_t n, double v, double* y);
+// out[i] = A[pos[i]] with 64-bit element positions.
+template <typename T>
+void launch_gather64(hipStream_t st, int64_t n, const int64_t* pos, const T* A, double* out);
+// w[i] = d[i] / s[i] where idx[i] >= 0, else 0.
+void launch_ratio(hipStream_t st, int64_t n, const double* d, const double* s, const int32_t* idx, double* w);
+// out[idx[i]] = in[i] (every idx valid).
+void launch_scatter_idx(hipStream_t st, int64_t n, const int32_t* idx, const double* in, double* out);
+
+}  // namespace mlbddc

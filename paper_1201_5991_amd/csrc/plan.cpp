@@ -1,0 +1,398 @@
+// Host planning of the multilevel decomposition; see plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+namespace mlbddc {
+
+namespace {
+
+mlbddc_status fail(Error& err, mlbddc_status st, const std::string& msg) {
+  err.status = st;
+  err.message = msg;
+  return st;
+}
+
+// Classification of a glob from its subdomain count and node count.
+int classify(size_t n_subs, size_t n_nodes, int dim) {
+  if (n_subs >= 3 && n_nodes == 1) return G_CORNER;
+  if (n_subs == 2) return dim == 3 ? G_FACE : G_EDGE;
+  return G_EDGE;
+}
+
+// Greedy element colouring so that elements sharing a node get different colours.
+mlbddc_status colour_elements(LevelPlan& L, Error& err) {
+  const int64_t ne = (int64_t)L.el_sub.size();
+  std::vector<uint64_t> node_mask(L.n_nodes, 0);
+  L.el_color.assign(ne, 0);
+  int ncol = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    uint64_t used = 0;
+    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+      if (L.el_nodes[j] >= 0) used |= node_mask[L.el_nodes[j]];
+    if (used == ~0ull) return fail(err, MLBDDC_E_ARG, "element colouring needs more than 64 colours");
+    int c = __builtin_ctzll(~used);
+    L.el_color[e] = c;
+    ncol = std::max(ncol, c + 1);
+    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+      if (L.el_nodes[j] >= 0) node_mask[L.el_nodes[j]] |= (1ull << c);
+  }
+  L.n_colors = ncol;
+  return MLBDDC_OK;
+}
+
+// Build one level from its elements (node lists, -1 = eliminated node) and
+// the subdomain of every element.
+mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
+  const int nd = L.ndof;
+  const int64_t ne = (int64_t)L.el_sub.size();
+  const int32_t ns = L.n_sub;
+
+  // --- subdomain node sets and elements
+  std::vector<std::vector<int64_t>> sub_nodes(ns);
+  L.subs.assign(ns, SubPlan());
+  for (int64_t e = 0; e < ne; ++e) {
+    int32_t b = L.el_sub[e];
+    if (b < 0 || b >= ns) return fail(err, MLBDDC_E_ARG, "element assigned to a non-existent subdomain");
+    L.subs[b].elems.push_back(e);
+    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+      if (L.el_nodes[j] >= 0) sub_nodes[b].push_back(L.el_nodes[j]);
+  }
+  for (int32_t b = 0; b < ns; ++b) {
+    auto& v = sub_nodes[b];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    if (L.subs[b].elems.empty() || v.empty())
+      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " is empty");
+  }
+
+  // --- node -> subdomains (CSR, sorted by subdomain)
+  std::vector<int32_t> cnt(L.n_nodes + 1, 0);
+  for (int32_t b = 0; b < ns; ++b)
+    for (int64_t n : sub_nodes[b]) cnt[n + 1]++;
+  std::vector<int64_t> nptr(L.n_nodes + 1, 0);
+  for (int64_t n = 0; n < L.n_nodes; ++n) nptr[n + 1] = nptr[n] + cnt[n + 1];
+  std::vector<int32_t> nsub(nptr[L.n_nodes]);
+  {
+    std::vector<int64_t> pos(nptr.begin(), nptr.end() - 1);
+    for (int32_t b = 0; b < ns; ++b)
+      for (int64_t n : sub_nodes[b]) nsub[pos[n]++] = b;
+  }
+  auto mult = [&](int64_t n) { return nptr[n + 1] - nptr[n]; };
+
+  // --- interface nodes and globs
+  std::vector<int64_t> iface_nodes;
+  if (!L.top)
+    for (int64_t n = 0; n < L.n_nodes; ++n)
+      if (mult(n) >= 2) iface_nodes.push_back(n);
+  std::vector<int64_t> node_iface(L.n_nodes, -1);
+  for (size_t i = 0; i < iface_nodes.size(); ++i) node_iface[iface_nodes[i]] = (int64_t)i;
+  L.iface_dofs.resize(iface_nodes.size() * nd);
+  for (size_t i = 0; i < iface_nodes.size(); ++i)
+    for (int c = 0; c < nd; ++c) L.iface_dofs[i * nd + c] = iface_nodes[i] * nd + c;
+
+  L.globs.clear();
+  if (constraints & MLBDDC_ALL_PRIMAL) {
+    for (int64_t n : iface_nodes) {
+      Glob g;
+      g.nodes = {n};
+      g.subs.assign(nsub.begin() + nptr[n], nsub.begin() + nptr[n + 1]);
+      g.kind = G_CORNER;
+      L.globs.push_back(std::move(g));
+    }
+  } else {
+    std::map<std::vector<int32_t>, size_t> by_set;
+    for (int64_t n : iface_nodes) {
+      std::vector<int32_t> s(nsub.begin() + nptr[n], nsub.begin() + nptr[n + 1]);
+      auto it = by_set.find(s);
+      if (it == by_set.end()) {
+        by_set.emplace(s, L.globs.size());
+        Glob g;
+        g.subs = s;
+        g.nodes = {n};
+        L.globs.push_back(std::move(g));
+      } else {
+        L.globs[it->second].nodes.push_back(n);
+      }
+    }
+    for (auto& g : L.globs) g.kind = classify(g.subs.size(), g.nodes.size(), L.dim);
+  }
+  std::sort(L.globs.begin(), L.globs.end(), [](const Glob& a, const Glob& b) { return a.nodes[0] < b.nodes[0]; });
+  L.counts[0] = L.counts[1] = L.counts[2] = 0;
+  L.n_coarse_nodes = 0;
+  for (auto& g : L.globs) {
+    L.counts[g.kind]++;
+    bool on = (constraints & MLBDDC_ALL_PRIMAL) || (g.kind == G_CORNER && (constraints & MLBDDC_CORNERS)) ||
+              (g.kind == G_EDGE && (constraints & MLBDDC_EDGES)) || (g.kind == G_FACE && (constraints & MLBDDC_FACES));
+    g.constrained = on;
+    g.coarse_node = on ? L.n_coarse_nodes++ : -1;
+  }
+  L.n_coarse = L.n_coarse_nodes * nd;
+  if (!L.top) {
+    if (iface_nodes.empty()) return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + " has no interface");
+    if (L.n_coarse == 0) return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + " has no coarse DOFs");
+  }
+
+  // subdomain -> constrained globs (in glob order)
+  std::vector<std::vector<int32_t>> sub_globs(ns);
+  for (size_t gi = 0; gi < L.globs.size(); ++gi)
+    if (L.globs[gi].constrained)
+      for (int32_t b : L.globs[gi].subs) sub_globs[b].push_back((int32_t)gi);
+
+  // --- local orderings, element maps, envelopes, constraints
+  std::vector<int64_t> node_local(L.n_nodes, -1);  // node -> local node slot (interior or interface)
+  std::vector<char> node_is_g(L.n_nodes, 0);
+  L.el_local_ptr.assign(ne + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) L.el_local_ptr[e + 1] = L.el_local_ptr[e] + (int32_t)((L.el_ptr[e + 1] - L.el_ptr[e]) * nd);
+  L.el_local.assign(L.el_local_ptr[ne], -1);
+
+  for (int32_t b = 0; b < ns; ++b) {
+    SubPlan& S = L.subs[b];
+    std::vector<int64_t> inodes, gnodes;
+    for (int64_t n : sub_nodes[b]) (mult(n) >= 2 && !L.top ? gnodes : inodes).push_back(n);
+    S.nI = (int64_t)inodes.size() * nd;
+    S.nG = (int64_t)gnodes.size() * nd;
+    S.nIp = round_up(S.nI, TS);
+    S.nGp = round_up(S.nG, TS);
+    for (size_t i = 0; i < inodes.size(); ++i) node_local[inodes[i]] = (int64_t)i;
+
+    // interface nodes sorted by the first interior node they couple to, so that
+    // the tile envelope of the interface rows is tight
+    std::vector<int64_t> key(gnodes.size(), INT64_MAX);
+    for (size_t i = 0; i < gnodes.size(); ++i) { node_local[gnodes[i]] = (int64_t)i; node_is_g[gnodes[i]] = 1; }
+    for (int64_t e : S.elems) {
+      int64_t mn = INT64_MAX;
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+        int64_t n = L.el_nodes[j];
+        if (n >= 0 && !node_is_g[n]) mn = std::min(mn, node_local[n]);
+      }
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+        int64_t n = L.el_nodes[j];
+        if (n >= 0 && node_is_g[n]) key[node_local[n]] = std::min(key[node_local[n]], mn);
+      }
+    }
+    std::vector<size_t> order(gnodes.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
+      return key[a] != key[c] ? key[a] < key[c] : gnodes[a] < gnodes[c];
+    });
+    std::vector<int64_t> gsorted(gnodes.size());
+    for (size_t i = 0; i < order.size(); ++i) gsorted[i] = gnodes[order[i]];
+    gnodes.swap(gsorted);
+    for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int64_t)i;
+
+    S.dofI.resize(S.nI);
+    for (size_t i = 0; i < inodes.size(); ++i)
+      for (int c = 0; c < nd; ++c) S.dofI[i * nd + c] = inodes[i] * nd + c;
+    S.dofG.resize(S.nG);
+    S.iface.resize(S.nG);
+    for (size_t i = 0; i < gnodes.size(); ++i)
+      for (int c = 0; c < nd; ++c) {
+        S.dofG[i * nd + c] = gnodes[i] * nd + c;
+        S.iface[i * nd + c] = (int32_t)(node_iface[gnodes[i]] * nd + c);
+      }
+
+    // local K index of a level DOF of this subdomain
+    auto kidx = [&](int64_t n, int c) -> int64_t {
+      return node_is_g[n] ? S.nIp + node_local[n] * nd + c : node_local[n] * nd + c;
+    };
+    const int64_t nK = S.nIp + S.nGp + (L.augmentK ? S.nIp : 0);
+    const int64_t ntK = nK / TS;
+    std::vector<int64_t> first(nK);
+    for (int64_t p = 0; p < nK; ++p) first[p] = p;
+    if (L.augmentK)
+      for (int64_t p = S.nIp + S.nGp; p < nK; ++p) first[p] = p - (S.nIp + S.nGp);
+    for (int64_t e : S.elems) {
+      int64_t mn = INT64_MAX;
+      int32_t base = L.el_local_ptr[e];
+      int k = 0;
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+        int64_t n = L.el_nodes[j];
+        for (int c = 0; c < nd; ++c, ++k) {
+          if (n < 0) { L.el_local[base + k] = -1; continue; }
+          int64_t p = kidx(n, c);
+          L.el_local[base + k] = (int32_t)p;
+          mn = std::min(mn, p);
+        }
+      }
+      k = 0;
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+        for (int c = 0; c < nd; ++c, ++k) {
+          int32_t p = L.el_local[base + k];
+          if (p >= 0) first[p] = std::min(first[p], mn);
+        }
+    }
+    S.envK.assign(ntK, 0);
+    for (int64_t r = 0; r < ntK; ++r) {
+      int64_t m = INT64_MAX;
+      for (int64_t p = r * TS; p < (r + 1) * TS; ++p) m = std::min(m, first[p]);
+      S.envK[r] = (int32_t)(m / TS);
+    }
+
+    // constraint rows and R_Ci
+    S.crow_ptr.assign(1, 0);
+    S.crow_col.clear();
+    S.coarse.clear();
+    for (int32_t gi : sub_globs[b]) {
+      const Glob& g = L.globs[gi];
+      for (int c = 0; c < nd; ++c) {
+        for (int64_t n : g.nodes) S.crow_col.push_back((int32_t)(node_local[n] * nd + c));
+        S.crow_ptr.push_back((int32_t)S.crow_col.size());
+        S.coarse.push_back((int32_t)(g.coarse_node * nd + c));
+      }
+    }
+    S.nc = (int32_t)S.coarse.size();
+    S.ncp = (int32_t)round_up(S.nc, TS);
+    if (!L.top && S.nc == 0)
+      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " has no constraints");
+
+    for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_is_g[n] = 0; }
+  }
+  return colour_elements(L, err);
+}
+
+}  // namespace
+
+mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
+  if (in.dim != 2 && in.dim != 3) return fail(err, MLBDDC_E_ARG, "dim must be 2 or 3");
+  if (in.ndof < 1 || in.ndof > 3) return fail(err, MLBDDC_E_ARG, "ndof_per_node must be 1..3");
+  if (in.n_levels < 2) return fail(err, MLBDDC_E_ARG, "n_levels must be >= 2");
+  if (in.n_elems <= 0 || in.n_nodes <= 0 || !in.elem_nodes || !in.elem_to_sub)
+    return fail(err, MLBDDC_E_ARG, "empty mesh or missing arrays");
+  if (in.n_levels > 2 && !in.sub_to_parent) return fail(err, MLBDDC_E_ARG, "sub_to_parent missing");
+
+  plan.levels.clear();
+  plan.node_to_free.assign(in.n_nodes, -1);
+  int64_t nf = 0;
+  for (int64_t n = 0; n < in.n_nodes; ++n)
+    if (!in.dirichlet || !in.dirichlet[n]) plan.node_to_free[n] = nf++;
+  plan.n_free_nodes = nf;
+
+  // ---- level 1 from the mesh
+  LevelPlan L1;
+  L1.level = 1;
+  L1.dim = in.dim;
+  L1.ndof = in.ndof;
+  L1.n_nodes = nf;
+  L1.n_dofs = nf * in.ndof;
+  int32_t nsub = 0;
+  L1.el_ptr.resize(in.n_elems + 1);
+  L1.el_nodes.resize(in.n_elems * in.nodes_per_elem);
+  L1.el_sub.resize(in.n_elems);
+  for (int64_t e = 0; e < in.n_elems; ++e) {
+    L1.el_ptr[e] = e * in.nodes_per_elem;
+    for (int a = 0; a < in.nodes_per_elem; ++a) {
+      int32_t n = in.elem_nodes[e * in.nodes_per_elem + a];
+      if (n < 0 || n >= in.n_nodes) return fail(err, MLBDDC_E_ARG, "element node out of range");
+      L1.el_nodes[e * in.nodes_per_elem + a] = plan.node_to_free[n];
+    }
+    int32_t s = in.elem_to_sub[e];
+    if (s < 0) return fail(err, MLBDDC_E_ARG, "element without a subdomain");
+    L1.el_sub[e] = s;
+    nsub = std::max(nsub, s + 1);
+  }
+  L1.el_ptr[in.n_elems] = in.n_elems * in.nodes_per_elem;
+  L1.n_sub = nsub;
+  mlbddc_status st = build_level(L1, in.constraints, err);
+  if (st != MLBDDC_OK) return st;
+  plan.levels.push_back(std::move(L1));
+
+  // ---- levels 2..L-1 and the top level from the pseudo-mesh
+  for (int l = 2; l <= in.n_levels; ++l) {
+    const LevelPlan& P = plan.levels.back();
+    LevelPlan L;
+    L.level = l;
+    L.dim = in.dim;
+    L.ndof = in.ndof;
+    L.n_nodes = P.n_coarse_nodes;
+    L.n_dofs = P.n_coarse;
+    L.augmentK = true;
+    L.top = (l == in.n_levels);
+    L.el_ptr.assign(P.n_sub + 1, 0);
+    L.el_sub.resize(P.n_sub);
+    // pseudo-elements: the previous level's subdomains, nodes = their constrained globs
+    std::vector<std::vector<int64_t>> gl(P.n_sub);
+    for (const Glob& g : P.globs)
+      if (g.constrained)
+        for (int32_t b : g.subs) gl[b].push_back(g.coarse_node);
+    int32_t ns = 1;
+    for (int32_t b = 0; b < P.n_sub; ++b) {
+      L.el_ptr[b + 1] = L.el_ptr[b] + (int64_t)gl[b].size();
+      L.el_nodes.insert(L.el_nodes.end(), gl[b].begin(), gl[b].end());
+      if (L.top) {
+        L.el_sub[b] = 0;
+      } else {
+        int32_t p = in.sub_to_parent[l - 2] ? in.sub_to_parent[l - 2][b] : -1;
+        if (p < 0) return fail(err, MLBDDC_E_ARG, "level " + std::to_string(l) + ": subdomain without a parent");
+        L.el_sub[b] = p;
+        ns = std::max(ns, p + 1);
+      }
+    }
+    L.n_sub = ns;
+    st = build_level(L, L.top ? 0 : (in.constraints & ~MLBDDC_ALL_PRIMAL), err);
+    if (st != MLBDDC_OK) return st;
+    plan.levels.push_back(std::move(L));
+  }
+  return MLBDDC_OK;
+}
+
+void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out) {
+  out.tasks.clear();
+  out.launches.clear();
+  out.flops = 0.0;
+  out.update_tasks = 0;
+  const double t3 = (double)TS * TS * TS;
+  if (panel < 1) panel = 1;
+  int maxk = 0;
+  for (auto& it : items) maxk = std::max(maxk, it.e1 + it.e2);
+  std::vector<uint64_t> lists[5];
+  for (int k = 0; k < maxk; ++k) {
+    for (auto& l : lists) l.clear();
+    for (size_t b = 0; b < items.size(); ++b) {
+      const FactorItemDesc& it = items[b];
+      const int e1 = it.e1, e2 = it.e2, nt = it.nt;
+      if (k >= e1 + e2) continue;
+      const int32_t* env = it.env;
+      int ph0 = k < e1 ? 0 : e1, ph1 = k < e1 ? e1 : e1 + e2;
+      int k0 = ph0 + ((k - ph0) / panel) * panel;
+      int kend = std::min(k0 + panel, ph1);
+      if (k == e1 && e2 > 0)
+        for (int s = e1; s < nt; ++s)
+          for (int r = s; r < nt; ++r) lists[L_NEGATE].push_back(pack_task(b, r, s, 0));
+      if (k > k0)
+        for (int r = k; r < nt; ++r)
+          if (std::max(env[r], env[k]) <= k - 1) {
+            lists[L_INPANEL].push_back(pack_task(b, r, k, k0));
+            out.flops += 2.0 * t3 * (k - k0);
+          }
+      lists[L_DIAG].push_back(pack_task(b, k, k, 0));
+      out.flops += t3 / 3.0;
+      for (int r = k + 1; r < nt; ++r)
+        if (env[r] <= k) {
+          lists[L_PANEL].push_back(pack_task(b, r, k, 0));
+          out.flops += t3;
+        }
+      if (k == kend - 1)
+        for (int s = k + 1; s < nt; ++s) {
+          if (env[s] > k) continue;
+          for (int r = s; r < nt; ++r)
+            if (env[r] <= k) {
+              lists[L_TRAIL].push_back(pack_task(b, r, s, k0));
+              out.flops += (r == s ? 1.0 : 2.0) * t3 * (k - k0 + 1);
+            }
+        }
+    }
+    for (int kind = 0; kind < 5; ++kind) {
+      if (lists[kind].empty()) continue;
+      FactorLaunch L{kind, k, (int64_t)out.tasks.size(), (int64_t)lists[kind].size()};
+      if (kind == L_TRAIL || kind == L_INPANEL) out.update_tasks += L.count;
+      out.tasks.insert(out.tasks.end(), lists[kind].begin(), lists[kind].end());
+      out.launches.push_back(L);
+    }
+  }
+}
+
+}  // namespace mlbddc

@@ -1,0 +1,121 @@
+// Host planning of the multilevel decomposition (set-up, Algorithm 1: the
+// integer part).  Builds, level by level, the subdomain node sets, the
+// interface, its classification into faces / edges / vertices ("globs"),
+// the corners, the constraint rows of C_i, the local DOF orderings and tile
+// layouts, the element colouring used by assembly, and the pseudo-mesh of
+// the next level (subdomains become elements, constrained globs become nodes).
+//
+// Readings of the paper's unspecified steps (shared with the written
+// description of the method, not with any other code):
+//  * a glob is a class of interface nodes with the same set of subdomains;
+//    a glob of three or more subdomains made of one node is a corner; in 3D
+//    a glob of two subdomains is a face, one of three or more with several
+//    nodes an edge; in 2D a glob of two subdomains is an edge;
+//  * Dirichlet nodes are removed before the interface is formed;
+//  * constraints: one row per glob and component, the value at a corner or
+//    the arithmetic mean (weights 1/m) over an edge or face;
+//  * globs are ordered by their smallest node; coarse DOFs glob by glob,
+//    component innermost.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace mlbddc {
+
+enum GlobKind { G_CORNER = 0, G_EDGE = 1, G_FACE = 2 };
+
+struct Glob {
+  std::vector<int64_t> nodes;  // level nodes, sorted
+  std::vector<int32_t> subs;   // sorted subdomains sharing it
+  int kind = G_EDGE;
+  bool constrained = false;
+  int64_t coarse_node = -1;
+};
+
+// One subdomain of one level.
+struct SubPlan {
+  int64_t nI = 0, nG = 0;      // interior / interface DOFs
+  int64_t nIp = 0, nGp = 0;    // padded to the tile edge
+  std::vector<int64_t> dofI;   // level DOFs of the interior, local order
+  std::vector<int64_t> dofG;   // level DOFs of the interface, local order
+  std::vector<int32_t> iface;  // R_i: local interface position -> level interface index
+  std::vector<int32_t> coarse; // R_Ci: local coarse DOF -> level coarse DOF
+  int32_t nc = 0, ncp = 0;     // constraints and padded count
+  // constraint rows: row c averages local interface positions crow_col[crow_ptr[c]..crow_ptr[c+1])
+  std::vector<int32_t> crow_ptr, crow_col;
+  // elements of the subdomain (ids in the level's element numbering)
+  std::vector<int64_t> elems;
+  // tile envelope (first nonzero tile column per tile row) of the local K matrix
+  std::vector<int32_t> envK;
+};
+
+struct LevelPlan {
+  int level = 1;               // 1-based
+  int dim = 3, ndof = 3;
+  int64_t n_nodes = 0, n_dofs = 0;
+  int32_t n_sub = 0;
+  bool augmentK = false;       // K matrix carries an identity block (levels >= 2)
+  bool top = false;            // single subdomain without interface: the coarse problem
+  // elements of this level: node lists (-1 = eliminated node) in CSR form
+  std::vector<int64_t> el_ptr, el_nodes;
+  std::vector<int32_t> el_sub;
+  // per element and element DOF: position in the padded local K ordering (-1 = none)
+  std::vector<int32_t> el_local_ptr;    // start of an element's DOF map in el_local
+  std::vector<int32_t> el_local;
+  std::vector<int32_t> el_color;
+  int32_t n_colors = 0;
+  std::vector<SubPlan> subs;
+  std::vector<int64_t> iface_dofs;      // level interface DOFs, increasing
+  std::vector<Glob> globs;
+  int64_t n_coarse_nodes = 0, n_coarse = 0;
+  int32_t counts[3] = {0, 0, 0};        // corners, edges, faces
+};
+
+struct PlanInput {
+  int dim = 3, ndof = 3;
+  int64_t n_nodes = 0, n_elems = 0;
+  int nodes_per_elem = 8;
+  const int32_t* elem_nodes = nullptr;
+  const uint8_t* dirichlet = nullptr;
+  int n_levels = 2;
+  const int32_t* elem_to_sub = nullptr;
+  const int32_t* const* sub_to_parent = nullptr;
+  int constraints = MLBDDC_CORNERS | MLBDDC_EDGES | MLBDDC_FACES;
+};
+
+struct Plan {
+  std::vector<LevelPlan> levels;        // BDDC levels 1..L-1, then the top (coarse) level
+  std::vector<int64_t> node_to_free;    // mesh node -> free node (-1 for Dirichlet)
+  int64_t n_free_nodes = 0;
+};
+
+// Build the whole plan.  Returns MLBDDC_OK or an error with a message.
+mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err);
+
+// Factorization schedule of a batch of tile-packed matrices, each eliminated
+// in one or two phases (the trailing block is negated between the phases).
+struct FactorItemDesc {
+  int32_t nt = 0;                       // tiles per side
+  int32_t e1 = 0, e2 = 0;               // tile columns eliminated per phase
+  const int32_t* env = nullptr;         // first nonzero tile column per tile row (size nt)
+};
+
+struct FactorLaunch {
+  int kind;
+  int k;                                // global tile column of this step
+  int64_t first, count;                 // task range
+};
+
+struct FactorSchedule {
+  std::vector<uint64_t> tasks;
+  std::vector<FactorLaunch> launches;
+  double flops = 0.0;                   // dense flops of the tasks (for rooflines)
+  int64_t update_tasks = 0;
+};
+
+void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out);
+
+}  // namespace mlbddc

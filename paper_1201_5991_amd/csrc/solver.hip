@@ -1,0 +1,1360 @@
+// Orchestration of the multilevel BDDC-PCG on one gfx950 device and the C ABI.
+//
+// Set-up (Algorithm 1), per level l = 1..L-1 and the top coarse level:
+//   K job  : assemble the subdomain matrices K_i (tile-packed), partially
+//            factorize them (interior block eliminated).  Level 1 keeps the
+//            interface Schur complement S_i = K_GG - K_GI K_II^{-1} K_IG in the
+//            trailing tiles.  Levels >= 2 and the top level carry an identity
+//            block, so the trailing tiles also hold -K_II^{-1} K_IG and
+//            -K_II^{-1} (the interior pre-/post-correction operators; at the
+//            top level simply -K_C^{-1}).
+//   M job  : for every subdomain the augmented matrix
+//              [ S+C^T W C   C^T   I    0  ]
+//              [ C           0     0    I  ]
+//              [ I           0     0    0  ]
+//              [ 0           I     0    0  ]
+//            is eliminated in two phases (the trailing block is negated in
+//            between).  The result holds G_i = S~^{-1} - S~^{-1}C^T A^{-1} C S~^{-1}
+//            (A = C S~^{-1} C^T), the operator of the constrained local problem
+//            of Eq. (2) restricted to the interface, and Psi_i^T, the coarse basis
+//            of Eq. (1); the penalty W (rho = sum of the glob's diagonal entries
+//            of S) makes S~ definite on floating subdomains and does not change
+//            the solution.
+//   K_Ci = Psi_i^T S_i Psi_i (= -Lambda_i), assembled as the elements of the next level.
+// Apply (Algorithm 2), level l interface vector r^:
+//   r_i = D_i R_i r^;  r_C = sum R_Ci^T Psi_i^T r_i;  z_C from the next level
+//   (interior pre-correction, BDDC, post-correction) or the top solve;
+//   z^ = sum R_i^T D_i (G_i r_i + Psi_i R_Ci z_C).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace mlbddc {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+#define HIPCHK(x)                                                                                  \
+  do {                                                                                             \
+    hipError_t e_ = (x);                                                                           \
+    if (e_ != hipSuccess) return herr(#x, e_);                                                     \
+  } while (0)
+
+// A batch of tile-packed matrices factorized together.
+struct Job {
+  bool fp32 = false;
+  void* buf = nullptr;
+  void* inv = nullptr;
+  int64_t elems = 0, inv_elems = 0;
+  std::vector<int64_t> off, inv_off;
+  std::vector<int32_t> nt;
+  std::vector<FactorItemDesc> items;
+  std::vector<std::vector<int32_t>> env;
+  FactorSchedule sched;
+  int64_t* d_off = nullptr;
+  int64_t* d_inv_off = nullptr;
+  int32_t* d_nt = nullptr;
+  uint64_t* d_tasks = nullptr;
+  int32_t* d_err = nullptr;
+};
+
+// A batched tile-block matrix-vector product.
+struct MvSet {
+  int mode = MV_SYM;
+  std::vector<MvDesc> h;
+  MvDesc* d = nullptr;
+  int64_t* d_prefix = nullptr;
+  int64_t tiles = 0;
+  int32_t max_out = 0;
+  int64_t partial_elems = 0;
+};
+
+struct LevelDev {
+  LevelPlan* P = nullptr;
+  bool kfp32 = false, mfp32 = false;
+  Job K, M;
+  // flat local layouts
+  int64_t nG_flat = 0, nI_flat = 0, nC_flat = 0;
+  std::vector<int64_t> gofs, iofs, cofs;
+  int32_t* d_gidx = nullptr;      // flat interface position -> level interface index (-1 pad)
+  int32_t* d_iidx = nullptr;      // flat interior position -> level DOF (-1 pad)
+  int32_t* d_cidx = nullptr;      // flat coarse position -> level coarse DOF (-1 pad)
+  int32_t* d_iface_dofs = nullptr;// level interface index -> level DOF
+  int64_t* d_gptr = nullptr;  int64_t* d_glist = nullptr;   // interface DOF -> flat positions
+  int64_t* d_cptr = nullptr;  int64_t* d_clist = nullptr;   // coarse DOF -> flat positions
+  double* d_w = nullptr;          // weights D_i (flat interface)
+  int64_t* d_gdiag_pos = nullptr; // element offsets of the interface diagonal of K (for weights)
+  // work vectors
+  void* rl = nullptr;   // flat interface, M precision
+  void* yl = nullptr;   // flat interface, M precision
+  void* zcl = nullptr;  // flat coarse, M precision
+  double* rcl = nullptr;// flat coarse, FP64
+  double* rC = nullptr; // level coarse vector (next level's DOFs)
+  double* zC = nullptr;
+  double* rhat = nullptr; // level interface vector (levels >= 2)
+  double* zhat = nullptr;
+  void* rI = nullptr;   // flat interior, K precision
+  void* uI = nullptr;
+  void* zG = nullptr;   // flat interface, K precision (post-correction input)
+  double* tG = nullptr; // flat interface FP64
+  double* gd = nullptr; // flat interface FP64 work (weights, S^ product)
+  double* gd2 = nullptr;
+  double* wI = nullptr; // flat interior FP64 (level 1 condensation)
+  void* partial = nullptr;
+  // tile mat-vec sets
+  MvSet mvS, mvG, mvPsiN, mvPsiT, mvPre, mvPreT, mvPostN, mvLgi, mvLgiT;
+  std::vector<TrsvDesc> trsv_h;
+  TrsvDesc* d_trsv = nullptr;
+  // coarse matrices of this level (inputs of the next level's assembly)
+  double* kc_compact = nullptr;
+  std::vector<int64_t> kc_off;
+  int64_t* d_kc_off = nullptr;
+  double* KCt = nullptr; double* Tscr = nullptr;
+  std::vector<KcDesc> kcd_h;
+  KcDesc* d_kcd = nullptr;
+  int32_t kc_max_ntg = 0, kc_max_ntc = 0, max_nc = 0;
+  std::vector<int64_t> kct_off_h;
+  int64_t* d_kct_off = nullptr;
+  int32_t* d_ntc = nullptr;
+  int32_t* d_nc = nullptr;
+  std::vector<CopyDesc> copy_h;
+  CopyDesc* d_copy = nullptr;
+  int32_t copy_max = 0;
+  std::vector<ConsDesc> cons_h;
+  ConsDesc* d_cons = nullptr;
+  int32_t* d_ccols = nullptr;
+  std::vector<DiagSeg> ksegs_h, msegs_h;
+  DiagSeg* d_ksegs = nullptr;
+  DiagSeg* d_msegs = nullptr;
+  int32_t kseg_max = 0, mseg_max = 0;
+  // assembly
+  int64_t* d_sub_off = nullptr;
+  int32_t* d_sub_nt = nullptr;
+  int64_t* d_elems_by_color = nullptr;
+  std::vector<int64_t> color_ptr;
+  int32_t* d_el_local_ptr = nullptr;
+  int32_t* d_el_local = nullptr;
+  int32_t* d_el_sub = nullptr;
+  int64_t* d_ekc_off = nullptr;   // element -> offset of its matrix in the previous level's kc_compact
+};
+
+}  // namespace
+
+struct Handle {
+  mlbddc_options opt{};
+  hipStream_t stream = nullptr;
+  Error err;
+  Plan plan;
+  bool planned = false, ready = false;
+  std::vector<void*> allocs;
+  std::vector<LevelDev> lev;
+  // mesh data kept for updates and element energies
+  int32_t nloc1 = 0;
+  int64_t n_elems = 0;
+  double* d_Kref = nullptr;
+  double* d_scale = nullptr;
+  int32_t* d_edof = nullptr;       // element DOF -> free DOF (-1 fixed)
+  // PCG state
+  double *d_x = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_g = nullptr;
+  double* d_s = nullptr;           // scalars
+  double* d_hist = nullptr;        // alpha/beta history
+  double* d_dotp = nullptr;
+  double* h_s = nullptr;           // pinned mirror of the scalars
+  int32_t max_hist = 0;
+  double t_plan = 0, t_setup = 0;
+  double flops_K = 0, flops_M = 0;
+
+  mlbddc_status herr(const char* what, hipError_t e) {
+    err.status = MLBDDC_E_HIP;
+    err.message = std::string(what) + ": " + hipGetErrorString(e);
+    return err.status;
+  }
+  mlbddc_status fail(mlbddc_status st, const std::string& m, int level = 0, int sub = -1, int col = -1) {
+    err.status = st;
+    err.message = m;
+    err.level = level;
+    err.subdomain = sub;
+    err.column = col;
+    return st;
+  }
+  template <typename T>
+  mlbddc_status dalloc(T** p, int64_t n) {
+    *p = nullptr;
+    if (n <= 0) return MLBDDC_OK;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MLBDDC_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * n) + " bytes failed");
+    }
+    allocs.push_back(q);
+    *p = (T*)q;
+    return MLBDDC_OK;
+  }
+  template <typename T>
+  mlbddc_status upload(T** p, const std::vector<T>& v) {
+    mlbddc_status st = dalloc(p, (int64_t)v.size());
+    if (st) return st;
+    if (!v.empty()) {
+      // synchronous: the host vector may be a temporary
+      HIPCHK(hipMemcpyAsync(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+    }
+    return MLBDDC_OK;
+  }
+  void free_all() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    if (h_s) (void)hipHostFree(h_s);
+    h_s = nullptr;
+    lev.clear();
+    ready = false;
+  }
+  mlbddc_status sync() {
+    HIPCHK(hipStreamSynchronize(stream));
+    return MLBDDC_OK;
+  }
+
+  mlbddc_status setup(const mlbddc_mesh* mesh, const mlbddc_partition* part);
+  mlbddc_status validate();
+  mlbddc_status numeric();
+  mlbddc_status prepare_job(Job& J, bool fp32);
+  mlbddc_status factor(Job& J, int level, bool precond);
+  mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
+  template <typename TA, typename TX, typename TY>
+  void run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial);
+  mlbddc_status apply_interface(int li, const double* rhat, double* zhat);
+  mlbddc_status apply_full(int li, const double* r, double* z);
+  mlbddc_status schur(const double* x, double* y);
+  mlbddc_status condense(const double* f, double* g);
+  mlbddc_status recover(const double* uhat, double* u);
+  mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
+};
+
+// ----------------------------------------------------------------- helpers
+mlbddc_status Handle::build_mv(MvSet& s, int mode, std::vector<MvDesc> descs) {
+  s.mode = mode;
+  s.h = std::move(descs);
+  std::vector<int64_t> prefix(s.h.size() + 1, 0);
+  int64_t poff = 0;
+  s.max_out = 0;
+  for (size_t i = 0; i < s.h.size(); ++i) {
+    MvDesc& d = s.h[i];
+    int64_t tiles = mode == MV_SYM ? (int64_t)d.nr * (d.nr + 1) / 2 : (int64_t)d.nr * d.nc;
+    prefix[i + 1] = prefix[i] + tiles;
+    d.p_off = poff;
+    poff += (int64_t)d.nr * d.nc * TS;
+    s.max_out = std::max(s.max_out, mode == MV_T ? d.nc : d.nr);
+  }
+  s.tiles = prefix.back();
+  s.partial_elems = poff;
+  mlbddc_status st = upload(&s.d, s.h);
+  if (st) return st;
+  return upload(&s.d_prefix, prefix);
+}
+
+template <typename TA, typename TX, typename TY>
+void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial) {
+  launch_tile_mv<TA, TX, TY>(stream, s.mode, s.d, (int32_t)s.h.size(), s.tiles, s.d_prefix, (const TA*)J.buf, x, y, alpha,
+                             acc, (TA*)partial, s.max_out);
+}
+
+mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
+  J.fp32 = fp32;
+  const size_t esz = fp32 ? 4 : 8;
+  J.off.resize(J.nt.size());
+  J.inv_off.resize(J.nt.size());
+  int64_t tot = 0, itot = 0;
+  for (size_t i = 0; i < J.nt.size(); ++i) {
+    J.off[i] = tot;
+    tot += packed_tiles(J.nt[i]) * TE;
+    J.inv_off[i] = itot;
+    itot += (int64_t)(J.items[i].e1 + J.items[i].e2) * TE;
+    J.items[i].env = J.env[i].data();
+  }
+  J.elems = tot;
+  J.inv_elems = itot;
+  void* b = nullptr;
+  void* iv = nullptr;
+  mlbddc_status st = fp32 ? dalloc((float**)&b, tot) : dalloc((double**)&b, tot);
+  if (st) return st;
+  st = fp32 ? dalloc((float**)&iv, std::max<int64_t>(itot, 1)) : dalloc((double**)&iv, std::max<int64_t>(itot, 1));
+  if (st) return st;
+  J.buf = b;
+  J.inv = iv;
+  (void)esz;
+  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 1, J.sched);
+  if ((st = upload(&J.d_off, J.off))) return st;
+  if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
+  if ((st = upload(&J.d_nt, J.nt))) return st;
+  if ((st = upload(&J.d_tasks, J.sched.tasks))) return st;
+  if ((st = dalloc(&J.d_err, 2))) return st;
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::factor(Job& J, int level, bool precond) {
+  HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
+  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err};
+  for (const FactorLaunch& L : J.sched.launches) {
+    if (J.fp32)
+      launch_factor_step<float>(stream, L.kind, L.k, a, L.first, L.count, (float*)J.buf, (float*)J.inv);
+    else
+      launch_factor_step<double>(stream, L.kind, L.k, a, L.first, L.count, (double*)J.buf, (double*)J.inv);
+  }
+  HIPCHK(hipGetLastError());
+  int32_t e[2];
+  HIPCHK(hipMemcpyAsync(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (e[0] != 0) {
+    int sub = e[0] - 1;
+    if (precond)
+      return fail(MLBDDC_E_SINGULAR_CONSTRAINTS, "constrained local problem is singular", level, sub, e[1]);
+    return fail(MLBDDC_E_NOT_SPD, "non-positive pivot in a subdomain factorization", level, sub, e[1]);
+  }
+  return MLBDDC_OK;
+}
+
+// --------------------------------------------------------------------- setup
+mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* part) {
+  if (!mesh || !part) return fail(MLBDDC_E_ARG, "null mesh or partition");
+  if (!mesh->elem_matrix_ref || !mesh->elem_scale) return fail(MLBDDC_E_ARG, "missing element matrix or scales");
+  free_all();
+  double t0 = now();
+  PlanInput in;
+  in.dim = mesh->dim;
+  in.ndof = mesh->ndof_per_node;
+  in.n_nodes = mesh->n_nodes;
+  in.n_elems = mesh->n_elems;
+  in.nodes_per_elem = mesh->nodes_per_elem;
+  in.elem_nodes = mesh->elem_nodes;
+  in.dirichlet = mesh->dirichlet_nodes;
+  in.n_levels = part->n_levels;
+  in.elem_to_sub = part->elem_to_sub;
+  in.sub_to_parent = part->sub_to_parent;
+  in.constraints = part->constraints;
+  if (in.nodes_per_elem != (1 << in.dim)) return fail(MLBDDC_E_ARG, "nodes_per_elem must be 2^dim");
+  Error e;
+  mlbddc_status st = build_plan(in, plan, e);
+  if (st) {
+    err = e;
+    return st;
+  }
+  planned = true;
+  const int nd = in.ndof;
+  nloc1 = in.nodes_per_elem * nd;
+  n_elems = in.n_elems;
+  const int nlev = (int)plan.levels.size();
+  lev.assign(nlev, LevelDev());
+  const bool mixed = opt.precision == MLBDDC_MIXED;
+
+  // ---- mesh data on the device
+  {
+    std::vector<double> kref(mesh->elem_matrix_ref, mesh->elem_matrix_ref + (size_t)nloc1 * nloc1);
+    if ((st = upload(&d_Kref, kref))) return st;
+    std::vector<double> sc(mesh->elem_scale, mesh->elem_scale + n_elems);
+    if ((st = upload(&d_scale, sc))) return st;
+    std::vector<int32_t> edof((size_t)n_elems * nloc1);
+    for (int64_t el = 0; el < n_elems; ++el)
+      for (int a = 0; a < in.nodes_per_elem; ++a) {
+        int64_t fnode = plan.node_to_free[mesh->elem_nodes[el * in.nodes_per_elem + a]];
+        for (int c = 0; c < nd; ++c) edof[el * nloc1 + a * nd + c] = fnode < 0 ? -1 : (int32_t)(fnode * nd + c);
+      }
+    if ((st = upload(&d_edof, edof))) return st;
+  }
+
+  for (int li = 0; li < nlev; ++li) {
+    LevelDev& D = lev[li];
+    LevelPlan& P = plan.levels[li];
+    D.P = &P;
+    D.kfp32 = mixed && li > 0 && !P.top;
+    D.mfp32 = mixed;
+    const int ns = P.n_sub;
+    // ---- K job
+    D.K.nt.resize(ns);
+    D.K.items.resize(ns);
+    D.K.env.resize(ns);
+    for (int b = 0; b < ns; ++b) {
+      const SubPlan& S = P.subs[b];
+      int64_t nK = S.nIp + S.nGp + (P.augmentK ? S.nIp : 0);
+      D.K.nt[b] = (int32_t)(nK / TS);
+      D.K.items[b].nt = D.K.nt[b];
+      D.K.items[b].e1 = (int32_t)(S.nIp / TS);
+      D.K.items[b].e2 = 0;
+      D.K.env[b] = S.envK;
+    }
+    if ((st = prepare_job(D.K, D.kfp32))) return st;
+    flops_K += D.K.sched.flops;
+
+    // diagonal segments of the K matrices: padding and identity block
+    for (int b = 0; b < ns; ++b) {
+      const SubPlan& S = P.subs[b];
+      int32_t nt = D.K.nt[b];
+      auto add = [&](int64_t r0, int64_t c0, int64_t cnt, double v) {
+        if (cnt > 0) D.ksegs_h.push_back(DiagSeg{D.K.off[b], nt, (int32_t)r0, (int32_t)c0, (int32_t)cnt, v});
+      };
+      add(S.nI, S.nI, S.nIp - S.nI, 1.0);
+      add(S.nIp + S.nG, S.nIp + S.nG, S.nGp - S.nG, 1.0);
+      if (P.augmentK) add(S.nIp + S.nGp, 0, S.nIp, 1.0);
+    }
+    for (auto& s : D.ksegs_h) D.kseg_max = std::max(D.kseg_max, s.count);
+    if ((st = upload(&D.d_ksegs, D.ksegs_h))) return st;
+
+    // assembly data
+    {
+      std::vector<int64_t> byc;
+      D.color_ptr.assign(P.n_colors + 1, 0);
+      for (int c = 0; c < P.n_colors; ++c) {
+        for (size_t el = 0; el < P.el_color.size(); ++el)
+          if (P.el_color[el] == c) byc.push_back((int64_t)el);
+        D.color_ptr[c + 1] = (int64_t)byc.size();
+      }
+      if ((st = upload(&D.d_elems_by_color, byc))) return st;
+      if ((st = upload(&D.d_el_local_ptr, P.el_local_ptr))) return st;
+      if ((st = upload(&D.d_el_local, P.el_local))) return st;
+      if ((st = upload(&D.d_el_sub, P.el_sub))) return st;
+      if ((st = upload(&D.d_sub_off, D.K.off))) return st;
+      if ((st = upload(&D.d_sub_nt, D.K.nt))) return st;
+      if (li > 0) {
+        if ((st = upload(&D.d_ekc_off, lev[li - 1].kc_off))) return st;
+      }
+    }
+
+    // flat layouts
+    D.gofs.assign(ns + 1, 0);
+    D.iofs.assign(ns + 1, 0);
+    D.cofs.assign(ns + 1, 0);
+    for (int b = 0; b < ns; ++b) {
+      D.gofs[b + 1] = D.gofs[b] + P.subs[b].nGp;
+      D.iofs[b + 1] = D.iofs[b] + P.subs[b].nIp;
+      D.cofs[b + 1] = D.cofs[b] + P.subs[b].ncp;
+    }
+    D.nG_flat = D.gofs[ns];
+    D.nI_flat = D.iofs[ns];
+    D.nC_flat = D.cofs[ns];
+    {
+      std::vector<int32_t> gidx(D.nG_flat, -1), iidx(D.nI_flat, -1), cidx(D.nC_flat, -1);
+      std::vector<int64_t> gdiag(D.nG_flat, 0);
+      const int64_t nif = (int64_t)P.iface_dofs.size();
+      std::vector<int64_t> gcnt(nif + 1, 0), ccnt(P.n_coarse + 1, 0);
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        for (int64_t k = 0; k < S.nG; ++k) {
+          gidx[D.gofs[b] + k] = S.iface[k];
+          gcnt[S.iface[k] + 1]++;
+        }
+        for (int64_t k = 0; k < S.nGp; ++k) gdiag[D.gofs[b] + k] = D.K.off[b] + packed_offset(S.nIp + k, S.nIp + k, D.K.nt[b]);
+        for (int64_t k = 0; k < S.nI; ++k) iidx[D.iofs[b] + k] = (int32_t)S.dofI[k];
+        for (int k = 0; k < S.nc; ++k) {
+          cidx[D.cofs[b] + k] = S.coarse[k];
+          ccnt[S.coarse[k] + 1]++;
+        }
+      }
+      for (int64_t g = 0; g < nif; ++g) gcnt[g + 1] += gcnt[g];
+      for (int64_t g = 0; g < P.n_coarse; ++g) ccnt[g + 1] += ccnt[g];
+      std::vector<int64_t> glist(gcnt[nif]), clist(ccnt[P.n_coarse]);
+      {
+        std::vector<int64_t> pos(gcnt.begin(), gcnt.end() - 1), cpos(ccnt.begin(), ccnt.end() - 1);
+        for (int b = 0; b < ns; ++b) {
+          const SubPlan& S = P.subs[b];
+          for (int64_t k = 0; k < S.nG; ++k) glist[pos[S.iface[k]]++] = D.gofs[b] + k;
+          for (int k = 0; k < S.nc; ++k) clist[cpos[S.coarse[k]]++] = D.cofs[b] + k;
+        }
+      }
+      std::vector<int32_t> ifd(nif);
+      for (int64_t g = 0; g < nif; ++g) ifd[g] = (int32_t)P.iface_dofs[g];
+      if ((st = upload(&D.d_gidx, gidx))) return st;
+      if ((st = upload(&D.d_iidx, iidx))) return st;
+      if ((st = upload(&D.d_cidx, cidx))) return st;
+      if ((st = upload(&D.d_iface_dofs, ifd))) return st;
+      if ((st = upload(&D.d_gptr, gcnt))) return st;
+      if ((st = upload(&D.d_glist, glist))) return st;
+      if ((st = upload(&D.d_cptr, ccnt))) return st;
+      if ((st = upload(&D.d_clist, clist))) return st;
+      if ((st = upload(&D.d_gdiag_pos, gdiag))) return st;
+    }
+    const size_t mesz = D.mfp32 ? 4 : 8, kesz = D.kfp32 ? 4 : 8;
+    auto valloc = [&](void** p, int64_t n, size_t esz) -> mlbddc_status {
+      return esz == 4 ? dalloc((float**)p, std::max<int64_t>(n, 1)) : dalloc((double**)p, std::max<int64_t>(n, 1));
+    };
+    if ((st = dalloc(&D.d_w, std::max<int64_t>(D.nG_flat, 1)))) return st;
+    if ((st = valloc(&D.rl, D.nG_flat, mesz))) return st;
+    if ((st = valloc(&D.yl, D.nG_flat, mesz))) return st;
+    if ((st = valloc(&D.zcl, D.nC_flat, mesz))) return st;
+    if ((st = dalloc(&D.rcl, std::max<int64_t>(D.nC_flat, 1)))) return st;
+    if ((st = dalloc(&D.rC, std::max<int64_t>(P.n_coarse, 1)))) return st;
+    if ((st = dalloc(&D.zC, std::max<int64_t>(P.n_coarse, 1)))) return st;
+    if ((st = dalloc(&D.rhat, std::max<int64_t>((int64_t)P.iface_dofs.size(), 1)))) return st;
+    if ((st = dalloc(&D.zhat, std::max<int64_t>((int64_t)P.iface_dofs.size(), 1)))) return st;
+    if ((st = valloc(&D.rI, D.nI_flat, kesz))) return st;
+    if ((st = valloc(&D.uI, D.nI_flat, kesz))) return st;
+    if ((st = valloc(&D.zG, D.nG_flat, kesz))) return st;
+    if ((st = dalloc(&D.tG, std::max<int64_t>(D.nG_flat, 1)))) return st;
+    if ((st = dalloc(&D.gd, std::max<int64_t>(D.nG_flat, 1)))) return st;
+    if ((st = dalloc(&D.gd2, std::max<int64_t>(D.nG_flat, 1)))) return st;
+    if ((st = dalloc(&D.wI, std::max<int64_t>(D.nI_flat, 1)))) return st;
+
+    // K-job tile mat-vecs
+    {
+      std::vector<MvDesc> s, pre, lgi;
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
+        if (li == 0) {
+          s.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, tI, tG, D.gofs[b], D.gofs[b], 0, nullptr});
+          if (tI > 0 && tG > 0)
+            lgi.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, 0, tI, D.iofs[b], D.gofs[b], 0, nullptr});
+        } else if (tI > 0) {
+          int tId = tI + tG;
+          pre.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tId, tI, D.iofs[b], D.iofs[b], 0, nullptr});
+        }
+      }
+      if (li == 0) {
+        if ((st = build_mv(D.mvS, MV_SYM, s))) return st;
+        // L_GI products: condensation (N: y_G = L_GI w_I) and recovery (T: y_I = L_GI^T u_G)
+        std::vector<MvDesc> lt = lgi;
+        for (auto& d : lt) { d.x_off = 0; }
+        for (size_t i = 0; i < lgi.size(); ++i) { lt[i].x_off = lgi[i].y_off; lt[i].y_off = lgi[i].x_off; }
+        if ((st = build_mv(D.mvLgi, MV_N, lgi))) return st;
+        if ((st = build_mv(D.mvLgiT, MV_T, lt))) return st;
+        std::vector<int32_t*> envs;
+        for (int b = 0; b < ns; ++b) {
+          const SubPlan& S = P.subs[b];
+          int32_t* de = nullptr;
+          if ((st = upload(&de, S.envK))) return st;
+          D.trsv_h.push_back(TrsvDesc{D.K.off[b], D.K.nt[b], (int32_t)(S.nIp / TS), D.K.inv_off[b], D.iofs[b], de});
+        }
+        // envelopes for the L_GI products
+        for (size_t i = 0; i < D.mvLgi.h.size(); ++i) {}
+        if ((st = upload(&D.d_trsv, D.trsv_h))) return st;
+      } else if (!P.top || true) {
+        if ((st = build_mv(D.mvPre, MV_SYM, pre))) return st;
+        if (!P.top) {
+          std::vector<MvDesc> pt, pn;
+          for (int b = 0; b < ns; ++b) {
+            const SubPlan& S = P.subs[b];
+            int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
+            if (tI == 0 || tG == 0) continue;
+            int tId = tI + tG;
+            pt.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.iofs[b], D.gofs[b], 0, nullptr});
+            pn.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.gofs[b], D.iofs[b], 0, nullptr});
+          }
+          if ((st = build_mv(D.mvPreT, MV_T, pt))) return st;
+          if ((st = build_mv(D.mvPostN, MV_N, pn))) return st;
+        }
+      }
+    }
+
+    // ---- preconditioner job and coarse matrices
+    if (!P.top) {
+      D.M.nt.resize(ns);
+      D.M.items.resize(ns);
+      D.M.env.resize(ns);
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
+        int nt = 2 * (tG + tC);
+        D.M.nt[b] = nt;
+        D.M.items[b].nt = nt;
+        D.M.items[b].e1 = tG;
+        D.M.items[b].e2 = tC;
+        std::vector<int32_t> env(nt, 0);
+        // C rows: first interface tile touched by the row's glob
+        std::vector<int32_t> cfirst(tC, tG);
+        for (int c = 0; c < S.nc; ++c) {
+          int m = INT32_MAX;
+          for (int j = S.crow_ptr[c]; j < S.crow_ptr[c + 1]; ++j) m = std::min(m, S.crow_col[j]);
+          cfirst[c / TS] = std::min(cfirst[c / TS], m / TS);
+        }
+        for (int r = 0; r < tC; ++r) env[tG + r] = std::min(cfirst[r], tG + r);
+        for (int r = 0; r < tG; ++r) env[tG + tC + r] = r;
+        for (int r = 0; r < tC; ++r) env[2 * tG + tC + r] = tG;
+        D.M.env[b] = env;
+      }
+      if ((st = prepare_job(D.M, D.mfp32))) return st;
+      flops_M += D.M.sched.flops;
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        int tG = (int)(S.nGp / TS);
+        D.copy_h.push_back(CopyDesc{D.K.off[b], D.K.nt[b], (int32_t)(S.nIp / TS), D.M.off[b], D.M.nt[b], tG});
+        D.copy_max = std::max(D.copy_max, tG);
+        auto add = [&](int64_t r0, int64_t c0, int64_t cnt, double v) {
+          if (cnt > 0) D.msegs_h.push_back(DiagSeg{D.M.off[b], D.M.nt[b], (int32_t)r0, (int32_t)c0, (int32_t)cnt, v});
+        };
+        add(S.nGp + S.nc, S.nGp + S.nc, S.ncp - S.nc, -1.0);
+        add(S.nGp + S.ncp, 0, S.nGp, 1.0);
+        add(2 * S.nGp + S.ncp, S.nGp, S.ncp, 1.0);
+      }
+      for (auto& s : D.msegs_h) D.mseg_max = std::max(D.mseg_max, s.count);
+      if ((st = upload(&D.d_msegs, D.msegs_h))) return st;
+      if ((st = upload(&D.d_copy, D.copy_h))) return st;
+      std::vector<int32_t> ccols;
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        for (int c = 0; c < S.nc; ++c) {
+          ConsDesc cd;
+          cd.kdiag_off = D.K.off[b];
+          cd.k_nt = D.K.nt[b];
+          cd.k_g0 = (int32_t)S.nIp;
+          cd.p_off = D.M.off[b];
+          cd.p_nt = D.M.nt[b];
+          cd.c_row0 = (int32_t)S.nGp + c;
+          cd.ptr0 = (int32_t)ccols.size();
+          for (int j = S.crow_ptr[c]; j < S.crow_ptr[c + 1]; ++j) ccols.push_back(S.crow_col[j]);
+          cd.ptr1 = (int32_t)ccols.size();
+          D.cons_h.push_back(cd);
+        }
+      }
+      if ((st = upload(&D.d_cons, D.cons_h))) return st;
+      if ((st = upload(&D.d_ccols, ccols))) return st;
+      // coarse matrices
+      int64_t toff = 0, kcoff = 0, cmp = 0;
+      std::vector<int32_t> ntc(ns), ncv(ns);
+      D.kc_off.resize(ns);
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
+        KcDesc kd;
+        kd.k_off = D.K.off[b];
+        kd.k_nt = D.K.nt[b];
+        kd.k_g0 = (int32_t)(S.nIp / TS);
+        kd.p_off = D.M.off[b];
+        kd.p_nt = D.M.nt[b];
+        kd.p_c0 = 2 * tG + tC;
+        kd.p_d0 = tG + tC;
+        kd.ntg = tG;
+        kd.ntc = tC;
+        kd.t_off = toff;
+        toff += (int64_t)tG * tC * TE;
+        kd.kc_off = kcoff;
+        D.kct_off_h.push_back(kcoff);
+        kcoff += (int64_t)tC * tC * TE;
+        D.kcd_h.push_back(kd);
+        D.kc_max_ntg = std::max(D.kc_max_ntg, tG);
+        D.kc_max_ntc = std::max(D.kc_max_ntc, tC);
+        D.max_nc = std::max(D.max_nc, S.nc);
+        ntc[b] = tC;
+        ncv[b] = S.nc;
+        D.kc_off[b] = cmp;
+        cmp += (int64_t)S.nc * S.nc;
+      }
+      if ((st = upload(&D.d_kcd, D.kcd_h))) return st;
+      if ((st = upload(&D.d_kct_off, D.kct_off_h))) return st;
+      if ((st = upload(&D.d_ntc, ntc))) return st;
+      if ((st = upload(&D.d_nc, ncv))) return st;
+      if ((st = upload(&D.d_kc_off, D.kc_off))) return st;
+      if ((st = dalloc(&D.Tscr, std::max<int64_t>(toff, 1)))) return st;
+      if ((st = dalloc(&D.KCt, std::max<int64_t>(kcoff, 1)))) return st;
+      if ((st = dalloc(&D.kc_compact, std::max<int64_t>(cmp, 1)))) return st;
+      // M-job tile mat-vecs
+      std::vector<MvDesc> g, pn, pt;
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
+        int id0 = tG + tC, ic0 = 2 * tG + tC;
+        g.push_back(MvDesc{D.M.off[b], D.M.nt[b], id0, tG, id0, tG, D.gofs[b], D.gofs[b], 0, nullptr});
+        pn.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.gofs[b], D.cofs[b], 0, nullptr});
+        pt.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.cofs[b], D.gofs[b], 0, nullptr});
+      }
+      if ((st = build_mv(D.mvG, MV_SYM, g))) return st;
+      if ((st = build_mv(D.mvPsiN, MV_N, pn))) return st;
+      if ((st = build_mv(D.mvPsiT, MV_T, pt))) return st;
+    }
+    // partial-sum scratch: the largest of this level's products
+    int64_t pmax = 1;
+    for (MvSet* s : {&D.mvS, &D.mvG, &D.mvPsiN, &D.mvPsiT, &D.mvPre, &D.mvPreT, &D.mvPostN, &D.mvLgi, &D.mvLgiT})
+      pmax = std::max(pmax, s->partial_elems);
+    if ((st = dalloc((double**)&D.partial, pmax))) return st;
+  }
+
+  // PCG vectors
+  const int64_t nif = (int64_t)plan.levels[0].iface_dofs.size();
+  const int64_t ndofs = plan.levels[0].n_dofs;
+  for (double** p : {&d_x, &d_r, &d_z, &d_p, &d_q, &d_g})
+    if ((st = dalloc(p, std::max<int64_t>(nif, 1)))) return st;
+  max_hist = std::max(opt.max_iter, 1) + 2;
+  if ((st = dalloc(&d_s, S_NSCAL))) return st;
+  if ((st = dalloc(&d_hist, 2 * (int64_t)max_hist))) return st;
+  if ((st = dalloc(&d_dotp, DOT_BLOCKS))) return st;
+  HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+  (void)ndofs;
+  HIPCHK(hipStreamSynchronize(stream));
+  if ((st = validate())) return st;
+  t_plan = now() - t0;
+  return numeric();
+}
+
+// Host check of every index the kernels will use against the buffers they
+// address, run once per set-up before any kernel touches the data.
+mlbddc_status Handle::validate() {
+  auto bad = [&](const std::string& what) { return fail(MLBDDC_E_ARG, "internal layout check failed: " + what); };
+  for (size_t li = 0; li < lev.size(); ++li) {
+    LevelDev& D = lev[li];
+    LevelPlan& P = *D.P;
+    const std::string L = "level " + std::to_string(li + 1) + ": ";
+    for (Job* J : {&D.K, &D.M}) {
+      if (J->nt.empty()) continue;
+      const size_t ni = J->nt.size();
+      for (size_t i = 0; i < ni; ++i) {
+        if (J->off[i] + packed_tiles(J->nt[i]) * TE > J->elems) return bad(L + "job matrix extent");
+        if (J->inv_off[i] + (int64_t)(J->items[i].e1 + J->items[i].e2) * TE > std::max<int64_t>(J->inv_elems, 1))
+          return bad(L + "inverse tile extent");
+        if (J->items[i].e1 + J->items[i].e2 > J->nt[i]) return bad(L + "elimination beyond the matrix");
+        if ((int)J->env[i].size() != J->nt[i]) return bad(L + "envelope size");
+        if (J->nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
+      }
+      if (ni >= (1u << 24)) return bad(L + "too many matrices for the task encoding");
+      for (const FactorLaunch& F : J->sched.launches) {
+        for (int64_t q = F.first; q < F.first + F.count; ++q) {
+          uint64_t t = J->sched.tasks[q];
+          size_t it = (size_t)task_item(t);
+          int r = task_r(t), c = task_s(t), kf = task_kf(t);
+          if (it >= ni) return bad(L + "task item");
+          int nt = J->nt[it], ee = J->items[it].e1 + J->items[it].e2;
+          if (r >= nt || c > r) return bad(L + "task tile");
+          switch (F.kind) {
+            case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return bad(L + "diag task"); break;
+            case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return bad(L + "panel task"); break;
+            case L_INPANEL: if (c != F.k || kf >= F.k) return bad(L + "in-panel task"); break;
+            case L_TRAIL: if (c <= F.k || kf > F.k) return bad(L + "trailing task"); break;
+            case L_NEGATE: if (c < J->items[it].e1) return bad(L + "negate task"); break;
+            default: return bad(L + "task kind");
+          }
+        }
+      }
+    }
+    // element maps
+    for (int64_t e = 0; e + 1 < (int64_t)P.el_local_ptr.size(); ++e) {
+      int b = P.el_sub[e];
+      int64_t nK = (int64_t)D.K.nt[b] * TS;
+      for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
+        if (P.el_local[j] >= nK) return bad(L + "element map");
+      if (li > 0) {
+        const LevelPlan& PP = *lev[li - 1].P;
+        int64_t nloc = P.el_local_ptr[e + 1] - P.el_local_ptr[e];
+        const SubPlan& S = PP.subs[e];
+        if (nloc != S.nc || lev[li - 1].kc_off[e] + nloc * nloc > (int64_t)lev[li - 1].kc_off.back() + (int64_t)PP.subs.back().nc * PP.subs.back().nc)
+          return bad(L + "coarse element matrix");
+      }
+    }
+    auto seg_ok = [&](const std::vector<DiagSeg>& v) {
+      for (const DiagSeg& g : v)
+        if (g.row0 < g.col0 || (int64_t)g.row0 + g.count > (int64_t)g.nt * TS || (int64_t)g.col0 + g.count > (int64_t)g.nt * TS)
+          return false;
+      return true;
+    };
+    if (!seg_ok(D.ksegs_h) || !seg_ok(D.msegs_h)) return bad(L + "diagonal segment");
+    auto mv_ok = [&](const MvSet& s, const Job& J, int64_t xlen, int64_t ylen) {
+      for (const MvDesc& d : s.h) {
+        if (d.r0 + d.nr > d.a_nt || d.c0 + d.nc > d.a_nt) return false;
+        if (s.mode == MV_SYM && (d.r0 != d.c0 || d.nr != d.nc)) return false;
+        if (s.mode != MV_SYM && d.r0 < d.c0 + d.nc) return false;
+        if (d.a_off + packed_tiles(d.a_nt) * TE > J.elems) return false;
+        int64_t nx = (s.mode == MV_T ? d.nr : d.nc) * (int64_t)TS, ny = (s.mode == MV_T ? d.nc : d.nr) * (int64_t)TS;
+        if (d.x_off + nx > xlen || d.y_off + ny > ylen) return false;
+        if (d.p_off + (int64_t)d.nr * d.nc * TS > s.partial_elems) return false;
+      }
+      return true;
+    };
+    if (li == 0) {
+      if (!mv_ok(D.mvS, D.K, D.nG_flat, D.nG_flat)) return bad(L + "S mat-vec");
+      if (!mv_ok(D.mvLgi, D.K, D.nI_flat, D.nG_flat)) return bad(L + "L_GI mat-vec");
+      if (!mv_ok(D.mvLgiT, D.K, D.nG_flat, D.nI_flat)) return bad(L + "L_GI^T mat-vec");
+      for (const TrsvDesc& t : D.trsv_h)
+        if (t.nti > t.a_nt || t.v_off + (int64_t)t.nti * TS > D.nI_flat || t.inv_off + (int64_t)t.nti * TE > D.K.inv_elems + (t.nti == 0))
+          return bad(L + "triangular solve");
+    } else {
+      if (!mv_ok(D.mvPre, D.K, D.nI_flat, D.nI_flat)) return bad(L + "interior mat-vec");
+      if (!P.top && (!mv_ok(D.mvPreT, D.K, D.nI_flat, D.nG_flat) || !mv_ok(D.mvPostN, D.K, D.nG_flat, D.nI_flat)))
+        return bad(L + "correction mat-vec");
+    }
+    if (!P.top) {
+      if (!mv_ok(D.mvG, D.M, D.nG_flat, D.nG_flat)) return bad(L + "G mat-vec");
+      if (!mv_ok(D.mvPsiN, D.M, D.nG_flat, D.nC_flat)) return bad(L + "Psi^T mat-vec");
+      if (!mv_ok(D.mvPsiT, D.M, D.nC_flat, D.nG_flat)) return bad(L + "Psi mat-vec");
+      int64_t tsz = 0, ksz = 0;
+      for (const KcDesc& k : D.kcd_h) {
+        tsz = std::max(tsz, k.t_off + (int64_t)k.ntg * k.ntc * TE);
+        ksz = std::max(ksz, k.kc_off + (int64_t)k.ntc * k.ntc * TE);
+        if (k.k_g0 + k.ntg > k.k_nt || k.p_c0 + k.ntc > k.p_nt || k.p_d0 + k.ntg > k.p_nt || k.p_c0 < k.p_d0 + k.ntg)
+          return bad(L + "coarse matrix descriptor");
+      }
+      for (const CopyDesc& c : D.copy_h)
+        if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt) return bad(L + "copy descriptor");
+      for (size_t b = 0; b < P.subs.size(); ++b) {
+        const SubPlan& S = P.subs[b];
+        for (int32_t col : S.crow_col)
+          if (col >= S.nG) return bad(L + "constraint column");
+        for (int32_t g : S.iface)
+          if (g < 0 || g >= (int64_t)P.iface_dofs.size()) return bad(L + "interface map");
+        for (int32_t c : S.coarse)
+          if (c < 0 || c >= P.n_coarse) return bad(L + "coarse map");
+        if (S.nGp + S.nc > (int64_t)D.M.nt[b] * TS) return bad(L + "constraint rows");
+      }
+    }
+    for (size_t b = 0; b < P.subs.size(); ++b)
+      for (int64_t d : P.subs[b].dofI)
+        if (d < 0 || d >= P.n_dofs) return bad(L + "interior map");
+    for (int64_t d : P.iface_dofs)
+      if (d < 0 || d >= P.n_dofs) return bad(L + "interface DOF");
+  }
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::numeric() {
+  double t0 = now();
+  mlbddc_status st;
+  const int nlev = (int)lev.size();
+  for (int li = 0; li < nlev; ++li) {
+    LevelDev& D = lev[li];
+    LevelPlan& P = *D.P;
+    // assemble K
+    HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
+    for (int c = 0; c < P.n_colors; ++c) {
+      int64_t n = D.color_ptr[c + 1] - D.color_ptr[c];
+      const int64_t* el = D.d_elems_by_color + D.color_ptr[c];
+      const double* kref = li == 0 ? d_Kref : nullptr;
+      const double* ekc = li == 0 ? nullptr : lev[li - 1].kc_compact;
+      if (D.kfp32)
+        launch_assemble<float>(stream, el, n, D.d_el_local_ptr, D.d_el_local, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
+                               d_scale, D.d_ekc_off, ekc, (float*)D.K.buf);
+      else
+        launch_assemble<double>(stream, el, n, D.d_el_local_ptr, D.d_el_local, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
+                                d_scale, D.d_ekc_off, ekc, (double*)D.K.buf);
+    }
+    if (D.kfp32)
+      launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf);
+    else
+      launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
+    HIPCHK(hipGetLastError());
+    // weights from the assembled interface diagonal (before factorization)
+    if (!P.top) {
+      const int64_t nif = (int64_t)P.iface_dofs.size();
+      if (opt.weights == MLBDDC_W_MULTIPLICITY) {
+        launch_fill(stream, D.nG_flat, 1.0, D.gd);
+      } else {
+        // gd[i] = K[gdiag_pos[i]]: the assembled (sub-assembled) diagonal at the interface
+        if (D.kfp32) launch_gather64<float>(stream, D.nG_flat, D.d_gdiag_pos, (const float*)D.K.buf, D.gd);
+        else launch_gather64<double>(stream, D.nG_flat, D.d_gdiag_pos, (const double*)D.K.buf, D.gd);
+      }
+      // sum over subdomains per interface DOF, then w = d / sum
+      launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd, D.rhat, 0.0);
+      launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.rhat, D.gd2);
+      launch_ratio(stream, D.nG_flat, D.gd, D.gd2, D.d_gidx, D.d_w);
+    }
+    if ((st = factor(D.K, P.level, false))) return st;
+    if (P.top) continue;
+    // preconditioner matrices
+    HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
+    if (D.kfp32) {  // K is FP32 only when M is FP32
+      launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
+      launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
+                                       (float*)D.M.buf);
+      launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
+    } else if (D.mfp32) {
+      launch_copy_block<double, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (float*)D.M.buf);
+      launch_constraints<double, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
+                                        (float*)D.M.buf);
+      launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
+    } else {
+      launch_copy_block<double, double>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (double*)D.M.buf);
+      launch_constraints<double, double>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
+                                         (double*)D.M.buf);
+      launch_set_diag<double>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (double*)D.M.buf);
+    }
+    HIPCHK(hipGetLastError());
+    if ((st = factor(D.M, P.level, true))) return st;
+    // K_Ci = Psi^T S Psi
+    if (D.kfp32) {
+      launch_coarse_matrix<float, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const float*)D.K.buf,
+                                         (const float*)D.M.buf, D.Tscr, D.KCt);
+    } else if (D.mfp32) {
+      launch_coarse_matrix<double, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
+                                  (const float*)D.M.buf, D.Tscr, D.KCt);
+    } else {
+      launch_coarse_matrix<double, double>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
+                                   (const double*)D.M.buf, D.Tscr, D.KCt);
+    }
+    launch_compact_kc(stream, D.d_kct_off, D.d_ntc, D.d_nc, D.d_kc_off, P.n_sub, D.max_nc, D.KCt, D.kc_compact);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  t_setup = now() - t0;
+  ready = true;
+  return MLBDDC_OK;
+}
+
+// --------------------------------------------------------------------- apply
+mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat) {
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
+  mlbddc_status st;
+  // r_i = D_i R_i r^
+  if (D.mfp32) launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
+  else launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
+  // r_C = sum R_Ci^T Psi_i^T r_i
+  if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
+  else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, 1.0, false, D.partial);
+  launch_seg_reduce<double>(stream, P.n_coarse, D.d_cptr, D.d_clist, nullptr, D.rcl, D.rC, 0.0);
+  // coarse correction: the next level
+  if ((st = apply_full(li + 1, D.rC, D.zC))) return st;
+  // y_i = G_i r_i + Psi_i R_Ci z_C
+  if (D.mfp32) {
+    launch_gather<double, float>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (float*)D.zcl);
+    run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial);
+    run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
+    launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0);
+  } else {
+    launch_gather<double, double>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (double*)D.zcl);
+    run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial);
+    run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
+    launch_seg_reduce<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl, zhat,
+                              0.0);
+  }
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+// One step of the level-li preconditioner on a whole level vector (interior
+// pre-correction, interface BDDC, post-correction), or the top solve.
+mlbddc_status Handle::apply_full(int li, const double* r, double* z) {
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
+  mlbddc_status st;
+  const bool f32 = D.kfp32;
+  // u_I = K_II^{-1} r_I  (the stored block is -K_II^{-1})
+  if (f32) {
+    launch_gather<double, float>(stream, D.nI_flat, D.d_iidx, nullptr, r, (float*)D.rI);
+    run_mv<float, float, float>(D.mvPre, D.K, (const float*)D.rI, (float*)D.uI, -1.0, false, D.partial);
+  } else {
+    launch_gather<double, double>(stream, D.nI_flat, D.d_iidx, nullptr, r, (double*)D.rI);
+    run_mv<double, double, double>(D.mvPre, D.K, (const double*)D.rI, (double*)D.uI, -1.0, false, D.partial);
+  }
+  if (P.top) {
+    if (f32) launch_scatter<float, double>(stream, D.nI_flat, D.d_iidx, (const float*)D.uI, z);
+    else launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, (const double*)D.uI, z);
+    HIPCHK(hipGetLastError());
+    return MLBDDC_OK;
+  }
+  // r^ = r_G - sum R^T K_GI u_I   (the stored block is -K_II^{-1} K_IG)
+  const int64_t nif = (int64_t)P.iface_dofs.size();
+  if (f32) run_mv<float, float, double>(D.mvPreT, D.K, (const float*)D.rI, D.tG, 1.0, false, D.partial);
+  else run_mv<double, double, double>(D.mvPreT, D.K, (const double*)D.rI, D.tG, 1.0, false, D.partial);
+  launch_gather<double, double>(stream, nif, D.d_iface_dofs, nullptr, r, D.rhat);
+  launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.tG, D.rhat, 1.0);
+  if ((st = apply_interface(li, D.rhat, D.zhat))) return st;
+  // z_I = u_I - K_II^{-1} K_IG z_G
+  if (f32) {
+    launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, nullptr, D.zhat, (float*)D.zG);
+    run_mv<float, float, float>(D.mvPostN, D.K, (const float*)D.zG, (float*)D.uI, 1.0, true, D.partial);
+    launch_scatter<float, double>(stream, D.nI_flat, D.d_iidx, (const float*)D.uI, z);
+  } else {
+    launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.zhat, (double*)D.zG);
+    run_mv<double, double, double>(D.mvPostN, D.K, (const double*)D.zG, (double*)D.uI, 1.0, true, D.partial);
+    launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, (const double*)D.uI, z);
+  }
+  launch_scatter_idx(stream, nif, D.d_iface_dofs, D.zhat, z);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::schur(const double* x, double* y) {
+  LevelDev& D = lev[0];
+  launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, x, D.gd);
+  run_mv<double, double, double>(D.mvS, D.K, D.gd, D.gd2, 1.0, false, D.partial);
+  launch_seg_reduce<double>(stream, (int64_t)D.P->iface_dofs.size(), D.d_gptr, D.d_glist, nullptr, D.gd2, y, 0.0);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::condense(const double* f, double* g) {
+  LevelDev& D = lev[0];
+  const int64_t nif = (int64_t)D.P->iface_dofs.size();
+  launch_gather<double, double>(stream, D.nI_flat, D.d_iidx, nullptr, f, D.wI);
+  launch_trsv(stream, false, D.d_trsv, D.P->n_sub, (const double*)D.K.buf, (const double*)D.K.inv, D.wI);
+  launch_fill(stream, D.nG_flat, 0.0, D.tG);
+  run_mv<double, double, double>(D.mvLgi, D.K, D.wI, D.tG, -1.0, false, D.partial);
+  launch_gather<double, double>(stream, nif, D.d_iface_dofs, nullptr, f, g);
+  launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.tG, g, 1.0);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::recover(const double* uhat, double* u) {
+  LevelDev& D = lev[0];
+  const int64_t nif = (int64_t)D.P->iface_dofs.size();
+  launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, uhat, D.gd);
+  run_mv<double, double, double>(D.mvLgiT, D.K, D.gd, D.wI, -1.0, true, D.partial);
+  launch_trsv(stream, true, D.d_trsv, D.P->n_sub, (const double*)D.K.buf, (const double*)D.K.inv, D.wI);
+  launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, D.wI, u);
+  launch_scatter_idx(stream, nif, D.d_iface_dofs, uhat, u);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+// Lanczos estimates from the CG coefficients (tridiagonal eigenvalues by bisection).
+static void lanczos(const std::vector<double>& al, const std::vector<double>& be, double& lo, double& hi) {
+  const int k = (int)al.size();
+  lo = hi = 0.0;
+  if (k == 0) return;
+  std::vector<double> d(k), e(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = std::sqrt(std::max(be[j], 0.0)) / al[j];
+  }
+  double gl = 1e300, gh = -1e300;
+  for (int j = 0; j < k; ++j) {
+    double rad = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < k ? std::fabs(e[j]) : 0.0);
+    gl = std::min(gl, d[j] - rad);
+    gh = std::max(gh, d[j] + rad);
+  }
+  auto count_below = [&](double x) {  // Sturm count of eigenvalues < x
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int j = 1; j < k; ++j) {
+      double qq = q == 0.0 ? 1e-300 : q;
+      q = d[j] - x - e[j - 1] * e[j - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int idx) {
+    double a = gl, b = gh;
+    for (int it = 0; it < 200; ++it) {
+      double m = 0.5 * (a + b);
+      if (count_below(m) > idx) b = m; else a = m;
+    }
+    return 0.5 * (a + b);
+  };
+  lo = kth(0);
+  hi = kth(k - 1);
+}
+
+mlbddc_status Handle::solve(const double* f, double* u, const double* u0, mlbddc_stats* stt) {
+  double t0 = now();
+  mlbddc_status st;
+  LevelDev& D = lev[0];
+  const int64_t n = (int64_t)D.P->iface_dofs.size();
+  if ((st = condense(f, d_g))) return st;
+  // x0
+  if (u0) launch_gather<double, double>(stream, n, D.d_iface_dofs, nullptr, u0, d_x);
+  else launch_fill(stream, n, 0.0, d_x);
+  // r = g - S x0
+  if (u0) {
+    if ((st = schur(d_x, d_r))) return st;
+    launch_axpby(stream, n, 1.0, d_g, -1.0, d_r);
+  } else {
+    HIPCHK(hipMemcpyAsync(d_r, d_g, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+  }
+  launch_dot(stream, n, d_g, d_g, d_dotp, DOT_BLOCKS, d_s + S_GG);
+  launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
+  HIPCHK(hipMemcpyAsync(h_s, d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const double gnorm = std::sqrt(h_s[S_GG]);
+  double rel = gnorm > 0 ? std::sqrt(h_s[S_RR]) / gnorm : 0.0;
+  int it = 0;
+  bool conv = rel < opt.rtol;
+  bool breakdown = false;
+  if (!conv) {
+    if ((st = apply_interface(0, d_r, d_z))) return st;
+    launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZ);
+    HIPCHK(hipMemcpyAsync(d_p, d_z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+    while (it < opt.max_iter) {
+      if ((st = schur(d_p, d_q))) return st;
+      launch_dot(stream, n, d_p, d_q, d_dotp, DOT_BLOCKS, d_s + S_PQ);
+      launch_pcg_alpha(stream, d_s, d_hist, it);
+      launch_pcg_update_xr(stream, n, d_x, d_r, d_p, d_q, d_s);
+      launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
+      HIPCHK(hipMemcpyAsync(h_s, d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
+      if ((st = apply_interface(0, d_r, d_z))) return st;
+      launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZNEW);
+      HIPCHK(hipStreamSynchronize(stream));
+      ++it;
+      if (!(h_s[S_PQ] > 0.0) || !std::isfinite(h_s[S_PQ])) { breakdown = true; break; }
+      rel = std::sqrt(h_s[S_RR]) / gnorm;
+      if (rel < opt.rtol) { conv = true; break; }
+      launch_pcg_beta(stream, d_s, d_hist, it - 1);
+      launch_pcg_update_p(stream, n, d_p, d_z, d_s);
+    }
+  }
+  if ((st = recover(d_x, u))) return st;
+  // history for the Lanczos estimate
+  std::vector<double> hist(2 * (size_t)std::max(it, 1));
+  if (it > 0) HIPCHK(hipMemcpyAsync(hist.data(), d_hist, sizeof(double) * 2 * it, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (stt) {
+    std::vector<double> al, be;
+    for (int j = 0; j < it; ++j) al.push_back(hist[2 * j]);
+    for (int j = 0; j + 1 < it; ++j) be.push_back(hist[2 * j + 1]);
+    double lo, hi;
+    lanczos(al, be, lo, hi);
+    stt->iterations = it;
+    stt->converged = conv ? 1 : 0;
+    stt->rel_res = rel;
+    stt->lambda_min = lo;
+    stt->lambda_max = hi;
+    stt->t_plan = t_plan;
+    stt->t_setup_num = t_setup;
+    stt->t_solve = now() - t0;
+  }
+  if (breakdown) return fail(MLBDDC_E_BREAKDOWN, "PCG breakdown: p^T S p <= 0 or not finite");
+  if (!conv) return fail(MLBDDC_E_NOT_CONVERGED, "PCG did not reach the tolerance");
+  return MLBDDC_OK;
+}
+
+}  // namespace mlbddc
+
+// ======================================================================= ABI
+using mlbddc::Handle;
+
+struct mlbddc_handle_s {
+  Handle h;
+};
+
+static mlbddc::Error g_create_error;
+
+extern "C" {
+
+const char* mlbddc_status_string(mlbddc_status code) {
+  switch (code) {
+    case MLBDDC_OK: return "ok";
+    case MLBDDC_E_ARG: return "invalid argument";
+    case MLBDDC_E_HIP: return "HIP runtime error";
+    case MLBDDC_E_NOMEM: return "out of memory";
+    case MLBDDC_E_STATE: return "call out of order";
+    case MLBDDC_E_NOT_SPD: return "subdomain matrix not positive definite";
+    case MLBDDC_E_SINGULAR_CONSTRAINTS: return "constrained local problem singular";
+    case MLBDDC_E_NOT_CONVERGED: return "PCG did not converge";
+    case MLBDDC_E_BREAKDOWN: return "PCG breakdown";
+    case MLBDDC_E_NO_DEVICE: return "no HIP device";
+  }
+  return "unknown status";
+}
+
+void mlbddc_default_options(mlbddc_options* o) {
+  if (!o) return;
+  o->precision = MLBDDC_FP64;
+  o->rtol = 1e-8;
+  o->max_iter = 1000;
+  o->weights = MLBDDC_W_STIFFNESS;
+  o->use_graph = 0;
+  o->panel_tiles = 0;
+  o->device = 0;
+}
+
+mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stream) {
+  if (!out) return MLBDDC_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    g_create_error.status = MLBDDC_E_NO_DEVICE;
+    g_create_error.message = "no HIP device available";
+    return MLBDDC_E_NO_DEVICE;
+  }
+  mlbddc_options o;
+  mlbddc_default_options(&o);
+  if (opt) o = *opt;
+  if (o.device < 0 || o.device >= ndev || !(o.rtol > 0) || o.max_iter < 1 ||
+      (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED)) {
+    g_create_error.status = MLBDDC_E_ARG;
+    g_create_error.message = "invalid options";
+    return MLBDDC_E_ARG;
+  }
+  if (hipSetDevice(o.device) != hipSuccess) {
+    g_create_error.status = MLBDDC_E_HIP;
+    g_create_error.message = "hipSetDevice failed";
+    return MLBDDC_E_HIP;
+  }
+  auto* h = new mlbddc_handle_s();
+  h->h.opt = o;
+  h->h.stream = (hipStream_t)stream;
+  *out = h;
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_setup(mlbddc_t h, const mlbddc_mesh* mesh, const mlbddc_partition* part) {
+  if (!h) return MLBDDC_E_ARG;
+  h->h.err = mlbddc::Error();
+  return h->h.setup(mesh, part);
+}
+
+mlbddc_status mlbddc_update_coefficients(mlbddc_t h, const double* scale_dev) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.planned) return h->h.fail(MLBDDC_E_STATE, "update_coefficients before setup");
+  if (!scale_dev) return h->h.fail(MLBDDC_E_ARG, "null scale pointer");
+  hipError_t e = hipMemcpyAsync(h->h.d_scale, scale_dev, sizeof(double) * h->h.n_elems, hipMemcpyDeviceToDevice, h->h.stream);
+  if (e != hipSuccess) return h->h.herr("hipMemcpyAsync", e);
+  h->h.ready = false;
+  return h->h.numeric();
+}
+
+int64_t mlbddc_num_dofs(mlbddc_t h) { return h && h->h.planned ? h->h.plan.levels[0].n_dofs : -1; }
+int64_t mlbddc_interface_size(mlbddc_t h) {
+  return h && h->h.planned ? (int64_t)h->h.plan.levels[0].iface_dofs.size() : -1;
+}
+int64_t mlbddc_coarse_size(mlbddc_t h, int32_t level) {
+  if (!h || !h->h.planned || level < 1 || level >= (int32_t)h->h.plan.levels.size() + 0) return -1;
+  return h->h.plan.levels[level - 1].n_coarse;
+}
+int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level) {
+  if (!h || !h->h.planned || level < 1 || level > (int32_t)h->h.plan.levels.size()) return -1;
+  return h->h.plan.levels[level - 1].n_sub;
+}
+
+mlbddc_status mlbddc_apply(mlbddc_t h, const double* r, double* z) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "apply before setup");
+  if (!r || !z || r == z) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  return h->h.apply_interface(0, r, z);
+}
+
+mlbddc_status mlbddc_apply_schur(mlbddc_t h, const double* x, double* y) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "apply_schur before setup");
+  if (!x || !y || x == y) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  return h->h.schur(x, y);
+}
+
+mlbddc_status mlbddc_condense(mlbddc_t h, const double* f, double* g) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "condense before setup");
+  if (!f || !g) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  return h->h.condense(f, g);
+}
+
+mlbddc_status mlbddc_solve(mlbddc_t h, const double* f, double* u, const double* u0, mlbddc_stats* st) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "solve before setup");
+  if (!f || !u || f == u) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  return h->h.solve(f, u, u0, st);
+}
+
+mlbddc_status mlbddc_element_energy(mlbddc_t h, const double* a, const double* b, double* out) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "element_energy before setup");
+  if (!a || !b || !out) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  mlbddc::launch_element_energy(h->h.stream, h->h.n_elems, h->h.nloc1, h->h.d_edof, h->h.d_Kref, h->h.d_scale, a, b, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return h->h.herr("element_energy", e);
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* out) {
+  if (!h || !out) return MLBDDC_E_ARG;
+  Handle& H = h->h;
+  if (!H.ready) return H.fail(MLBDDC_E_STATE, "get_coarse_matrix before setup");
+  if (level < 1 || level >= (int32_t)H.lev.size()) return H.fail(MLBDDC_E_ARG, "bad level");
+  auto& D = H.lev[level - 1];
+  auto& P = *D.P;
+  const int64_t n = P.n_coarse;
+  std::vector<double> kc(D.kc_off.empty() ? 0 : (size_t)(D.kc_off.back() + (int64_t)P.subs.back().nc * P.subs.back().nc));
+  if (!kc.empty()) {
+    hipError_t e = hipMemcpyAsync(kc.data(), D.kc_compact, sizeof(double) * kc.size(), hipMemcpyDeviceToHost, H.stream);
+    if (e != hipSuccess) return H.herr("hipMemcpyAsync", e);
+    e = hipStreamSynchronize(H.stream);
+    if (e != hipSuccess) return H.herr("hipStreamSynchronize", e);
+  }
+  std::fill(out, out + n * n, 0.0);
+  for (int b = 0; b < P.n_sub; ++b) {
+    const auto& S = P.subs[b];
+    for (int a = 0; a < S.nc; ++a)
+      for (int c = 0; c < S.nc; ++c) out[(int64_t)S.coarse[a] * n + S.coarse[c]] += kc[D.kc_off[b] + (int64_t)a * S.nc + c];
+  }
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_destroy(mlbddc_t h) {
+  if (!h) return MLBDDC_OK;
+  (void)hipStreamSynchronize(h->h.stream);
+  h->h.free_all();
+  delete h;
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_last_error(mlbddc_t h, mlbddc_error* info) {
+  if (!info) return MLBDDC_E_ARG;
+  const mlbddc::Error& e = h ? h->h.err : g_create_error;
+  info->status = e.status;
+  info->level = e.level;
+  info->subdomain = e.subdomain;
+  info->column = e.column;
+  std::snprintf(info->message, sizeof(info->message), "%s", e.message.c_str());
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_plan_counts(const mlbddc_mesh* mesh, const mlbddc_partition* part, int64_t* counts) {
+  if (!mesh || !part || !counts) return MLBDDC_E_ARG;
+  mlbddc::PlanInput in;
+  in.dim = mesh->dim;
+  in.ndof = mesh->ndof_per_node;
+  in.n_nodes = mesh->n_nodes;
+  in.n_elems = mesh->n_elems;
+  in.nodes_per_elem = mesh->nodes_per_elem;
+  in.elem_nodes = mesh->elem_nodes;
+  in.dirichlet = mesh->dirichlet_nodes;
+  in.n_levels = part->n_levels;
+  in.elem_to_sub = part->elem_to_sub;
+  in.sub_to_parent = part->sub_to_parent;
+  in.constraints = part->constraints;
+  mlbddc::Plan plan;
+  mlbddc::Error err;
+  mlbddc_status st = mlbddc::build_plan(in, plan, err);
+  if (st) return st;
+  for (int l = 0; l + 1 < (int)plan.levels.size(); ++l) {
+    const auto& L = plan.levels[l];
+    int64_t* c = counts + 6 * l;
+    c[0] = L.n_sub;
+    c[1] = (int64_t)L.iface_dofs.size();
+    c[2] = L.n_coarse;
+    c[3] = L.counts[0];
+    c[4] = L.counts[1];
+    c[5] = L.counts[2];
+  }
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_plan_interface(const mlbddc_mesh* mesh, const mlbddc_partition* part, int64_t* iface_dofs, int32_t sub,
+                                    int64_t* n_gamma, int64_t* sub_iface) {
+  if (!mesh || !part) return MLBDDC_E_ARG;
+  mlbddc::PlanInput in;
+  in.dim = mesh->dim;
+  in.ndof = mesh->ndof_per_node;
+  in.n_nodes = mesh->n_nodes;
+  in.n_elems = mesh->n_elems;
+  in.nodes_per_elem = mesh->nodes_per_elem;
+  in.elem_nodes = mesh->elem_nodes;
+  in.dirichlet = mesh->dirichlet_nodes;
+  in.n_levels = 2;
+  in.elem_to_sub = part->elem_to_sub;
+  in.sub_to_parent = nullptr;
+  in.constraints = part->constraints;
+  mlbddc::Plan plan;
+  mlbddc::Error err;
+  mlbddc_status st = mlbddc::build_plan(in, plan, err);
+  if (st) return st;
+  const auto& L = plan.levels[0];
+  if (iface_dofs) std::copy(L.iface_dofs.begin(), L.iface_dofs.end(), iface_dofs);
+  if (sub >= 0 && sub < L.n_sub) {
+    const auto& S = L.subs[sub];
+    if (n_gamma) *n_gamma = S.nG;
+    if (sub_iface) std::copy(S.iface.begin(), S.iface.end(), sub_iface);
+  } else if (n_gamma) {
+    *n_gamma = -1;
+  }
+  return MLBDDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""Host-side checks of the HIP library (CPU only, no kernel launches).
+
+* the shared library loads and exports every entry point declared in
+  include/mlbddc.h;
+* its host routines (element matrices and loads, level planning: interface
+  numbering, globs, coarse sizes, local interface maps) agree with the oracle,
+  which was written independently from the paper.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from oracle.bddc import MultilevelBDDC
+from workloads import box_workload, config
+from workloads.gen import uniform_cuts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1201_5991_amd import _lib as L
+    return L
+
+
+def test_library_exports_header_symbols():
+    L = _lib()
+    lib = L.load()
+    header = open(os.path.join(ROOT, "include", "mlbddc.h")).read()
+    declared = set(re.findall(r"\b(mlbddc_[a-z_]+)\s*\(", header))
+    assert len(declared) >= 20
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTED)
+    assert lib.mlbddc_status_string(-5) == b"subdomain matrix not positive definite"
+
+
+def test_element_matrices_match_oracle():
+    from paper_1201_5991_amd import element_load, element_matrix
+    L = _lib()
+    for h in (0.125, 1.0 / 48):
+        K = element_matrix(L.MLBDDC_ELASTICITY_HEX8, h, 0.3)
+        assert np.allclose(K, fem.hex8_elasticity_element(1.0, 0.3, h), rtol=1e-13, atol=1e-16)
+    assert np.allclose(element_matrix(L.MLBDDC_POISSON_Q1, 0.1), fem.q1_laplace_element(), atol=1e-15)
+    w = box_workload("t", "elasticity", (4, 4, 4), [uniform_cuts(4, 2)] * 3)
+    assert np.allclose(element_load(L.MLBDDC_ELASTICITY_HEX8, w.h, w.body_force), fem.element_load(w))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_plan_counts_and_load_match_oracle(k):
+    from paper_1201_5991_amd import Problem
+    w = config(k)
+    pr = Problem(w)
+    counts = pr.counts()
+    b = MultilevelBDDC(w, structure_only=True)
+    for l, lev in enumerate(b.levels):
+        c = lev.glob_counts()
+        assert counts[l].tolist() == [lev.n_sub, lev.n_iface, lev.n_coarse, c["corner"], c["edge"], c["face"]]
+    _, f = fem.assemble_global(w)
+    assert np.allclose(pr.load_vector(), f, rtol=0, atol=1e-15)
+
+
+def test_plan_counts_large_configs_closed_form():
+    # 12^3 boxes (config 3): corners 11^3, edges 3*12*11^2, faces 3*12^2*11; level 2 (3^3): 8/36/54.
+    from paper_1201_5991_amd import Problem
+    c = Problem(config(3)).counts()
+    assert c[0].tolist() == [1728, 823812, 31317, 1331, 4356, 4752]
+    assert c[1].tolist()[0] == 27 and c[1].tolist()[2:] == [294, 8, 36, 54]
+    c4 = Problem(config(4)).counts()
+    assert c4[0].tolist() == [512, 375396, 8589, 343, 1176, 1344] and c4[1][2] == 837
+
+
+def test_plan_interface_maps_match_oracle():
+    from paper_1201_5991_amd import Problem
+    L = _lib()
+    rng = np.random.default_rng(0)
+    w = box_workload("t", "elasticity", (9, 9, 9), [uniform_cuts(9, 3)] * 3, young=10 ** (3 * rng.random(729)))
+    pr = Problem(w)
+    lev = MultilevelBDDC(w, n_levels=2).level1
+    m, p, keep = pr.structs()
+    ifd = np.zeros(lev.n_iface, dtype=np.int64)
+    ng = C.c_int64()
+    lib = L.load()
+    for sub in (0, 13, 26):
+        out = np.zeros(2000, dtype=np.int64)
+        L.check(lib.mlbddc_plan_interface(C.byref(m), C.byref(p), ifd.ctypes.data_as(C.POINTER(C.c_int64)), sub,
+                                          C.byref(ng), out.ctypes.data_as(C.POINTER(C.c_int64))))
+        assert np.array_equal(ifd, lev.iface_dofs)
+        assert sorted(out[: ng.value].tolist()) == sorted(lev.R[sub].tolist())
+
+
+def test_plan_rejects_bad_partition():
+    from paper_1201_5991_amd import Problem
+    L = _lib()
+    w = box_workload("t", "elasticity", (4, 4, 4), [uniform_cuts(4, 2)] * 3)
+    pr = Problem(w)
+    pr.elem_to_sub = pr.elem_to_sub.copy()
+    pr.elem_to_sub[pr.elem_to_sub == 3] = 7     # subdomains 3..6 become empty
+    with pytest.raises(L.MlbddcError) as e:
+        pr.counts()
+    assert e.value.name == "E_ARG"
