@@ -27,13 +27,18 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int LDT = TS + 1;  // LDS leading dimension of a staged tile (odd: conflict-free columns)
 
 template <typename T> struct Mfma;
+// Output layout of the 16x16x4 products: register v of lane l holds row
+// row(l/16, v) and column l%16 of the 16x16 block; the FP64 instruction
+// interleaves the rows (g + 4v), the FP32 one keeps them contiguous (4g + v).
 template <> struct Mfma<double> {
   typedef d4 acc_t;
+  __device__ static int row(int g, int v) { return g + 4 * v; }
   __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
   __device__ static acc_t mac(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 template <> struct Mfma<float> {
   typedef f4 acc_t;
+  __device__ static int row(int g, int v) { return 4 * g + v; }
   __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
   __device__ static acc_t mac(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
@@ -51,7 +56,7 @@ __device__ inline void stage_tile(T* __restrict__ s, const TSRC* __restrict__ g,
 
 // acc(i, j) += sum_k R(i, k) S(j, k) over one staged k-tile.  Wave w owns
 // rows (w&1)*32.. and columns (w>>1)*32.. of the output; lane l of block
-// (bi, bj) ends with rows i0 + l%16, columns j0 + 4*(l/16) + v.
+// (bi, bj) ends with rows i0 + l%16, columns j0 + Mfma<T>::row(l/16, v).
 template <typename T>
 __device__ inline void tile_nt(typename Mfma<T>::acc_t (&acc)[2][2], const T* __restrict__ sR, const T* __restrict__ sS) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -84,7 +89,7 @@ __device__ inline void for_acc(typename Mfma<T>::acc_t (&acc)[2][2], F f) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int i = iw + bi * 16 + (lane & 15);
-        int j = jw + bj * 16 + 4 * (lane >> 4) + v;
+        int j = jw + bj * 16 + Mfma<T>::row(lane >> 4, v);
         f(i, j, acc[bi][bj][v]);
       }
 }
