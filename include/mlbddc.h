@@ -140,6 +140,11 @@ int64_t mlbddc_interface_size(mlbddc_t h);
 int64_t mlbddc_coarse_size(mlbddc_t h, int32_t level);
 int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level);
 
+/* Local sizes of the level-`level` subdomains after setup: out[3*i + 0..2] =
+ * {interior DOFs, interface DOFs, constraints} of subdomain i (host
+ * [3 * num_subdomains(level)]).  Used to count algorithmic bytes and flops. */
+mlbddc_status mlbddc_subdomain_sizes(mlbddc_t h, int32_t level, int64_t* out);
+
 /* z^ = M_BDDC r^ (one application of Algorithm 2) on the level-1 interface.
  * r_dev, z_dev: device FP64 [interface_size].  Asynchronous.  E_STATE before setup. */
 mlbddc_status mlbddc_apply(mlbddc_t h, const double* r_dev, double* z_dev);
@@ -169,6 +174,31 @@ mlbddc_status mlbddc_element_energy(mlbddc_t h, const double* a_dev, const doubl
 /* Copy a level's coarse matrix K_C (dense, row-major, coarse_size^2 FP64)
  * to host memory; for tests. */
 mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* host_out);
+
+/* Kernel-level profiling of the set-up factorizations (for rooflines).
+ * When enabled, HIP events are recorded on the handle's stream around every
+ * factorization launch; mlbddc_get_profile returns, per kernel class, the
+ * accumulated device time, the number of launches and the algorithmic
+ * flops of the tiles those launches processed (dense tile counts: a tile
+ * update with k inner tile columns is 2*64^3*k flops, a diagonal tile
+ * 64^3/3 for the factor plus 64^3/3 for its inverse).  Enabling resets the
+ * counters. */
+enum {
+  MLBDDC_PROF_UPDATE_FP64 = 0,  /* trailing / in-panel tile updates, FP64 MFMA */
+  MLBDDC_PROF_UPDATE_FP32 = 1,  /* trailing / in-panel tile updates, FP32 MFMA */
+  MLBDDC_PROF_PANEL = 2,        /* panel solves with inverted diagonal tiles */
+  MLBDDC_PROF_DIAG = 3,         /* diagonal tile factor + inverse */
+  MLBDDC_PROF_NEGATE = 4,       /* sign flips between elimination phases */
+  MLBDDC_PROF_N = 8
+};
+typedef struct {
+  double time_s[MLBDDC_PROF_N];
+  double flops[MLBDDC_PROF_N];
+  int64_t launches[MLBDDC_PROF_N];
+  int64_t tiles[MLBDDC_PROF_N];   /* tile tasks processed */
+} mlbddc_profile;
+mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable);
+mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out);
 
 /* Release all device and host memory of the handle. */
 mlbddc_status mlbddc_destroy(mlbddc_t h);

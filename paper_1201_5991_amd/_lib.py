@@ -29,7 +29,10 @@ EXPORTED = [
     "mlbddc_num_subdomains", "mlbddc_apply", "mlbddc_apply_schur", "mlbddc_condense", "mlbddc_solve",
     "mlbddc_element_energy", "mlbddc_get_coarse_matrix", "mlbddc_destroy", "mlbddc_last_error",
     "mlbddc_element_matrix", "mlbddc_element_load", "mlbddc_plan_counts", "mlbddc_plan_interface",
+    "mlbddc_set_profiling", "mlbddc_get_profile", "mlbddc_subdomain_sizes",
 ]
+PROF_N = 8
+PROF_NAMES = ["update_fp64", "update_fp32", "panel", "diag", "negate"]
 
 
 class Options(C.Structure):
@@ -56,6 +59,15 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Profile(C.Structure):
+    _fields_ = [("time_s", C.c_double * 8), ("flops", C.c_double * 8), ("launches", C.c_int64 * 8),
+                ("tiles", C.c_int64 * 8)]
+
+    def as_dict(self):
+        return {n: {"time_s": self.time_s[i], "flops": self.flops[i], "launches": self.launches[i],
+                    "tiles": self.tiles[i]} for i, n in enumerate(PROF_NAMES)}
 
 
 class ErrorInfo(C.Structure):
@@ -108,6 +120,9 @@ def load():
         "mlbddc_element_load": (I32, [I32, D, P(D), P(D)]),
         "mlbddc_plan_counts": (I32, [P(Mesh), P(Partition), P(I64)]),
         "mlbddc_plan_interface": (I32, [P(Mesh), P(Partition), P(I64), I32, P(I64), P(I64)]),
+        "mlbddc_set_profiling": (I32, [VP, I32]),
+        "mlbddc_get_profile": (I32, [VP, P(Profile)]),
+        "mlbddc_subdomain_sizes": (I32, [VP, I32, P(I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -349,8 +349,10 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   int maxk = 0;
   for (auto& it : items) maxk = std::max(maxk, it.e1 + it.e2);
   std::vector<uint64_t> lists[5];
+  double lflops[5];
   for (int k = 0; k < maxk; ++k) {
     for (auto& l : lists) l.clear();
+    for (double& f : lflops) f = 0.0;
     for (size_t b = 0; b < items.size(); ++b) {
       const FactorItemDesc& it = items[b];
       const int e1 = it.e1, e2 = it.e2, nt = it.nt;
@@ -366,14 +368,14 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
         for (int r = k; r < nt; ++r)
           if (std::max(env[r], env[k]) <= k - 1) {
             lists[L_INPANEL].push_back(pack_task(b, r, k, k0));
-            out.flops += 2.0 * t3 * (k - k0);
+            lflops[L_INPANEL] += 2.0 * t3 * (k - k0);
           }
       lists[L_DIAG].push_back(pack_task(b, k, k, 0));
-      out.flops += t3 / 3.0;
+      lflops[L_DIAG] += 2.0 * t3 / 3.0;
       for (int r = k + 1; r < nt; ++r)
         if (env[r] <= k) {
           lists[L_PANEL].push_back(pack_task(b, r, k, 0));
-          out.flops += t3;
+          lflops[L_PANEL] += 2.0 * t3;
         }
       if (k == kend - 1)
         for (int s = k + 1; s < nt; ++s) {
@@ -381,13 +383,14 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
           for (int r = s; r < nt; ++r)
             if (env[r] <= k) {
               lists[L_TRAIL].push_back(pack_task(b, r, s, k0));
-              out.flops += (r == s ? 1.0 : 2.0) * t3 * (k - k0 + 1);
+              lflops[L_TRAIL] += 2.0 * t3 * (k - k0 + 1);
             }
         }
     }
     for (int kind = 0; kind < 5; ++kind) {
       if (lists[kind].empty()) continue;
-      FactorLaunch L{kind, k, (int64_t)out.tasks.size(), (int64_t)lists[kind].size()};
+      FactorLaunch L{kind, k, (int64_t)out.tasks.size(), (int64_t)lists[kind].size(), lflops[kind]};
+      out.flops += lflops[kind];
       if (kind == L_TRAIL || kind == L_INPANEL) out.update_tasks += L.count;
       out.tasks.insert(out.tasks.end(), lists[kind].begin(), lists[kind].end());
       out.launches.push_back(L);

@@ -107,6 +107,7 @@ struct FactorLaunch {
   int kind;
   int k;                                // global tile column of this step
   int64_t first, count;                 // task range
+  double flops;                         // algorithmic flops of the launch's tasks
 };
 
 struct FactorSchedule {

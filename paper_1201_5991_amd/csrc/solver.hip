@@ -175,6 +175,10 @@ struct Handle {
   int32_t max_hist = 0;
   double t_plan = 0, t_setup = 0;
   double flops_K = 0, flops_M = 0;
+  // profiling
+  bool prof = false;
+  mlbddc_profile pdata{};
+  std::vector<hipEvent_t> events;
 
   mlbddc_status herr(const char* what, hipError_t e) {
     err.status = MLBDDC_E_HIP;
@@ -215,6 +219,8 @@ struct Handle {
     return MLBDDC_OK;
   }
   void free_all() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     if (h_s) (void)hipHostFree(h_s);
@@ -307,16 +313,41 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
 mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
   FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err};
-  for (const FactorLaunch& L : J.sched.launches) {
+  const size_t nl = J.sched.launches.size();
+  if (prof)
+    while (events.size() < 2 * nl) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreate(&ev));
+      events.push_back(ev);
+    }
+  for (size_t i = 0; i < nl; ++i) {
+    const FactorLaunch& L = J.sched.launches[i];
+    if (prof) HIPCHK(hipEventRecord(events[2 * i], stream));
     if (J.fp32)
       launch_factor_step<float>(stream, L.kind, L.k, a, L.first, L.count, (float*)J.buf, (float*)J.inv);
     else
       launch_factor_step<double>(stream, L.kind, L.k, a, L.first, L.count, (double*)J.buf, (double*)J.inv);
+    if (prof) HIPCHK(hipEventRecord(events[2 * i + 1], stream));
   }
   HIPCHK(hipGetLastError());
   int32_t e[2];
   HIPCHK(hipMemcpyAsync(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
+  if (prof) {
+    for (size_t i = 0; i < nl; ++i) {
+      const FactorLaunch& L = J.sched.launches[i];
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, events[2 * i], events[2 * i + 1]));
+      int c = MLBDDC_PROF_NEGATE;
+      if (L.kind == L_TRAIL || L.kind == L_INPANEL) c = J.fp32 ? MLBDDC_PROF_UPDATE_FP32 : MLBDDC_PROF_UPDATE_FP64;
+      else if (L.kind == L_PANEL) c = MLBDDC_PROF_PANEL;
+      else if (L.kind == L_DIAG) c = MLBDDC_PROF_DIAG;
+      pdata.time_s[c] += 1e-3 * ms;
+      pdata.flops[c] += L.flops;
+      pdata.launches[c] += 1;
+      pdata.tiles[c] += L.count;
+    }
+  }
   if (e[0] != 0) {
     int sub = e[0] - 1;
     if (precond)
@@ -1214,6 +1245,19 @@ int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level) {
   return h->h.plan.levels[level - 1].n_sub;
 }
 
+mlbddc_status mlbddc_subdomain_sizes(mlbddc_t h, int32_t level, int64_t* out) {
+  if (!h || !out) return MLBDDC_E_ARG;
+  if (!h->h.planned) return h->h.fail(MLBDDC_E_STATE, "subdomain_sizes before setup");
+  if (level < 1 || level > (int32_t)h->h.plan.levels.size()) return h->h.fail(MLBDDC_E_ARG, "bad level");
+  const auto& L = h->h.plan.levels[level - 1];
+  for (int b = 0; b < L.n_sub; ++b) {
+    out[3 * b] = L.subs[b].nI;
+    out[3 * b + 1] = L.subs[b].nG;
+    out[3 * b + 2] = L.subs[b].nc;
+  }
+  return MLBDDC_OK;
+}
+
 mlbddc_status mlbddc_apply(mlbddc_t h, const double* r, double* z) {
   if (!h) return MLBDDC_E_ARG;
   if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "apply before setup");
@@ -1273,6 +1317,19 @@ mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* out) {
     for (int a = 0; a < S.nc; ++a)
       for (int c = 0; c < S.nc; ++c) out[(int64_t)S.coarse[a] * n + S.coarse[c]] += kc[D.kc_off[b] + (int64_t)a * S.nc + c];
   }
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable) {
+  if (!h) return MLBDDC_E_ARG;
+  h->h.prof = enable != 0;
+  h->h.pdata = mlbddc_profile{};
+  return MLBDDC_OK;
+}
+
+mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out) {
+  if (!h || !out) return MLBDDC_E_ARG;
+  *out = h->h.pdata;
   return MLBDDC_OK;
 }
 

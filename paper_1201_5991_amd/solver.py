@@ -208,6 +208,21 @@ class Solver:
                                                  C.c_void_p(out.data_ptr())))
         return out
 
+    def subdomain_sizes(self, level: int) -> np.ndarray:
+        """(interior DOFs, interface DOFs, constraints) of every level-`level` subdomain."""
+        n = self.num_subdomains(level)
+        out = np.zeros((n, 3), dtype=np.int64)
+        self._chk(self.lib.mlbddc_subdomain_sizes(self.h, level, _ptr(out, C.c_int64)))
+        return out
+
+    def set_profiling(self, enable: bool = True):
+        self._chk(self.lib.mlbddc_set_profiling(self.h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        p = L.Profile()
+        self._chk(self.lib.mlbddc_get_profile(self.h, C.byref(p)))
+        return p.as_dict()
+
     def coarse_matrix(self, level: int) -> np.ndarray:
         n = self.coarse_size(level)
         out = np.zeros((n, n))
