@@ -64,10 +64,10 @@ def algorithmic_apply_bytes(s, precision: str) -> dict:
     return {"apply": total, "schur": schur}
 
 
-def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int):
+def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0):
     import torch
     from paper_1201_5991_amd import Solver
-    s = Solver(precision=precision)
+    s = Solver(precision=precision, panel_tiles=panel)
     for _ in range(warmup):
         s.setup(prob)
         s.solve(f)
@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--applies", type=int, default=100)
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--panel", type=int, default=0, help="tile columns per factorization panel (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -198,7 +199,7 @@ def main():
     modes = args.modes.split(",")
     out = {}
     for m in modes:
-        out[m] = run_mode(prob, f, m, args.steps, args.warmup, args.applies)
+        out[m] = run_mode(prob, f, m, args.steps, args.warmup, args.applies, args.panel)
     main_mode = "mixed" if "mixed" in out else modes[0]
     R = out[main_mode]
     # dominant kernel of the timed path: the largest device-time class of the set-up profile

@@ -125,12 +125,18 @@ __global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A) {
 }
 
 // ------------------------------------------------------------ factorization
+// Diagonal tile: Cholesky factor and inverse of the lower factor.
+// Factor: right-looking in LDS; per column one pivot/scale pass and one
+// rank-1 update of the trailing columns, whose 16 per-thread read-modify-
+// writes are independent (unrolled).  Inverse W = L^{-1}: four neighbouring
+// lanes own one column c of W (lane p keeps W(p+4m, c), m = 0..15, in
+// registers); W(i, c) = (delta_ic - sum_{q<i} L(i, q) W(q, c)) / L(i, i) with
+// the sum split over the four lanes and combined by two shuffles.
 template <typename T>
 __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
-  __shared__ T sW[TS * LDT];
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
   const int nt = ntv[item];
@@ -138,43 +144,65 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
   const int tid = threadIdx.x;
   stage_tile<T, T>(sA, g, false);
   __syncthreads();
+  bool bad = false;
+  int badcol = 0;
+  const int i = tid & (TS - 1), l0 = tid >> 6;
   for (int j = 0; j < TS; ++j) {
-    if (tid == 0) {
+    if (tid < TS) {
       T d = sA[j * LDT + j];
       if (!(d > (T)0)) {
-        if (atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + j;
+        if (!bad) badcol = j;
+        bad = true;
         d = (T)NAN;
       }
-      sA[j * LDT + j] = sqrt(d);
+      const T sq = sqrt(d);
+      if (tid > j) sA[j * LDT + tid] /= sq;
+      __builtin_amdgcn_wave_barrier();
+      if (tid == j) sA[j * LDT + j] = sq;
     }
     __syncthreads();
-    if (tid > j && tid < TS) sA[j * LDT + tid] /= sA[j * LDT + j];
-    __syncthreads();
-    for (int idx = tid; idx < TE; idx += blockDim.x) {
-      int i = idx & (TS - 1), l = idx >> 6;
-      if (l > j && i >= l) sA[l * LDT + i] -= sA[j * LDT + i] * sA[j * LDT + l];
+    const T lij = sA[j * LDT + i];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int l = l0 + 4 * m;
+      if (l > j && i >= l) sA[l * LDT + i] -= lij * sA[j * LDT + l];
     }
     __syncthreads();
   }
-  // inverse of the lower factor, column by column (one lane per column)
-  if (tid < TS) {
-    const int c = tid;
-    for (int i = 0; i < TS; ++i) sW[c * LDT + i] = (T)0;
-    sW[c * LDT + c] = (T)1 / sA[c * LDT + c];
-    for (int i = 1; i < TS; ++i) {
-      T s = 0;
-      for (int kk = 0; kk < i; ++kk)
-        if (kk >= c) s += sA[kk * LDT + i] * sW[c * LDT + kk];
-      if (i > c) sW[c * LDT + i] = -s / sA[i * LDT + i];
-    }
+  if (bad && tid == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
+  // zero the upper triangle and write L back
+  for (int idx = tid; idx < TE; idx += blockDim.x) {
+    const int r = idx & (TS - 1), c = idx >> 6;
+    if (r < c) sA[c * LDT + r] = (T)0;
   }
   __syncthreads();
-  T* gi = Inv + inv_off[item] + (int64_t)k * TE;
-  for (int idx = tid; idx < TE; idx += blockDim.x) {
-    int i = idx & (TS - 1), j = idx >> 6;
-    g[idx] = i >= j ? sA[j * LDT + i] : (T)0;
-    gi[idx] = sW[j * LDT + i];
+  for (int idx = tid; idx < TE; idx += blockDim.x) g[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
+  // inverse
+  const int c = tid >> 2, p = tid & 3;
+  T w[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) w[m] = (T)0;
+  for (int r = 0; r < TS; ++r) {
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int q = p + 4 * m;
+      if (q < r) s += sA[q * LDT + r] * w[m];
+    }
+    s += __shfl_xor(s, 1, 4);
+    s += __shfl_xor(s, 2, 4);
+    const T v = ((r == c ? (T)1 : (T)0) - s) / sA[r * LDT + r];
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (p + 4 * m == r) w[m] = v;
   }
+  __syncthreads();
+  // stage W column-major through LDS for a coalesced store
+#pragma unroll
+  for (int m = 0; m < 16; ++m) sA[c * LDT + p + 4 * m] = w[m];
+  __syncthreads();
+  T* gi = Inv + inv_off[item] + (int64_t)k * TE;
+  for (int idx = tid; idx < TE; idx += blockDim.x) gi[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
 }
 
 template <typename T>
