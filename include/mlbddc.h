@@ -61,7 +61,7 @@ typedef struct {
   int32_t max_iter;    /* default 1000 */
   int32_t weights;     /* MLBDDC_W_* */
   int32_t use_graph;   /* capture one PCG iteration as a HIP graph (1) or launch eagerly (0) */
-  int32_t panel_tiles; /* tile columns per factorization panel (0 = autotuned) */
+  int32_t panel_tiles; /* tile columns per factorization panel (0 = default, 4) */
   int32_t device;      /* HIP device ordinal */
 } mlbddc_options;
 

@@ -150,65 +150,91 @@ __global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* 
 }
 
 // ------------------------------------------------------------------ trsv
-// (L v)_tile products inside one workgroup: out[a] -= sum_b L(a, b) v[b]
-__device__ inline void tile_mv_lds(const double* __restrict__ L, const double* __restrict__ v, double* __restrict__ red,
-                                   bool trans) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  double acc = 0.0;
-  if (!trans) {
-    for (int b = w * 16; b < w * 16 + 16; ++b) acc += L[b * TS + lane] * v[b];
-    red[w * TS + lane] = acc;
-  } else {
-    // out[b] = sum_a L(a, b) v[a]: wave w handles b = w*16 .. +16, lane = a
-    for (int b = w * 16; b < w * 16 + 16; ++b) {
-      double p = L[b * TS + lane] * v[lane];
-      for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
-      if (lane == 0) red[b] = p;
-    }
+// Blocked triangular solve with the interior factor of one subdomain per
+// workgroup.  Block row k: the four wavefronts split the envelope tiles of
+// the row (tile s goes to wave s mod 4); lane a accumulates entry a of
+// sum_s L_ks v_s (or, transposed, entry b of sum_r L_rk^T u_r from a tile
+// staged in the wave's own LDS slot so that global loads stay coalesced);
+// wavefront 0 then applies the stored inverse of the diagonal tile.
+constexpr int LDV = TS + 1;
+
+__device__ inline double tile_dot_col(const double* __restrict__ L, const double* __restrict__ v, int lane) {
+  // sum_b L(lane, b) v[b] (L column-major in global memory, v broadcast from LDS)
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 4
+  for (int b = 0; b < TS; b += 4) {
+    a0 += L[(b + 0) * TS + lane] * v[b + 0];
+    a1 += L[(b + 1) * TS + lane] * v[b + 1];
+    a2 += L[(b + 2) * TS + lane] * v[b + 2];
+    a3 += L[(b + 3) * TS + lane] * v[b + 3];
   }
+  return (a0 + a1) + (a2 + a3);
+}
+
+__device__ inline double tile_dot_row_lds(const double* __restrict__ sT, const double* __restrict__ v, int lane) {
+  // sum_a T(a, lane) v[a] with T staged column-major in LDS (leading dimension LDV)
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 4
+  for (int q = 0; q < TS; q += 4) {
+    a0 += sT[lane * LDV + q + 0] * v[q + 0];
+    a1 += sT[lane * LDV + q + 1] * v[q + 1];
+    a2 += sT[lane * LDV + q + 2] * v[q + 2];
+    a3 += sT[lane * LDV + q + 3] * v[q + 3];
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
+__device__ inline void stage_wave(double* __restrict__ sT, const double* __restrict__ g, int lane) {
+#pragma unroll 8
+  for (int b = 0; b < TS; ++b) sT[b * LDV + lane] = g[b * TS + lane];
 }
 
 __global__ void __launch_bounds__(256) k_trsv(int trans, const TrsvDesc* __restrict__ d, const double* __restrict__ A,
                                               const double* __restrict__ Inv, double* v) {
   const TrsvDesc D = d[blockIdx.x];
-  __shared__ double acc[TS], sv[TS], red[4 * TS];
-  const int t = threadIdx.x;
+  __shared__ double sT[4][TS * LDV];
+  __shared__ double sv[4][TS];
+  __shared__ double red[4][TS];
+  __shared__ double acc[TS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const double* base = A + D.a_off;
   double* vv = v + D.v_off;
   for (int step = 0; step < D.nti; ++step) {
     const int k = trans ? D.nti - 1 - step : step;
-    if (t < TS) acc[t] = vv[(int64_t)k * TS + t];
-    __syncthreads();
+    double part = 0.0;
     if (!trans) {
-      for (int s = D.env ? D.env[k] : 0; s < k; ++s) {
-        if (t < TS) sv[t] = vv[(int64_t)s * TS + t];
-        __syncthreads();
-        tile_mv_lds(base + tile_index(k, s, D.a_nt) * TE, sv, red, false);
-        __syncthreads();
-        if (t < TS) acc[t] -= red[t] + red[TS + t] + red[2 * TS + t] + red[3 * TS + t];
-        __syncthreads();
+      const int s0 = D.env ? D.env[k] : 0;
+      for (int s = s0 + w; s < k; s += 4) {
+        sv[w][lane] = vv[(int64_t)s * TS + lane];
+        __builtin_amdgcn_wave_barrier();
+        part += tile_dot_col(base + tile_index(k, s, D.a_nt) * TE, sv[w], lane);
+        __builtin_amdgcn_wave_barrier();
       }
     } else {
-      for (int r = k + 1; r < D.nti; ++r) {
+      for (int r = k + 1 + w; r < D.nti; r += 4) {
         if (D.env && D.env[r] > k) continue;
-        if (t < TS) sv[t] = vv[(int64_t)r * TS + t];
-        __syncthreads();
-        tile_mv_lds(base + tile_index(r, k, D.a_nt) * TE, sv, red, true);
-        __syncthreads();
-        if (t < TS) acc[t] -= red[t];
-        __syncthreads();
+        sv[w][lane] = vv[(int64_t)r * TS + lane];
+        stage_wave(sT[w], base + tile_index(r, k, D.a_nt) * TE, lane);
+        __builtin_amdgcn_wave_barrier();
+        part += tile_dot_row_lds(sT[w], sv[w], lane);
+        __builtin_amdgcn_wave_barrier();
       }
     }
-    // v_k = W acc (or W^T acc) with the stored inverse diagonal tile
-    const double* W = Inv + D.inv_off + (int64_t)k * TE;
-    if (!trans) {
-      tile_mv_lds(W, acc, red, false);
-      __syncthreads();
-      if (t < TS) vv[(int64_t)k * TS + t] = red[t] + red[TS + t] + red[2 * TS + t] + red[3 * TS + t];
-    } else {
-      tile_mv_lds(W, acc, red, true);
-      __syncthreads();
-      if (t < TS) vv[(int64_t)k * TS + t] = red[t];
+    red[w][lane] = part;
+    __syncthreads();
+    if (w == 0) {
+      acc[lane] = vv[(int64_t)k * TS + lane] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+      __builtin_amdgcn_wave_barrier();
+      const double* W = Inv + D.inv_off + (int64_t)k * TE;
+      double x;
+      if (!trans) {
+        x = tile_dot_col(W, acc, lane);
+      } else {
+        stage_wave(sT[0], W, lane);
+        __builtin_amdgcn_wave_barrier();
+        x = tile_dot_row_lds(sT[0], acc, lane);
+      }
+      vv[(int64_t)k * TS + lane] = x;
     }
     __syncthreads();
   }

@@ -125,79 +125,106 @@ __global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A) {
 }
 
 // ------------------------------------------------------------ factorization
+// Exchange within groups of four lanes through DPP (quad permutations).
+template <int CTRL>
+__device__ inline double quad_perm(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ inline float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int DPP_XOR1 = 0xB1;  // quad_perm(1, 0, 3, 2)
+constexpr int DPP_XOR2 = 0x4E;  // quad_perm(2, 3, 0, 1)
+
 // Diagonal tile: Cholesky factor and inverse of the lower factor.
-// Factor: right-looking in LDS; per column one pivot/scale pass and one
-// rank-1 update of the trailing columns, whose 16 per-thread read-modify-
-// writes are independent (unrolled).  Inverse W = L^{-1}: four neighbouring
-// lanes own one column c of W (lane p keeps W(p+4m, c), m = 0..15, in
-// registers); W(i, c) = (delta_ic - sum_{q<i} L(i, q) W(q, c)) / L(i, i) with
-// the sum split over the four lanes and combined by two shuffles.
+// Factor: wavefront 0, lane i keeps row i in registers; per column j the pivot
+// and then the new column of L are broadcast through LDS (reads issued
+// unconditionally, so they pipeline), and the right-looking update touches
+// registers only.  Entries right of a lane's diagonal are left as they are
+// and ignored.  Inverse W = L^{-1}: four neighbouring lanes own column c of W
+// (lane p keeps W(p+4m, c)); W(r, c) = (delta_rc - sum_{q<r} L(r, q) W(q, c)) /
+// L(r, r).  Entries of W not yet computed are zero, so the sum runs over all
+// of the lane's entries without predicates; the four partial sums are combined
+// with DPP quad permutations.
 template <typename T>
 __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
+  __shared__ T col[TS];
+  __shared__ T piv[2];
+  __shared__ T dinv[TS];
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
   const int nt = ntv[item];
   T* g = A + off[item] + tile_index(k, k, nt) * TE;
   const int tid = threadIdx.x;
-  stage_tile<T, T>(sA, g, false);
-  __syncthreads();
-  bool bad = false;
-  int badcol = 0;
-  const int i = tid & (TS - 1), l0 = tid >> 6;
-  for (int j = 0; j < TS; ++j) {
-    if (tid < TS) {
-      T d = sA[j * LDT + j];
+  if (tid < TS) {
+    const int lane = tid;
+    T a[TS];
+#pragma unroll
+    for (int c = 0; c < TS; ++c) a[c] = g[c * TS + lane];
+    bool bad = false;
+    int badcol = 0;
+    for (int j = 0; j < TS; ++j) {
+      T x = 0;
+#pragma unroll
+      for (int c = 0; c < TS; ++c) x = (c == j) ? a[c] : x;   // a[j] without a dynamic register index
+      if (lane == j) piv[0] = x;
+      __builtin_amdgcn_wave_barrier();
+      T d = piv[0];
       if (!(d > (T)0)) {
         if (!bad) badcol = j;
         bad = true;
         d = (T)NAN;
       }
       const T sq = sqrt(d);
-      if (tid > j) sA[j * LDT + tid] /= sq;
+      const T lij = lane > j ? x / sq : (lane == j ? sq : (T)0);
+      col[lane] = lij;
       __builtin_amdgcn_wave_barrier();
-      if (tid == j) sA[j * LDT + j] = sq;
-    }
-    __syncthreads();
-    const T lij = sA[j * LDT + i];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int l = l0 + 4 * m;
-      if (l > j && i >= l) sA[l * LDT + i] -= lij * sA[j * LDT + l];
+      for (int c = 0; c < TS; ++c) {
+        const T u = a[c] - lij * col[c];
+        a[c] = c > j ? u : (c == j ? lij : a[c]);
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-  }
-  if (bad && tid == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
-  // zero the upper triangle and write L back
-  for (int idx = tid; idx < TE; idx += blockDim.x) {
-    const int r = idx & (TS - 1), c = idx >> 6;
-    if (r < c) sA[c * LDT + r] = (T)0;
+    if (bad && lane == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const T v = c <= lane ? a[c] : (T)0;
+      sA[c * LDT + lane] = v;
+      g[c * TS + lane] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    dinv[lane] = (T)1 / sA[lane * LDT + lane];
   }
   __syncthreads();
-  for (int idx = tid; idx < TE; idx += blockDim.x) g[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
   // inverse
   const int c = tid >> 2, p = tid & 3;
   T w[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) w[m] = (T)0;
   for (int r = 0; r < TS; ++r) {
-    T s = 0;
+    T s0 = 0, s1 = 0;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int q = p + 4 * m;
-      if (q < r) s += sA[q * LDT + r] * w[m];
+    for (int m = 0; m < 16; m += 2) {
+      s0 += sA[(p + 4 * m) * LDT + r] * w[m];
+      s1 += sA[(p + 4 * m + 4) * LDT + r] * w[m + 1];
     }
-    s += __shfl_xor(s, 1, 4);
-    s += __shfl_xor(s, 2, 4);
-    const T v = ((r == c ? (T)1 : (T)0) - s) / sA[r * LDT + r];
+    T s = s0 + s1;
+    s += quad_perm<DPP_XOR1>(s);
+    s += quad_perm<DPP_XOR2>(s);
+    const T v = ((r == c ? (T)1 : (T)0) - s) * dinv[r];
 #pragma unroll
     for (int m = 0; m < 16; ++m)
       if (p + 4 * m == r) w[m] = v;
   }
   __syncthreads();
-  // stage W column-major through LDS for a coalesced store
 #pragma unroll
   for (int m = 0; m < 16; ++m) sA[c * LDT + p + 4 * m] = w[m];
   __syncthreads();
@@ -225,27 +252,102 @@ __global__ void __launch_bounds__(256) k_panel(const uint64_t* __restrict__ task
   for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = v; });
 }
 
+// Register staging of one 64x64 tile: each of the 256 threads holds 16
+// elements as 16-byte vectors (coalesced loads), then stores them to LDS.
+template <typename T>
+struct TileRegs {
+  static constexpr int V = 16 / sizeof(T);          // elements per 16-byte vector
+  static constexpr int N = TE / (256 * V);          // vectors per thread
+  typedef T vec __attribute__((ext_vector_type(V)));
+  vec v[N];
+  __device__ void load(const T* __restrict__ g) {
+    const vec* gv = reinterpret_cast<const vec*>(g);
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = gv[threadIdx.x + 256 * m];
+  }
+  template <int LD>
+  __device__ void store(T* __restrict__ s) const {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int e = (threadIdx.x + 256 * m) * V;     // first element: row e%64, column e/64
+      const int i = e & (TS - 1), j = e >> 6;
+#pragma unroll
+      for (int q = 0; q < V; ++q) s[j * LD + i + q] = v[m][q];
+    }
+  }
+};
+
+// acc(i, j) += sum_k R(i, k) S(j, k) from LDS tiles with leading dimension LD.
+template <typename T, int LD>
+__device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T* __restrict__ sR, const T* __restrict__ sS) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
+  const int l16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < TS; k0 += 4) {
+    const int kk = k0 + kq;
+    T a[2], b[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) a[bj] = sS[kk * LD + jw + bj * 16 + l16];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) b[bi] = sR[kk * LD + iw + bi * 16 + l16];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::mac(a[bj], b[bi], acc[bi][bj]);
+  }
+}
+
+constexpr int LDU = TS + 16;  // keeps the four k-groups of a fragment read on distinct LDS banks
+
+// A_rs <- A_rs - sum_{kk=kf..klast} A_{r,kk} A_{s,kk}^T.  The output tile is
+// prefetched into registers at the start; the next pair of k-tiles is loaded
+// into registers while the current pair is multiplied from LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                                 const int32_t* __restrict__ ntv, int klast, T* A) {
-  __shared__ T sR[TS * LDT];
-  __shared__ T sS[TS * LDT];
+  __shared__ T sR[TS * LDU];
+  __shared__ T sS[TS * LDU];
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), r = task_r(t), s = task_s(t), kf = task_kf(t);
   const int nt = ntv[item];
-  const T* base = A + off[item];
+  T* base = A + off[item];
+  T* g = base + tile_index(r, s, nt) * TE;
+  T creg[16];
+  {
+    int n = 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = iw + bi * 16 + (lane & 15), j = jw + bj * 16 + Mfma<T>::row(lane >> 4, v);
+          creg[n++] = g[j * TS + i];
+        }
+  }
   typename Mfma<T>::acc_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
+  TileRegs<T> pr, ps;
+  const bool diag = r == s;
+  pr.load(base + tile_index(r, kf, nt) * TE);
+  if (!diag) ps.load(base + tile_index(s, kf, nt) * TE);
   for (int kk = kf; kk <= klast; ++kk) {
-    stage_tile<T, T>(sR, base + tile_index(r, kk, nt) * TE, false);
-    if (r != s) stage_tile<T, T>(sS, base + tile_index(s, kk, nt) * TE, false);
+    pr.template store<LDU>(sR);
+    if (!diag) ps.template store<LDU>(sS);
     __syncthreads();
-    tile_nt<T>(acc, sR, r != s ? sS : sR);
+    if (kk < klast) {
+      pr.load(base + tile_index(r, kk + 1, nt) * TE);
+      if (!diag) ps.load(base + tile_index(s, kk + 1, nt) * TE);
+    }
+    tile_nt_ld<T, LDU>(acc, sR, diag ? sR : sS);
     __syncthreads();
   }
-  T* g = A + off[item] + tile_index(r, s, nt) * TE;
-  for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] -= v; });
+  int n = 0;
+  for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - v; });
 }
 
 template <typename T>

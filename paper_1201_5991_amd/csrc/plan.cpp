@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <numeric>
 
 namespace mlbddc {
@@ -58,15 +59,23 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     int32_t b = L.el_sub[e];
     if (b < 0 || b >= ns) return fail(err, MLBDDC_E_ARG, "element assigned to a non-existent subdomain");
     L.subs[b].elems.push_back(e);
-    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
-      if (L.el_nodes[j] >= 0) sub_nodes[b].push_back(L.el_nodes[j]);
   }
-  for (int32_t b = 0; b < ns; ++b) {
-    auto& v = sub_nodes[b];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    if (L.subs[b].elems.empty() || v.empty())
-      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " is empty");
+  {
+    std::vector<int32_t> stamp(L.n_nodes, -1);  // last subdomain that listed the node
+    for (int32_t b = 0; b < ns; ++b) {
+      auto& v = sub_nodes[b];
+      for (int64_t e : L.subs[b].elems)
+        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+          int64_t n = L.el_nodes[j];
+          if (n >= 0 && stamp[n] != b) {
+            stamp[n] = b;
+            v.push_back(n);
+          }
+        }
+      std::sort(v.begin(), v.end());
+      if (L.subs[b].elems.empty() || v.empty())
+        return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " is empty");
+    }
   }
 
   // --- node -> subdomains (CSR, sorted by subdomain)
@@ -104,18 +113,29 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
       L.globs.push_back(std::move(g));
     }
   } else {
-    std::map<std::vector<int32_t>, size_t> by_set;
+    // group interface nodes by their subdomain set: hash of the sorted set,
+    // exact comparison on a hash hit
+    std::unordered_map<uint64_t, std::vector<size_t>> by_hash;
+    by_hash.reserve(iface_nodes.size() / 4 + 16);
     for (int64_t n : iface_nodes) {
-      std::vector<int32_t> s(nsub.begin() + nptr[n], nsub.begin() + nptr[n + 1]);
-      auto it = by_set.find(s);
-      if (it == by_set.end()) {
-        by_set.emplace(s, L.globs.size());
+      const int32_t* sb = nsub.data() + nptr[n];
+      const size_t sl = (size_t)(nptr[n + 1] - nptr[n]);
+      uint64_t h = 1469598103934665603ull ^ sl;
+      for (size_t q = 0; q < sl; ++q) h = (h ^ (uint64_t)(uint32_t)sb[q]) * 1099511628211ull;
+      auto& cand = by_hash[h];
+      size_t found = SIZE_MAX;
+      for (size_t gi : cand) {
+        const auto& gs = L.globs[gi].subs;
+        if (gs.size() == sl && std::equal(gs.begin(), gs.end(), sb)) { found = gi; break; }
+      }
+      if (found == SIZE_MAX) {
+        cand.push_back(L.globs.size());
         Glob g;
-        g.subs = s;
+        g.subs.assign(sb, sb + sl);
         g.nodes = {n};
         L.globs.push_back(std::move(g));
       } else {
-        L.globs[it->second].nodes.push_back(n);
+        L.globs[found].nodes.push_back(n);
       }
     }
     for (auto& g : L.globs) g.kind = classify(g.subs.size(), g.nodes.size(), L.dim);

@@ -301,7 +301,7 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
   J.buf = b;
   J.inv = iv;
   (void)esz;
-  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 1, J.sched);
+  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 4, J.sched);
   if ((st = upload(&J.d_off, J.off))) return st;
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
   if ((st = upload(&J.d_nt, J.nt))) return st;
