@@ -155,54 +155,57 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
-  __shared__ T col[TS];
-  __shared__ T piv[2];
   __shared__ T dinv[TS];
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
   const int nt = ntv[item];
   T* g = A + off[item] + tile_index(k, k, nt) * TE;
   const int tid = threadIdx.x;
-  if (tid < TS) {
-    const int lane = tid;
-    T a[TS];
-#pragma unroll
-    for (int c = 0; c < TS; ++c) a[c] = g[c * TS + lane];
-    bool bad = false;
-    int badcol = 0;
+  // factor in LDS: per column one pivot/scale pass (wavefront 0) and one
+  // branch-free rank-1 update (each thread owns 16 entries of the tile)
+  stage_tile<T, T>(sA, g, false);
+  __syncthreads();
+  bool bad = false;
+  int badcol = 0;
+  {
+    const int i = tid & (TS - 1), l0 = tid >> 6;
     for (int j = 0; j < TS; ++j) {
-      T x = 0;
-#pragma unroll
-      for (int c = 0; c < TS; ++c) x = (c == j) ? a[c] : x;   // a[j] without a dynamic register index
-      if (lane == j) piv[0] = x;
-      __builtin_amdgcn_wave_barrier();
-      T d = piv[0];
-      if (!(d > (T)0)) {
-        if (!bad) badcol = j;
-        bad = true;
-        d = (T)NAN;
+      if (tid < TS) {
+        T d = sA[j * LDT + j];
+        if (!(d > (T)0)) {
+          if (!bad) badcol = j;
+          bad = true;
+          d = (T)NAN;
+        }
+        const T sq = sqrt(d);
+        const T v = sA[j * LDT + tid];
+        __builtin_amdgcn_wave_barrier();
+        sA[j * LDT + tid] = tid > j ? v / sq : (tid == j ? sq : v);
       }
-      const T sq = sqrt(d);
-      const T lij = lane > j ? x / sq : (lane == j ? sq : (T)0);
-      col[lane] = lij;
-      __builtin_amdgcn_wave_barrier();
+      __syncthreads();
+      const T lij = sA[j * LDT + i];
+      T lj[16], cur[16];
 #pragma unroll
-      for (int c = 0; c < TS; ++c) {
-        const T u = a[c] - lij * col[c];
-        a[c] = c > j ? u : (c == j ? lij : a[c]);
+      for (int m = 0; m < 16; ++m) {
+        lj[m] = sA[j * LDT + l0 + 4 * m];
+        cur[m] = sA[(l0 + 4 * m) * LDT + i];
       }
-      __builtin_amdgcn_wave_barrier();
-    }
-    if (bad && lane == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
 #pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const T v = c <= lane ? a[c] : (T)0;
-      sA[c * LDT + lane] = v;
-      g[c * TS + lane] = v;
+      for (int m = 0; m < 16; ++m) {
+        const int l = l0 + 4 * m;
+        sA[l * LDT + i] = (l > j && i >= l) ? cur[m] - lij * lj[m] : cur[m];
+      }
+      __syncthreads();
     }
-    __builtin_amdgcn_wave_barrier();
-    dinv[lane] = (T)1 / sA[lane * LDT + lane];
   }
+  if (bad && tid == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
+  for (int idx = tid; idx < TE; idx += blockDim.x) {
+    const int r = idx & (TS - 1), cc = idx >> 6;
+    if (r < cc) sA[cc * LDT + r] = (T)0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < TE; idx += blockDim.x) g[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
+  if (tid < TS) dinv[tid] = (T)1 / sA[tid * LDT + tid];
   __syncthreads();
   // inverse
   const int c = tid >> 2, p = tid & 3;
