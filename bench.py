@@ -64,10 +64,10 @@ def algorithmic_apply_bytes(s, precision: str) -> dict:
     return {"apply": total, "schur": schur}
 
 
-def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0):
+def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0, graph: bool = True):
     import torch
     from paper_1201_5991_amd import Solver
-    s = Solver(precision=precision, panel_tiles=panel)
+    s = Solver(precision=precision, panel_tiles=panel, use_graph=graph)
     for _ in range(warmup):
         s.setup(prob)
         s.solve(f)
@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--panel", type=int, default=0, help="tile columns per factorization panel (0 = library default)")
+    ap.add_argument("--no-graph", action="store_true", help="launch PCG iterations eagerly instead of replaying a HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -199,7 +200,7 @@ def main():
     modes = args.modes.split(",")
     out = {}
     for m in modes:
-        out[m] = run_mode(prob, f, m, args.steps, args.warmup, args.applies, args.panel)
+        out[m] = run_mode(prob, f, m, args.steps, args.warmup, args.applies, args.panel, not args.no_graph)
     main_mode = "mixed" if "mixed" in out else modes[0]
     R = out[main_mode]
     # dominant kernel of the timed path: the largest device-time class of the set-up profile
@@ -228,7 +229,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "dofs": int(prob.n_dofs), "levels": int(prob.n_levels),
                    "subdomains": [int(c[0]) for c in counts], "interface": int(counts[0][1]),
-                   "coarse": [int(c[2]) for c in counts], "value_mode": main_mode},
+                   "coarse": [int(c[2]) for c in counts], "value_mode": main_mode,
+                   "pcg_graph": not args.no_graph},
         "applies_per_s": R["applies_per_s"],
         "roofline": roof,
     }

@@ -269,15 +269,20 @@ __global__ void __launch_bounds__(256) k_dot_final(int nb, const double* __restr
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_pcg_alpha(double* s, double* hist, int it) {
+// The iteration counter lives on the device (so that an iteration can be
+// replayed from a captured graph): alpha_j goes to hist[2j]; beta_j, computed
+// at the start of iteration j+1, to hist[2j+1], after which the counter moves on.
+__global__ void k_pcg_alpha(double* s, double* hist, const int* it) {
   s[S_ALPHA] = s[S_RZ] / s[S_PQ];
-  if (hist) hist[2 * it] = s[S_ALPHA];
+  if (hist) hist[2 * (*it)] = s[S_ALPHA];
 }
-__global__ void k_pcg_beta(double* s, double* hist, int it) {
+__global__ void k_pcg_beta(double* s, double* hist, int* it) {
   s[S_BETA] = s[S_RZNEW] / s[S_RZ];
   s[S_RZ] = s[S_RZNEW];
-  if (hist) hist[2 * it + 1] = s[S_BETA];
+  if (hist) hist[2 * (*it) + 1] = s[S_BETA];
+  *it += 1;
 }
+__global__ void k_set_int(int* p, int v) { *p = v; }
 __global__ void k_pcg_update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                                 const double* __restrict__ q, const double* __restrict__ s) {
   const double a = s[S_ALPHA];
@@ -382,12 +387,13 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, nblocks, partial, out);
 }
 
-void launch_pcg_alpha(hipStream_t st, double* s, double* hist, int it) {
+void launch_pcg_alpha(hipStream_t st, double* s, double* hist, const int* it) {
   hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, st, s, hist, it);
 }
-void launch_pcg_beta(hipStream_t st, double* s, double* hist, int it) {
+void launch_pcg_beta(hipStream_t st, double* s, double* hist, int* it) {
   hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s, hist, it);
 }
+void launch_set_int(hipStream_t st, int* p, int v) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v); }
 void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q, const double* s) {
   hipLaunchKernelGGL(k_pcg_update_xr, dim3(grid_for(n)), dim3(256), 0, st, n, x, r, p, q, s);
 }

@@ -359,7 +359,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
   return MLBDDC_OK;
 }
 
-void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out) {
+void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out, bool lookahead) {
   out.tasks.clear();
   out.launches.clear();
   out.flops = 0.0;
@@ -368,8 +368,9 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   if (panel < 1) panel = 1;
   int maxk = 0;
   for (auto& it : items) maxk = std::max(maxk, it.e1 + it.e2);
-  std::vector<uint64_t> lists[5];
-  double lflops[5];
+  enum { NEG = 0, INP = 1, DIA = 2, PAN = 3, NXT = 4, RST = 5, NL = 6 };
+  std::vector<uint64_t> lists[NL];
+  double lflops[NL];
   for (int k = 0; k < maxk; ++k) {
     for (auto& l : lists) l.clear();
     for (double& f : lflops) f = 0.0;
@@ -383,36 +384,47 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
       int kend = std::min(k0 + panel, ph1);
       if (k == e1 && e2 > 0)
         for (int s = e1; s < nt; ++s)
-          for (int r = s; r < nt; ++r) lists[L_NEGATE].push_back(pack_task(b, r, s, 0));
+          for (int r = s; r < nt; ++r) lists[NEG].push_back(pack_task(b, r, s, 0));
       if (k > k0)
         for (int r = k; r < nt; ++r)
           if (std::max(env[r], env[k]) <= k - 1) {
-            lists[L_INPANEL].push_back(pack_task(b, r, k, k0));
-            lflops[L_INPANEL] += 2.0 * t3 * (k - k0);
+            lists[INP].push_back(pack_task(b, r, k, k0));
+            lflops[INP] += 2.0 * t3 * (k - k0);
           }
-      lists[L_DIAG].push_back(pack_task(b, k, k, 0));
-      lflops[L_DIAG] += 2.0 * t3 / 3.0;
+      lists[DIA].push_back(pack_task(b, k, k, 0));
+      lflops[DIA] += 2.0 * t3 / 3.0;
       for (int r = k + 1; r < nt; ++r)
         if (env[r] <= k) {
-          lists[L_PANEL].push_back(pack_task(b, r, k, 0));
-          lflops[L_PANEL] += 2.0 * t3;
+          lists[PAN].push_back(pack_task(b, r, k, 0));
+          lflops[PAN] += 2.0 * t3;
         }
-      if (k == kend - 1)
+      if (k == kend - 1) {
+        // columns of the next panel of this item (same phase); with look-ahead
+        // they are updated first, on the critical stream
+        int nxt_end = k + 1;
+        if (lookahead && k + 1 < ph1) nxt_end = std::min(k + 1 + panel, ph1);
         for (int s = k + 1; s < nt; ++s) {
           if (env[s] > k) continue;
+          const int dst = (!lookahead || s < nxt_end) ? NXT : RST;
           for (int r = s; r < nt; ++r)
             if (env[r] <= k) {
-              lists[L_TRAIL].push_back(pack_task(b, r, s, k0));
-              lflops[L_TRAIL] += 2.0 * t3 * (k - k0 + 1);
+              lists[dst].push_back(pack_task(b, r, s, k0));
+              lflops[dst] += 2.0 * t3 * (k - k0 + 1);
             }
         }
+      }
     }
-    for (int kind = 0; kind < 5; ++kind) {
-      if (lists[kind].empty()) continue;
-      FactorLaunch L{kind, k, (int64_t)out.tasks.size(), (int64_t)lists[kind].size(), lflops[kind]};
-      out.flops += lflops[kind];
-      if (kind == L_TRAIL || kind == L_INPANEL) out.update_tasks += L.count;
-      out.tasks.insert(out.tasks.end(), lists[kind].begin(), lists[kind].end());
+    static const int kind_of[NL] = {L_NEGATE, L_INPANEL, L_DIAG, L_PANEL, L_TRAIL, L_TRAIL};
+    for (int l = 0; l < NL; ++l) {
+      if (lists[l].empty()) continue;
+      FactorLaunch L{kind_of[l], k, (int64_t)out.tasks.size(), (int64_t)lists[l].size(), lflops[l], 0, false};
+      if (lookahead) {
+        if (l == RST) { L.stream = 1; L.wait = true; }      // after the panel and the next-panel update
+        if (l == NXT || l == NEG) L.wait = true;            // after the previous bulk update
+      }
+      if (L.kind == L_TRAIL || L.kind == L_INPANEL) out.update_tasks += L.count;
+      out.flops += lflops[l];
+      out.tasks.insert(out.tasks.end(), lists[l].begin(), lists[l].end());
       out.launches.push_back(L);
     }
   }

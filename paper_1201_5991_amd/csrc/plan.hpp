@@ -108,6 +108,8 @@ struct FactorLaunch {
   int k;                                // global tile column of this step
   int64_t first, count;                 // task range
   double flops;                         // algorithmic flops of the launch's tasks
+  int stream;                           // 0: critical path, 1: bulk trailing updates (look-ahead)
+  bool wait;                            // wait for the other stream's work issued so far
 };
 
 struct FactorSchedule {
@@ -117,6 +119,10 @@ struct FactorSchedule {
   int64_t update_tasks = 0;
 };
 
-void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out);
+// panel: tile columns per panel.  lookahead: split each trailing update into
+// the next panel's columns (stream 0) and the rest (stream 1), so that the
+// next panel's factorization overlaps the bulk of the update.
+void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out,
+                           bool lookahead = false);
 
 }  // namespace mlbddc

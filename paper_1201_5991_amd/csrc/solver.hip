@@ -172,6 +172,14 @@ struct Handle {
   double* d_hist = nullptr;        // alpha/beta history
   double* d_dotp = nullptr;
   double* h_s = nullptr;           // pinned mirror of the scalars
+  int32_t* d_it = nullptr;         // device iteration counter
+  // HIP graph of one PCG iteration (captured on an internal stream)
+  hipStream_t cap = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  // second stream for the look-ahead factorization schedule
+  hipStream_t fstream = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
   int32_t max_hist = 0;
   double t_plan = 0, t_setup = 0;
   double flops_K = 0, flops_M = 0;
@@ -219,6 +227,8 @@ struct Handle {
     return MLBDDC_OK;
   }
   void free_all() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
     for (void* p : allocs) (void)hipFree(p);
@@ -236,6 +246,7 @@ struct Handle {
   mlbddc_status setup(const mlbddc_mesh* mesh, const mlbddc_partition* part);
   mlbddc_status validate();
   mlbddc_status numeric();
+  bool lookahead = true;
   mlbddc_status prepare_job(Job& J, bool fp32);
   mlbddc_status factor(Job& J, int level, bool precond);
   mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
@@ -247,6 +258,8 @@ struct Handle {
   mlbddc_status condense(const double* f, double* g);
   mlbddc_status recover(const double* uhat, double* u);
   mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
+  mlbddc_status pcg_body(bool first);
+  mlbddc_status solve_on_stream(const double* f, double* u, const double* u0, mlbddc_stats* st);
 };
 
 // ----------------------------------------------------------------- helpers
@@ -301,7 +314,7 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
   J.buf = b;
   J.inv = iv;
   (void)esz;
-  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 4, J.sched);
+  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 4, J.sched, lookahead);
   if ((st = upload(&J.d_off, J.off))) return st;
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
   if ((st = upload(&J.d_nt, J.nt))) return st;
@@ -320,14 +333,36 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
       HIPCHK(hipEventCreate(&ev));
       events.push_back(ev);
     }
+  bool two = false;
+  for (const FactorLaunch& L : J.sched.launches) two = two || L.stream == 1;
+  if (two && !fstream) {
+    HIPCHK(hipStreamCreateWithFlags(&fstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
+  }
+  if (two) {  // the second stream starts after everything queued so far
+    HIPCHK(hipEventRecord(ev_a, stream));
+    HIPCHK(hipStreamWaitEvent(fstream, ev_a, 0));
+  }
   for (size_t i = 0; i < nl; ++i) {
     const FactorLaunch& L = J.sched.launches[i];
-    if (prof) HIPCHK(hipEventRecord(events[2 * i], stream));
+    hipStream_t s0 = L.stream == 1 ? fstream : stream;
+    if (L.wait && two) {
+      hipStream_t other = L.stream == 1 ? stream : fstream;
+      hipEvent_t ev = L.stream == 1 ? ev_a : ev_b;
+      HIPCHK(hipEventRecord(ev, other));
+      HIPCHK(hipStreamWaitEvent(s0, ev, 0));
+    }
+    if (prof) HIPCHK(hipEventRecord(events[2 * i], s0));
     if (J.fp32)
-      launch_factor_step<float>(stream, L.kind, L.k, a, L.first, L.count, (float*)J.buf, (float*)J.inv);
+      launch_factor_step<float>(s0, L.kind, L.k, a, L.first, L.count, (float*)J.buf, (float*)J.inv);
     else
-      launch_factor_step<double>(stream, L.kind, L.k, a, L.first, L.count, (double*)J.buf, (double*)J.inv);
-    if (prof) HIPCHK(hipEventRecord(events[2 * i + 1], stream));
+      launch_factor_step<double>(s0, L.kind, L.k, a, L.first, L.count, (double*)J.buf, (double*)J.inv);
+    if (prof) HIPCHK(hipEventRecord(events[2 * i + 1], s0));
+  }
+  if (two) {  // everything on the second stream before the caller's stream continues
+    HIPCHK(hipEventRecord(ev_b, fstream));
+    HIPCHK(hipStreamWaitEvent(stream, ev_b, 0));
   }
   HIPCHK(hipGetLastError());
   int32_t e[2];
@@ -718,6 +753,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if ((st = dalloc(&d_s, S_NSCAL))) return st;
   if ((st = dalloc(&d_hist, 2 * (int64_t)max_hist))) return st;
   if ((st = dalloc(&d_dotp, DOT_BLOCKS))) return st;
+  if ((st = dalloc(&d_it, 1))) return st;
   HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
   (void)ndofs;
   HIPCHK(hipStreamSynchronize(stream));
@@ -1073,7 +1109,51 @@ static void lanczos(const std::vector<double>& al, const std::vector<double>& be
   hi = kth(k - 1);
 }
 
+// One PCG iteration after the first (first == false) or the first one:
+//   [beta = rz_new / rz, p = z + beta p]   (not in the first iteration)
+//   q = S^ p;  alpha = rz / (p.q);  x += alpha p;  r -= alpha q;  rr = r.r
+//   z = M r;  rz_new = r.z
+// The host checks rr (and p.q) after the iteration.
+mlbddc_status Handle::pcg_body(bool first) {
+  mlbddc_status st;
+  const int64_t n = (int64_t)lev[0].P->iface_dofs.size();
+  if (!first) {
+    launch_pcg_beta(stream, d_s, d_hist, d_it);
+    launch_pcg_update_p(stream, n, d_p, d_z, d_s);
+  }
+  if ((st = schur(d_p, d_q))) return st;
+  launch_dot(stream, n, d_p, d_q, d_dotp, DOT_BLOCKS, d_s + S_PQ);
+  launch_pcg_alpha(stream, d_s, d_hist, d_it);
+  launch_pcg_update_xr(stream, n, d_x, d_r, d_p, d_q, d_s);
+  launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
+  if ((st = apply_interface(0, d_r, d_z))) return st;
+  launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZNEW);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+// With graphs the whole solve runs on an internal stream ordered after the
+// caller's stream (the caller's stream may be the null stream, which cannot
+// be captured); the caller's stream waits for it at the end.
 mlbddc_status Handle::solve(const double* f, double* u, const double* u0, mlbddc_stats* stt) {
+  if (!opt.use_graph) return solve_on_stream(f, u, u0, stt);
+  if (!cap) {
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  }
+  hipStream_t user = stream;
+  HIPCHK(hipEventRecord(ev_in, user));
+  HIPCHK(hipStreamWaitEvent(cap, ev_in, 0));
+  stream = cap;
+  mlbddc_status st = solve_on_stream(f, u, u0, stt);
+  stream = user;
+  HIPCHK(hipEventRecord(ev_out, cap));
+  HIPCHK(hipStreamWaitEvent(user, ev_out, 0));
+  return st;
+}
+
+mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* u0, mlbddc_stats* stt) {
   double t0 = now();
   mlbddc_status st;
   LevelDev& D = lev[0];
@@ -1102,22 +1182,33 @@ mlbddc_status Handle::solve(const double* f, double* u, const double* u0, mlbddc
     if ((st = apply_interface(0, d_r, d_z))) return st;
     launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZ);
     HIPCHK(hipMemcpyAsync(d_p, d_z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+    launch_set_int(stream, d_it, 0);
     while (it < opt.max_iter) {
-      if ((st = schur(d_p, d_q))) return st;
-      launch_dot(stream, n, d_p, d_q, d_dotp, DOT_BLOCKS, d_s + S_PQ);
-      launch_pcg_alpha(stream, d_s, d_hist, it);
-      launch_pcg_update_xr(stream, n, d_x, d_r, d_p, d_q, d_s);
-      launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
+      if (it == 0 || !opt.use_graph) {
+        if ((st = pcg_body(it == 0))) return st;
+      } else {
+        if (!gexec) {
+          hipGraph_t graph = nullptr;
+          HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+          mlbddc_status cst = pcg_body(false);
+          hipError_t ce = hipStreamEndCapture(stream, &graph);
+          if (cst) return cst;
+          if (ce != hipSuccess) return herr("hipStreamEndCapture", ce);
+          hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          if (ie != hipSuccess) {
+            gexec = nullptr;
+            return herr("hipGraphInstantiate", ie);
+          }
+        }
+        HIPCHK(hipGraphLaunch(gexec, stream));
+      }
       HIPCHK(hipMemcpyAsync(h_s, d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
-      if ((st = apply_interface(0, d_r, d_z))) return st;
-      launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZNEW);
       HIPCHK(hipStreamSynchronize(stream));
       ++it;
       if (!(h_s[S_PQ] > 0.0) || !std::isfinite(h_s[S_PQ])) { breakdown = true; break; }
       rel = std::sqrt(h_s[S_RR]) / gnorm;
       if (rel < opt.rtol) { conv = true; break; }
-      launch_pcg_beta(stream, d_s, d_hist, it - 1);
-      launch_pcg_update_p(stream, n, d_p, d_z, d_s);
     }
   }
   if ((st = recover(d_x, u))) return st;
@@ -1337,6 +1428,18 @@ mlbddc_status mlbddc_destroy(mlbddc_t h) {
   if (!h) return MLBDDC_OK;
   (void)hipStreamSynchronize(h->h.stream);
   h->h.free_all();
+  if (h->h.cap) {
+    (void)hipStreamSynchronize(h->h.cap);
+    (void)hipStreamDestroy(h->h.cap);
+  }
+  if (h->h.fstream) {
+    (void)hipStreamSynchronize(h->h.fstream);
+    (void)hipStreamDestroy(h->h.fstream);
+  }
+  if (h->h.ev_a) (void)hipEventDestroy(h->h.ev_a);
+  if (h->h.ev_b) (void)hipEventDestroy(h->h.ev_b);
+  if (h->h.ev_in) (void)hipEventDestroy(h->h.ev_in);
+  if (h->h.ev_out) (void)hipEventDestroy(h->h.ev_out);
   delete h;
   return MLBDDC_OK;
 }

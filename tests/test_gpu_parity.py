@@ -167,3 +167,28 @@ def test_error_paths():
         s.setup(Problem(w))
     assert ex.value.name == "E_NOT_SPD"
     assert ex.value.info.level == 1 and ex.value.info.subdomain == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager(precision):
+    """A solve whose PCG iterations replay a captured HIP graph gives the same
+    iterates as the eager launches; repeated solves (several replays each, with
+    eager applies and synchronizations in between) agree every time."""
+    from paper_1201_5991_amd import Problem, Solver
+    _say(f"[graph] {precision}")
+    w, b = _oracle("elast_4x4x4_of_3_L3")
+    prob = Problem(w)
+    f = torch.tensor(prob.load_vector(), device="cuda")
+    eager = Solver(precision=precision, use_graph=False).setup(prob)
+    graph = Solver(precision=precision, use_graph=True).setup(prob)
+    u0, st0 = eager.solve(f)
+    r = torch.tensor(np.random.default_rng(9).standard_normal(eager.n_iface), device="cuda")
+    z0 = eager.apply(r)
+    for rep in range(3):
+        u1, st1 = graph.solve(f)
+        torch.cuda.synchronize()
+        assert st1["iterations"] == st0["iterations"]
+        assert torch.equal(u1, u0), f"replay {rep} differs"
+        z1 = graph.apply(r)          # eager work between graph solves
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z0)
