@@ -30,7 +30,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -158,7 +160,8 @@ struct Handle {
   Error err;
   Plan plan;
   bool planned = false, ready = false;
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;
+  std::multimap<size_t, void*> pool;
   std::vector<LevelDev> lev;
   // mesh data kept for updates and element energies
   int32_t nloc1 = 0;
@@ -205,15 +208,31 @@ struct Handle {
   mlbddc_status dalloc(T** p, int64_t n) {
     *p = nullptr;
     if (n <= 0) return MLBDDC_OK;
+    const size_t bytes = (size_t)round_up((int64_t)(sizeof(T) * (size_t)n), 256);
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)n);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(MLBDDC_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * n) + " bytes failed");
+    auto it = pool.find(bytes);
+    if (it != pool.end()) {  // reuse a block of the previous set-up
+      q = it->second;
+      pool.erase(it);
+    } else {
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        trim_pool();  // retry once without the previous set-up's blocks
+        e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(MLBDDC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+      }
     }
-    allocs.push_back(q);
+    allocs.push_back({q, bytes});
     *p = (T*)q;
     return MLBDDC_OK;
+  }
+  void trim_pool() {
+    for (auto& kv : pool) (void)hipFree(kv.second);
+    pool.clear();
   }
   template <typename T>
   mlbddc_status upload(T** p, const std::vector<T>& v) {
@@ -226,12 +245,20 @@ struct Handle {
     }
     return MLBDDC_OK;
   }
-  void free_all() {
+  // keep = true: device blocks go to a size-keyed pool that the next set-up
+  // reuses (a new set-up of the same problem then allocates nothing); blocks
+  // the next set-up does not take are released at its end.
+  void free_all(bool keep = false) {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
-    for (void* p : allocs) (void)hipFree(p);
+    if (keep) {
+      for (auto& a : allocs) pool.emplace(a.second, a.first);
+    } else {
+      for (auto& a : allocs) (void)hipFree(a.first);
+      trim_pool();
+    }
     allocs.clear();
     if (h_s) (void)hipHostFree(h_s);
     h_s = nullptr;
@@ -396,8 +423,15 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
 mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* part) {
   if (!mesh || !part) return fail(MLBDDC_E_ARG, "null mesh or partition");
   if (!mesh->elem_matrix_ref || !mesh->elem_scale) return fail(MLBDDC_E_ARG, "missing element matrix or scales");
-  free_all();
   double t0 = now();
+  HIPCHK(hipStreamSynchronize(stream));
+  free_all(true);
+  const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
+  double tm = now();
+  auto mark = [&](const char* what) {
+    if (verbose) std::fprintf(stderr, "[mlbddc setup] %-28s %8.2f ms\n", what, (now() - tm) * 1e3);
+    tm = now();
+  };
   PlanInput in;
   in.dim = mesh->dim;
   in.ndof = mesh->ndof_per_node;
@@ -418,6 +452,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     return st;
   }
   planned = true;
+  mark("build_plan");
   const int nd = in.ndof;
   nloc1 = in.nodes_per_elem * nd;
   n_elems = in.n_elems;
@@ -757,7 +792,11 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
   (void)ndofs;
   HIPCHK(hipStreamSynchronize(stream));
+  mark("layouts, schedules, uploads");
+  trim_pool();
+  mark("release unused blocks");
   if ((st = validate())) return st;
+  mark("validate");
   t_plan = now() - t0;
   return numeric();
 }
@@ -1427,7 +1466,7 @@ mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out) {
 mlbddc_status mlbddc_destroy(mlbddc_t h) {
   if (!h) return MLBDDC_OK;
   (void)hipStreamSynchronize(h->h.stream);
-  h->h.free_all();
+  h->h.free_all(false);
   if (h->h.cap) {
     (void)hipStreamSynchronize(h->h.cap);
     (void)hipStreamDestroy(h->h.cap);
