@@ -6,6 +6,10 @@
 #include <map>
 #include <unordered_map>
 #include <numeric>
+#include <thread>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 namespace mlbddc {
 
@@ -24,30 +28,33 @@ int classify(size_t n_subs, size_t n_nodes, int dim) {
   return G_EDGE;
 }
 
-// Greedy element colouring so that elements sharing a node get different colours.
-mlbddc_status colour_elements(LevelPlan& L, Error& err) {
-  const int64_t ne = (int64_t)L.el_sub.size();
-  std::vector<uint64_t> node_mask(L.n_nodes, 0);
-  L.el_color.assign(ne, 0);
-  int ncol = 0;
-  for (int64_t e = 0; e < ne; ++e) {
-    uint64_t used = 0;
-    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
-      if (L.el_nodes[j] >= 0) used |= node_mask[L.el_nodes[j]];
-    if (used == ~0ull) return fail(err, MLBDDC_E_ARG, "element colouring needs more than 64 colours");
-    int c = __builtin_ctzll(~used);
-    L.el_color[e] = c;
-    ncol = std::max(ncol, c + 1);
-    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
-      if (L.el_nodes[j] >= 0) node_mask[L.el_nodes[j]] |= (1ull << c);
+// Run work(begin, end) over [0, n) split into contiguous ranges on up to 16 threads.
+template <typename F>
+void parallel_ranges(int32_t n, F&& work) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int T = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+  T = std::min<int>(T, std::max(1, n / 4));
+  if (T <= 1) { work(0, n); return; }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) {
+    int32_t b0 = (int32_t)((int64_t)n * t / T), b1 = (int32_t)((int64_t)n * (t + 1) / T);
+    th.emplace_back([&, b0, b1] { work(b0, b1); });
   }
-  L.n_colors = ncol;
-  return MLBDDC_OK;
+  for (auto& x : th) x.join();
 }
 
 // Build one level from its elements (node lists, -1 = eliminated node) and
 // the subdomain of every element.
 mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
+  const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
+  auto t_last = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    auto t = std::chrono::steady_clock::now();
+    if (verbose)
+      std::fprintf(stderr, "[mlbddc plan L%d] %-24s %8.2f ms\n", L.level, what,
+                   std::chrono::duration<double, std::milli>(t - t_last).count());
+    t_last = t;
+  };
   const int nd = L.ndof;
   const int64_t ne = (int64_t)L.el_sub.size();
   const int32_t ns = L.n_sub;
@@ -78,6 +85,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     }
   }
 
+  mark("subdomain node sets");
   // --- node -> subdomains (CSR, sorted by subdomain)
   std::vector<int32_t> cnt(L.n_nodes + 1, 0);
   for (int32_t b = 0; b < ns; ++b)
@@ -92,6 +100,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
   }
   auto mult = [&](int64_t n) { return nptr[n + 1] - nptr[n]; };
 
+  mark("node subdomain lists");
   // --- interface nodes and globs
   std::vector<int64_t> iface_nodes;
   if (!L.top)
@@ -156,6 +165,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     if (L.n_coarse == 0) return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + " has no coarse DOFs");
   }
 
+  mark("globs");
   // subdomain -> constrained globs (in glob order)
   std::vector<std::vector<int32_t>> sub_globs(ns);
   for (size_t gi = 0; gi < L.globs.size(); ++gi)
@@ -163,13 +173,20 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
       for (int32_t b : L.globs[gi].subs) sub_globs[b].push_back((int32_t)gi);
 
   // --- local orderings, element maps, envelopes, constraints
-  std::vector<int64_t> node_local(L.n_nodes, -1);  // node -> local node slot (interior or interface)
-  std::vector<char> node_is_g(L.n_nodes, 0);
   L.el_local_ptr.assign(ne + 1, 0);
   for (int64_t e = 0; e < ne; ++e) L.el_local_ptr[e + 1] = L.el_local_ptr[e] + (int32_t)((L.el_ptr[e + 1] - L.el_ptr[e]) * nd);
   L.el_local.assign(L.el_local_ptr[ne], -1);
+  L.el_color.assign(ne, 0);
+  std::vector<int32_t> sub_colors(ns, 0);
+  std::vector<int32_t> sub_fail(ns, 0);
 
-  for (int32_t b = 0; b < ns; ++b) {
+  // Per-subdomain work is independent: split the subdomains over threads, each
+  // with its own node-indexed scratch (reset only where it was touched).
+  auto work = [&](int32_t b_begin, int32_t b_end) {
+  std::vector<int64_t> node_local(L.n_nodes, -1);  // node -> local node slot (interior or interface)
+  std::vector<char> node_is_g(L.n_nodes, 0);
+  std::vector<uint64_t> node_mask(L.n_nodes, 0);
+  for (int32_t b = b_begin; b < b_end; ++b) {
     SubPlan& S = L.subs[b];
     std::vector<int64_t> inodes, gnodes;
     for (int64_t n : sub_nodes[b]) (mult(n) >= 2 && !L.top ? gnodes : inodes).push_back(n);
@@ -266,12 +283,37 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     }
     S.nc = (int32_t)S.coarse.size();
     S.ncp = (int32_t)round_up(S.nc, TS);
-    if (!L.top && S.nc == 0)
-      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " has no constraints");
+    if (!L.top && S.nc == 0) sub_fail[b] = 1;
 
-    for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_is_g[n] = 0; }
+    // greedy colouring of the subdomain's elements: elements sharing a node get
+    // different colours (only elements of one subdomain write the same matrix)
+    int ncol = 0;
+    for (int64_t e : S.elems) {
+      uint64_t used = 0;
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+        if (L.el_nodes[j] >= 0) used |= node_mask[L.el_nodes[j]];
+      if (used == ~0ull) { sub_fail[b] = 2; break; }
+      int c = __builtin_ctzll(~used);
+      L.el_color[e] = c;
+      ncol = std::max(ncol, c + 1);
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
+        if (L.el_nodes[j] >= 0) node_mask[L.el_nodes[j]] |= (1ull << c);
+    }
+    sub_colors[b] = ncol;
+
+    for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_is_g[n] = 0; node_mask[n] = 0; }
   }
-  return colour_elements(L, err);
+  };
+  parallel_ranges(ns, work);
+  mark("local layouts (parallel)");
+  for (int32_t b = 0; b < ns; ++b) {
+    if (sub_fail[b] == 1)
+      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " has no constraints");
+    if (sub_fail[b] == 2) return fail(err, MLBDDC_E_ARG, "element colouring needs more than 64 colours");
+  }
+  L.n_colors = 0;
+  for (int32_t b = 0; b < ns; ++b) L.n_colors = std::max(L.n_colors, sub_colors[b]);
+  return MLBDDC_OK;
 }
 
 }  // namespace
@@ -359,75 +401,117 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
   return MLBDDC_OK;
 }
 
+namespace {
+
+enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_N = 6 };
+
+// All tasks of one item, in (tile column, step kind) order: emit(k, kind, task, flops).
+template <typename F>
+void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
+  const double t3 = (double)TS * TS * TS;
+  const int e1 = it.e1, e2 = it.e2, nt = it.nt;
+  const int32_t* env = it.env;
+  for (int k = 0; k < e1 + e2; ++k) {
+    int ph0 = k < e1 ? 0 : e1, ph1 = k < e1 ? e1 : e1 + e2;
+    int k0 = ph0 + ((k - ph0) / panel) * panel;
+    int kend = std::min(k0 + panel, ph1);
+    if (k == e1 && e2 > 0)
+      for (int s = e1; s < nt; ++s)
+        for (int r = s; r < nt; ++r) emit(k, SK_NEG, pack_task(b, r, s, 0), 0.0);
+    if (k > k0)
+      for (int r = k; r < nt; ++r)
+        if (std::max(env[r], env[k]) <= k - 1) emit(k, SK_INP, pack_task(b, r, k, k0), 2.0 * t3 * (k - k0));
+    emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
+    for (int r = k + 1; r < nt; ++r)
+      if (env[r] <= k) emit(k, SK_PAN, pack_task(b, r, k, 0), 2.0 * t3);
+    if (k == kend - 1) {
+      // columns of the item's next panel (same phase): with look-ahead they are
+      // updated first, on the critical stream
+      int nxt_end = k + 1;
+      if (lookahead && k + 1 < ph1) nxt_end = std::min(k + 1 + panel, ph1);
+      for (int s = k + 1; s < nt; ++s) {
+        if (env[s] > k) continue;
+        const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
+        for (int r = s; r < nt; ++r)
+          if (env[r] <= k) emit(k, dst, pack_task(b, r, s, k0), 2.0 * t3 * (k - k0 + 1));
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// Tasks are ordered by tile column, step kind and item; built in two parallel
+// passes over contiguous item ranges (count, then place at prefix offsets).
 void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out, bool lookahead) {
   out.tasks.clear();
   out.launches.clear();
   out.flops = 0.0;
   out.update_tasks = 0;
-  const double t3 = (double)TS * TS * TS;
   if (panel < 1) panel = 1;
   int maxk = 0;
   for (auto& it : items) maxk = std::max(maxk, it.e1 + it.e2);
-  enum { NEG = 0, INP = 1, DIA = 2, PAN = 3, NXT = 4, RST = 5, NL = 6 };
-  std::vector<uint64_t> lists[NL];
-  double lflops[NL];
-  for (int k = 0; k < maxk; ++k) {
-    for (auto& l : lists) l.clear();
-    for (double& f : lflops) f = 0.0;
-    for (size_t b = 0; b < items.size(); ++b) {
-      const FactorItemDesc& it = items[b];
-      const int e1 = it.e1, e2 = it.e2, nt = it.nt;
-      if (k >= e1 + e2) continue;
-      const int32_t* env = it.env;
-      int ph0 = k < e1 ? 0 : e1, ph1 = k < e1 ? e1 : e1 + e2;
-      int k0 = ph0 + ((k - ph0) / panel) * panel;
-      int kend = std::min(k0 + panel, ph1);
-      if (k == e1 && e2 > 0)
-        for (int s = e1; s < nt; ++s)
-          for (int r = s; r < nt; ++r) lists[NEG].push_back(pack_task(b, r, s, 0));
-      if (k > k0)
-        for (int r = k; r < nt; ++r)
-          if (std::max(env[r], env[k]) <= k - 1) {
-            lists[INP].push_back(pack_task(b, r, k, k0));
-            lflops[INP] += 2.0 * t3 * (k - k0);
-          }
-      lists[DIA].push_back(pack_task(b, k, k, 0));
-      lflops[DIA] += 2.0 * t3 / 3.0;
-      for (int r = k + 1; r < nt; ++r)
-        if (env[r] <= k) {
-          lists[PAN].push_back(pack_task(b, r, k, 0));
-          lflops[PAN] += 2.0 * t3;
-        }
-      if (k == kend - 1) {
-        // columns of the next panel of this item (same phase); with look-ahead
-        // they are updated first, on the critical stream
-        int nxt_end = k + 1;
-        if (lookahead && k + 1 < ph1) nxt_end = std::min(k + 1 + panel, ph1);
-        for (int s = k + 1; s < nt; ++s) {
-          if (env[s] > k) continue;
-          const int dst = (!lookahead || s < nxt_end) ? NXT : RST;
-          for (int r = s; r < nt; ++r)
-            if (env[r] <= k) {
-              lists[dst].push_back(pack_task(b, r, s, k0));
-              lflops[dst] += 2.0 * t3 * (k - k0 + 1);
-            }
-        }
-      }
+  const int32_t ni = (int32_t)items.size();
+  unsigned hw = std::thread::hardware_concurrency();
+  int T = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+  T = std::max(1, std::min<int>(T, ni / 8));
+  const size_t slots = (size_t)maxk * SK_N;
+  std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(slots, 0));
+  std::vector<std::vector<double>> fl(T, std::vector<double>(slots, 0.0));
+  auto range = [&](int t, int32_t& b0, int32_t& b1) {
+    b0 = (int32_t)((int64_t)ni * t / T);
+    b1 = (int32_t)((int64_t)ni * (t + 1) / T);
+  };
+  auto run = [&](auto&& body) {
+    if (T == 1) { body(0); return; }
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back([&, t] { body(t); });
+    for (auto& x : th) x.join();
+  };
+  run([&](int t) {
+    int32_t b0, b1;
+    range(t, b0, b1);
+    for (int32_t b = b0; b < b1; ++b)
+      enumerate_item(items[b], (uint64_t)b, panel, lookahead, [&](int k, int kind, uint64_t, double f) {
+        cnt[t][(size_t)k * SK_N + kind]++;
+        fl[t][(size_t)k * SK_N + kind] += f;
+      });
+  });
+  // offsets: slot-major, thread-minor (= item order within a slot)
+  std::vector<std::vector<int64_t>> off(T, std::vector<int64_t>(slots, 0));
+  int64_t total = 0;
+  static const int kind_of[SK_N] = {L_NEGATE, L_INPANEL, L_DIAG, L_PANEL, L_TRAIL, L_TRAIL};
+  for (size_t sl = 0; sl < slots; ++sl) {
+    int64_t n = 0;
+    double f = 0.0;
+    for (int t = 0; t < T; ++t) {
+      off[t][sl] = total + n;
+      n += cnt[t][sl];
+      f += fl[t][sl];
     }
-    static const int kind_of[NL] = {L_NEGATE, L_INPANEL, L_DIAG, L_PANEL, L_TRAIL, L_TRAIL};
-    for (int l = 0; l < NL; ++l) {
-      if (lists[l].empty()) continue;
-      FactorLaunch L{kind_of[l], k, (int64_t)out.tasks.size(), (int64_t)lists[l].size(), lflops[l], 0, false};
+    if (n > 0) {
+      const int k = (int)(sl / SK_N), l = (int)(sl % SK_N);
+      FactorLaunch L{kind_of[l], k, total, n, f, 0, false};
       if (lookahead) {
-        if (l == RST) { L.stream = 1; L.wait = true; }      // after the panel and the next-panel update
-        if (l == NXT || l == NEG) L.wait = true;            // after the previous bulk update
+        if (l == SK_RST) { L.stream = 1; L.wait = true; }   // after the panel and the next-panel update
+        if (l == SK_NXT || l == SK_NEG) L.wait = true;     // after the previous bulk update
       }
-      if (L.kind == L_TRAIL || L.kind == L_INPANEL) out.update_tasks += L.count;
-      out.flops += lflops[l];
-      out.tasks.insert(out.tasks.end(), lists[l].begin(), lists[l].end());
+      if (L.kind == L_TRAIL || L.kind == L_INPANEL) out.update_tasks += n;
+      out.flops += f;
       out.launches.push_back(L);
     }
+    total += n;
   }
+  out.tasks.resize(total);
+  run([&](int t) {
+    int32_t b0, b1;
+    range(t, b0, b1);
+    std::vector<int64_t>& o = off[t];
+    for (int32_t b = b0; b < b1; ++b)
+      enumerate_item(items[b], (uint64_t)b, panel, lookahead, [&](int k, int kind, uint64_t task, double) {
+        out.tasks[o[(size_t)k * SK_N + kind]++] = task;
+      });
+  });
 }
 
 }  // namespace mlbddc

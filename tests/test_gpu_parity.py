@@ -192,3 +192,29 @@ def test_graph_replays_match_eager(precision):
         z1 = graph.apply(r)          # eager work between graph solves
         torch.cuda.synchronize()
         assert torch.equal(z1, z0)
+
+
+def test_uneven_boxes_three_levels():
+    """Uneven batching: a 20^3 mesh cut by seeded random planes into 4x4x4
+    boxes of 3..8 elements per side (different interior / interface sizes and
+    envelopes per subdomain), 3 levels, FP64 and mixed."""
+    from workloads.gen import random_cuts
+    from paper_1201_5991_amd import Problem, Solver
+    _say("[parity] uneven boxes")
+    cuts = random_cuts(3, n=20, parts=4, lo=3, hi=8)
+    w = box_workload("uneven", "elasticity", (20, 20, 20), cuts, groups=[(2, 2, 2)],
+                     young=10 ** (2 * np.random.default_rng(5).random(20 ** 3)))
+    b = MultilevelBDDC(w)
+    s = Solver().setup(Problem(w))
+    r = np.random.default_rng(6).standard_normal(b.level1.n_iface)
+    z = s.apply(torch.tensor(r, device="cuda")).cpu().numpy()
+    assert _rel(z, b.apply(r)) < RTOL64
+    y = s.apply_schur(torch.tensor(r, device="cuda")).cpu().numpy()
+    assert _rel(y, b.schur_apply(r)) < RTOL64
+    _, f = fem.assemble_global(w)
+    u, st = s.solve(torch.tensor(f, device="cuda"))
+    ref = pcg(b.schur_apply, b.condense(f), b.apply, tol=1e-8)
+    assert abs(st["iterations"] - ref.iterations) <= 1
+    sm = Solver(precision="mixed").setup(Problem(w))
+    um, stm = sm.solve(torch.tensor(f, device="cuda"))
+    assert stm["converged"] == 1 and stm["iterations"] <= int(np.ceil(1.15 * ref.iterations)) + 1
