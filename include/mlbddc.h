@@ -61,8 +61,12 @@ typedef struct {
   int32_t max_iter;    /* default 1000 */
   int32_t weights;     /* MLBDDC_W_* */
   int32_t use_graph;   /* capture one PCG iteration as a HIP graph (1) or launch eagerly (0) */
-  int32_t panel_tiles; /* tile columns per factorization panel (0 = default, 4) */
+  int32_t panel_tiles; /* tile columns per panel of the subdomain-matrix factorizations
+                          (0 = from the tune table, else 4) */
   int32_t device;      /* HIP device ordinal */
+  int32_t panel_tiles_precond; /* same for the constrained local problems (0 = tune table / 4) */
+  const char* tune_table;      /* path of a tune table written by the autotuner, or NULL;
+                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel>" */
 } mlbddc_options;
 
 typedef struct {
@@ -196,6 +200,9 @@ typedef struct {
   double flops[MLBDDC_PROF_N];
   int64_t launches[MLBDDC_PROF_N];
   int64_t tiles[MLBDDC_PROF_N];   /* tile tasks processed */
+  double job_time_s[2];           /* wall time of the factorization jobs: [0] subdomain
+                                     matrices (all levels), [1] constrained local problems */
+  int32_t panel[2];               /* panel widths used by the last set-up (K, M jobs) */
 } mlbddc_profile;
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable);
 mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out);

@@ -32,7 +32,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <array>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <memory>
 #include <string>
 #include <vector>
@@ -70,6 +73,7 @@ struct Job {
   int32_t* d_nt = nullptr;
   uint64_t* d_tasks = nullptr;
   int32_t* d_err = nullptr;
+  int panel = 4;
 };
 
 // A batched tile-block matrix-vector product.
@@ -274,7 +278,9 @@ struct Handle {
   mlbddc_status validate();
   mlbddc_status numeric();
   bool lookahead = true;
-  mlbddc_status prepare_job(Job& J, bool fp32);
+  std::vector<std::array<int, 4>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel)
+  int pick_panel(int job, bool fp32, int ntmax) const;
+  mlbddc_status prepare_job(Job& J, bool fp32, int job = 0);
   mlbddc_status factor(Job& J, int level, bool precond);
   mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
   template <typename TA, typename TX, typename TY>
@@ -317,7 +323,24 @@ void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bo
                              acc, (TA*)partial, s.max_out);
 }
 
-mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
+// Panel width of a factorization job: explicit option, else the tune table's
+// entry for (job kind, precision, ceil(log2(max tiles per side))), else the
+// nearest bucket of the same kind, else 4.
+int Handle::pick_panel(int job, bool fp32, int ntmax) const {
+  const int explicit_p = job == 0 ? opt.panel_tiles : opt.panel_tiles_precond;
+  if (explicit_p > 0) return explicit_p;
+  int bucket = 0;
+  while ((1 << bucket) < ntmax) ++bucket;
+  int best = -1, bestd = 1 << 30;
+  for (const auto& t : tune) {
+    if (t[0] != job || t[1] != (fp32 ? 1 : 0)) continue;
+    int d = std::abs(t[2] - bucket);
+    if (d < bestd) { bestd = d; best = t[3]; }
+  }
+  return best > 0 ? best : 4;
+}
+
+mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   J.fp32 = fp32;
   const size_t esz = fp32 ? 4 : 8;
   J.off.resize(J.nt.size());
@@ -341,7 +364,11 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
   J.buf = b;
   J.inv = iv;
   (void)esz;
-  build_factor_schedule(J.items, opt.panel_tiles > 0 ? opt.panel_tiles : 4, J.sched, lookahead);
+  int ntmax = 1;
+  for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
+  J.panel = pick_panel(job, fp32, ntmax);
+  pdata.panel[job] = J.panel;
+  build_factor_schedule(J.items, J.panel, J.sched, lookahead);
   if ((st = upload(&J.d_off, J.off))) return st;
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
   if ((st = upload(&J.d_nt, J.nt))) return st;
@@ -352,6 +379,8 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32) {
 
 mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
+  if (prof) HIPCHK(hipStreamSynchronize(stream));  // job time excludes earlier queued work
+  const double tj0 = prof ? now() : 0.0;
   FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err};
   const size_t nl = J.sched.launches.size();
   if (prof)
@@ -396,6 +425,7 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemcpyAsync(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   if (prof) {
+    pdata.job_time_s[precond ? 1 : 0] += now() - tj0;
     for (size_t i = 0; i < nl; ++i) {
       const FactorLaunch& L = J.sched.launches[i];
       float ms = 0.f;
@@ -683,7 +713,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         for (int r = 0; r < tC; ++r) env[2 * tG + tC + r] = tG;
         D.M.env[b] = env;
       }
-      if ((st = prepare_job(D.M, D.mfp32))) return st;
+      if ((st = prepare_job(D.M, D.mfp32, 1))) return st;
       flops_M += D.M.sched.flops;
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
@@ -1313,6 +1343,8 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->use_graph = 0;
   o->panel_tiles = 0;
   o->device = 0;
+  o->panel_tiles_precond = 0;
+  o->tune_table = nullptr;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stream) {
@@ -1341,6 +1373,19 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stre
   }
   auto* h = new mlbddc_handle_s();
   h->h.opt = o;
+  if (o.tune_table) {
+    std::ifstream in(o.tune_table);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.empty() || line[0] == '#') continue;
+      std::istringstream ls(line);
+      std::string job, prec;
+      int bucket = 0, panel = 0;
+      if (!(ls >> job >> prec >> bucket >> panel) || panel < 1 || panel > 16) continue;
+      h->h.tune.push_back({job == "M" ? 1 : 0, prec == "f32" ? 1 : 0, bucket, panel});
+    }
+    h->h.opt.tune_table = nullptr;  // the path is not kept
+  }
   h->h.stream = (hipStream_t)stream;
   *out = h;
   return MLBDDC_OK;
@@ -1453,7 +1498,10 @@ mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* out) {
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable) {
   if (!h) return MLBDDC_E_ARG;
   h->h.prof = enable != 0;
+  int p0 = h->h.pdata.panel[0], p1 = h->h.pdata.panel[1];
   h->h.pdata = mlbddc_profile{};
+  h->h.pdata.panel[0] = p0;
+  h->h.pdata.panel[1] = p1;
   return MLBDDC_OK;
 }
 

@@ -12,12 +12,15 @@ element sensitivities in a library kernel.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Optional, Sequence
 
 import numpy as np
 import torch
 
 from . import _lib as L
+
+TUNE_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.txt")
 
 _CONSTRAINTS = {
     "c": L.MLBDDC_CORNERS,
@@ -109,7 +112,8 @@ class Solver:
     """Handle of the HIP multilevel BDDC library on one device."""
 
     def __init__(self, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000, weights: str = "stiffness",
-                 device: int = 0, panel_tiles: int = 0, use_graph: bool = False):
+                 device: int = 0, panel_tiles: int = 0, use_graph: bool = False, panel_tiles_precond: int = 0,
+                 tune_table: Optional[str] = TUNE_TABLE):
         lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the BDDC library needs a HIP device")
@@ -123,6 +127,9 @@ class Solver:
         opt.weights = L.MLBDDC_W_MULTIPLICITY if weights == "multiplicity" else L.MLBDDC_W_STIFFNESS
         opt.use_graph = 1 if use_graph else 0
         opt.panel_tiles = panel_tiles
+        opt.panel_tiles_precond = panel_tiles_precond
+        self._tune = tune_table.encode() if tune_table and os.path.exists(tune_table) else None
+        opt.tune_table = self._tune
         opt.device = device
         self.opt = opt
         with torch.cuda.device(self.device):
