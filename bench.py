@@ -64,6 +64,29 @@ def algorithmic_apply_bytes(s, precision: str) -> dict:
     return {"apply": total, "schur": schur}
 
 
+def kernel_source_hash() -> str:
+    """Hash of the tile-update kernel's source (the PMC traffic figure in
+    profiles/ is only valid for the kernel it was measured on)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1201_5991_amd", "csrc", "dense.hip")).read()
+    a = src.index("// Register staging of one 64x64 tile")
+    b = src.index("template <typename T>\n__global__ void __launch_bounds__(256) k_negate(")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None."""
+    path = os.path.join(ROOT, "profiles", "k_update_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("source_hash") != kernel_source_hash():
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
 def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0, graph: bool = True):
     import torch
     from paper_1201_5991_amd import Solver
@@ -187,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--panel", type=int, default=0, help="tile columns per factorization panel (0 = library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG iterations eagerly instead of replaying a HIP graph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 512 MiB (3 times) to calibrate PMC byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a "
@@ -210,7 +235,7 @@ def main():
     main_mode = "mixed" if "mixed" in out else modes[0]
     R = out[main_mode]
     # dominant kernel of the timed path: the largest device-time class of the set-up profile
-    prof = R["profile"]
+    prof = {k: v for k, v in R["profile"].items() if k != "jobs"}
     dom = max(prof, key=lambda k: prof[k]["time_s"])
     dprof = prof[dom]
     prec = "fp32" if dom.endswith("fp32") else "fp64"
@@ -218,8 +243,12 @@ def main():
     roof = {"kernel": f"k_update<{'float' if prec == 'fp32' else 'double'}>" if dom.startswith("update") else dom,
             "bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
             "frac": achieved / PEAK[prec], "traffic": None,
+            "traffic_unit": "bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launches": dprof["launches"], "avg_launch_ms": dprof["time_s"] / max(dprof["launches"], 1) * 1e3,
-            "flops_per_launch": dprof["flops"] / max(dprof["launches"], 1)}
+            "flops_per_launch": dprof["flops"] / max(dprof["launches"], 1),
+            # lower bound on a launch's HBM bytes: each updated 64x64 tile read and written once
+            "c_tile_bytes_per_launch": dprof["tiles"] / max(dprof["launches"], 1) * 2 * 64 * 64 * (4 if prec == "fp32" else 8)}
+    roof["traffic"] = measured_traffic(roof["kernel"])
     line = {
         "metric": METRIC,
         "value": R["tts_s"],
@@ -242,14 +271,23 @@ def main():
     }
     for m in modes:
         d = dict(out[m])
+        jobs = d["profile"].get("jobs", {})
         d["profile"] = {k: {"time_ms": v["time_s"] * 1e3, "tflops": (v["flops"] / v["time_s"] * 1e-12 if v["time_s"] else 0.0),
-                            "launches": v["launches"]} for k, v in d["profile"].items()}
+                            "launches": v["launches"]} for k, v in d["profile"].items() if k != "jobs"}
+        d["profile"]["jobs"] = jobs
         line[m] = d
     if "fp64" in out and "mixed" in out:
         line["mixed_speedup"] = {"tts": out["fp64"]["tts_s"] / out["mixed"]["tts_s"],
                                  "apply": out["mixed"]["applies_per_s"] / out["fp64"]["applies_per_s"]}
     line["apply_roofline"] = {"bound": "hbm", "achieved": R["apply_alg_GBps"], "peak": HBM_PEAK, "unit": "GB/s",
                               "frac": R["apply_alg_GBps"] / HBM_PEAK}
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 2 * a.numel() * 8
     if not args.no_cpu_baseline:
         _log("[cpu baseline] oracle sample ...")
         line["cpu_baseline"] = cpu_baseline()
