@@ -15,6 +15,8 @@
 // with 64-wide wavefronts; a 64x64 output tile is split over 4 wavefronts.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mlbddc {
@@ -125,142 +127,204 @@ __global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A) {
 }
 
 // ------------------------------------------------------------ factorization
-// Exchange within groups of four lanes through DPP (quad permutations).
-template <int CTRL>
-__device__ inline double quad_perm(double v) {
+// Value of v in lane n of the caller's row of 16 lanes (DPP row_newbcast).
+template <int N>
+__device__ inline double row_bcast(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x150 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + N, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int CTRL>
-__device__ inline float quad_perm(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+template <int N>
+__device__ inline float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, false));
 }
-constexpr int DPP_XOR1 = 0xB1;  // quad_perm(1, 0, 3, 2)
-constexpr int DPP_XOR2 = 0x4E;  // quad_perm(2, 3, 0, 1)
 
-// Diagonal tile: Cholesky factor and inverse of the lower factor.
-// Factor: wavefront 0, lane i keeps row i in registers; per column j the pivot
-// and then the new column of L are broadcast through LDS (reads issued
-// unconditionally, so they pipeline), and the right-looking update touches
-// registers only.  Entries right of a lane's diagonal are left as they are
-// and ignored.  Inverse W = L^{-1}: four neighbouring lanes own column c of W
-// (lane p keeps W(p+4m, c)); W(r, c) = (delta_rc - sum_{q<r} L(r, q) W(q, c)) /
-// L(r, r).  Entries of W not yet computed are zero, so the sum runs over all
-// of the lane's entries without predicates; the four partial sums are combined
-// with DPP quad permutations.
+// Compile-time loop: f(integral_constant<J>) for J = B..E-1.
+template <int B, int E, typename F>
+__device__ inline void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// 16x16 block products on MFMA between blocks held in LDS with leading
+// dimension LDT: acc += sx * X * Y.  Lane l supplies X(m, k) and Y(k, n) for
+// m = n = l%16 and k = 4s + l/16, and holds the result entries
+// (Mfma<T>::row(l/16, v), l%16).  Operand storage forms:
+//   X: XC  X(m, k) = X[k*LDT + m] (column-major)
+//      XR  X(m, k) = X[m*LDT + k], zero above the diagonal (m < k)
+//   Y: YR  Y(k, n) = Y[k*LDT + n], optionally zero where k < n
+//      YC  Y(k, n) = Y[n*LDT + k], zero where n < k
+enum { XC = 0, XR = 1, YR = 0, YRL = 1, YC = 2 };
+template <typename T, int XF, int YF>
+__device__ inline void mm16(typename Mfma<T>::acc_t& acc, const T* X, const T* Y, T sx) {
+  const int l16 = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3;
+  T a[4], b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + g;
+    a[s] = XF == XC ? X[k * LDT + l16] : (l16 >= k ? X[l16 * LDT + k] : (T)0);
+    a[s] *= sx;
+    b[s] = YF == YR ? Y[k * LDT + l16] : YF == YRL ? (k >= l16 ? Y[k * LDT + l16] : (T)0)
+                                                    : (l16 >= k ? Y[l16 * LDT + k] : (T)0);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = Mfma<T>::mac(a[s], b[s], acc);
+}
+// Result block stored column-major (O[n*LDT + m]) or transposed (O[m*LDT + n]).
 template <typename T>
-__global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
+__device__ inline void load16(typename Mfma<T>::acc_t& acc, const T* O) {
+  const int l16 = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = O[l16 * LDT + Mfma<T>::row(g, v)];
+}
+template <typename T>
+__device__ inline void store16(const typename Mfma<T>::acc_t& acc, T* O) {
+  const int l16 = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) O[l16 * LDT + Mfma<T>::row(g, v)] = acc[v];
+}
+template <typename T>
+__device__ inline void store16t(const typename Mfma<T>::acc_t& acc, T* O) {
+  const int l16 = threadIdx.x & 15, g = (threadIdx.x >> 4) & 3;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) O[Mfma<T>::row(g, v) * LDT + l16] = acc[v];
+}
+
+// Diagonal tile: Cholesky factor L and W = L^{-1}, blocked by 16, in one
+// LDS tile (small enough to share a CU with the update kernel).
+// For each block column jb: wavefront 0 factors the 16x16 diagonal block in
+// registers (lane i keeps row i; pivots and the column of L are read from
+// the owning lanes), writes that block of L to global memory, and forms the
+// block's inverse by forward substitution; the blocks below are multiplied
+// by that inverse and the trailing blocks updated with MFMA products, one
+// block per wavefront.  The off-diagonal blocks of W follow from
+// W_ij = -inv(L_ii) sum_{j<=m<i} L_im W_mj, one block column per wavefront.
+// W is kept transposed in the upper triangle of the tile (entry (r, c) of W
+// at LDS position (c, r)), the strict lower triangle holds L.  A
+// non-positive pivot is reported in err (first failing item, then its
+// column) and turns the rest of the tile into NaN.
+template <typename T>
+__global__ void __launch_bounds__(256, 4) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
-  __shared__ T dinv[TS];
+  typedef typename Mfma<T>::acc_t acc_t;
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
   const int nt = ntv[item];
-  T* g = A + off[item] + tile_index(k, k, nt) * TE;
-  const int tid = threadIdx.x;
-  // factor in LDS: per column one pivot/scale pass (wavefront 0) and one
-  // branch-free rank-1 update (each thread owns 16 entries of the tile)
-  stage_tile<T, T>(sA, g, false);
+  T* gA = A + off[item] + tile_index(k, k, nt) * TE;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  stage_tile<T, T>(sA, gA, false);
   __syncthreads();
-  bool bad = false;
-  int badcol = 0;
-  {
-    const int i = tid & (TS - 1), l0 = tid >> 6;
-    for (int j = 0; j < TS; ++j) {
-      if (tid < TS) {
-        T d = sA[j * LDT + j];
-        if (!(d > (T)0)) {
-          if (!bad) badcol = j;
-          bad = true;
-          d = (T)NAN;
+  int badcol = -1;
+#pragma unroll 1
+  for (int jb = 0; jb < 4; ++jb) {
+    const int j0 = 16 * jb;
+    T* D = &sA[j0 * LDT + j0];
+    if (w == 0) {
+      // lane i of every row of 16 lanes keeps row i of the block (d) and row
+      // i of V, the inverse of the block's factor (v).  Step j finishes
+      // column j of L and eliminates it from the trailing block, then
+      // finishes row j of V (scale by 1/L(j, j)) and eliminates it from the
+      // rows of V below, which needs only column j of L.
+      const int i = lane & 15;
+      T d[16], v[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        d[m] = D[m * LDT + i];
+        v[m] = m == i ? (T)1 : (T)0;
+      }
+      static_for<0, 16>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        T piv = row_bcast<j>(d[j]);
+        const bool ok = piv > (T)0;
+        badcol = (!ok && badcol < 0) ? j0 + j : badcol;
+        piv = ok ? piv : (T)NAN;
+        const T sq = sqrt(piv), inv = (T)1 / sq;
+        d[j] = i > j ? d[j] * inv : (i == j ? sq : (T)0);
+        static_for<j + 1, 16>([&](auto M) {
+          constexpr int m = decltype(M)::value;
+          d[m] -= d[j] * row_bcast<m>(d[j]);
+        });
+        const T lij = i > j ? d[j] : (T)0;
+        static_for<0, j + 1>([&](auto C) {
+          constexpr int c = decltype(C)::value;
+          if (i == j) v[c] *= inv;
+          v[c] -= lij * row_bcast<j>(v[c]);
+        });
+      });
+      if (lane < 16) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          gA[(j0 + m) * TS + j0 + i] = m <= i ? d[m] : (T)0;
+          if (m < i) D[m * LDT + i] = d[m];
+          if (m <= i) D[i * LDT + m] = v[m];  // V(i, m) at block position (m, i)
         }
-        const T sq = sqrt(d);
-        const T v = sA[j * LDT + tid];
-        __builtin_amdgcn_wave_barrier();
-        sA[j * LDT + tid] = tid > j ? v / sq : (tid == j ? sq : v);
       }
-      __syncthreads();
-      const T lij = sA[j * LDT + i];
-      T lj[16], cur[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        lj[m] = sA[j * LDT + l0 + 4 * m];
-        cur[m] = sA[(l0 + 4 * m) * LDT + i];
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int l = l0 + 4 * m;
-        sA[l * LDT + i] = (l > j && i >= l) ? cur[m] - lij * lj[m] : cur[m];
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    if (w < 3 - jb) {  // L(ib, jb) = A(ib, jb) V^T
+      const int ib = jb + 1 + w;
+      acc_t acc = Mfma<T>::zero();
+      mm16<T, XC, YC>(acc, &sA[j0 * LDT + 16 * ib], D, (T)1);
+      store16<T>(acc, &sA[j0 * LDT + 16 * ib]);
+    }
+    __syncthreads();
+    const int nb = (3 - jb) * (4 - jb) / 2;  // trailing blocks (ib, kb), jb < kb <= ib
+    for (int b = w; b < nb; b += 4) {
+      int kb = jb + 1, rem = b;
+      while (rem >= 4 - kb) {
+        rem -= 4 - kb;
+        ++kb;
+      }
+      const int ib = kb + rem;
+      acc_t acc;
+      load16<T>(acc, &sA[16 * kb * LDT + 16 * ib]);
+      mm16<T, XC, YR>(acc, &sA[j0 * LDT + 16 * ib], &sA[j0 * LDT + 16 * kb], (T)-1);
+      store16<T>(acc, &sA[16 * kb * LDT + 16 * ib]);
+    }
+    __syncthreads();
   }
-  if (bad && tid == 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
+  // off-diagonal blocks of W: wavefront w computes block column w
+#pragma unroll 1
+  for (int step = 1; step <= 3; ++step) {
+    const int jb = w, ib = w + step;
+    const bool act = ib <= 3;
+    T* Wij = &sA[16 * ib * LDT + 16 * jb];  // W(ib, jb), transposed storage
+    acc_t acc = Mfma<T>::zero();
+    if (act) {
+      mm16<T, XC, YRL>(acc, &sA[16 * jb * LDT + 16 * ib], &sA[16 * jb * LDT + 16 * jb], (T)1);
+      for (int mb = jb + 1; mb < ib; ++mb) mm16<T, XC, YR>(acc, &sA[16 * mb * LDT + 16 * ib], &sA[16 * mb * LDT + 16 * jb], (T)1);
+      store16t<T>(acc, Wij);
+    }
+    __syncthreads();
+    if (act) {
+      acc = Mfma<T>::zero();
+      mm16<T, XR, YR>(acc, &sA[16 * ib * LDT + 16 * ib], Wij, (T)-1);
+      store16t<T>(acc, Wij);
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && badcol >= 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
+  T* gI = Inv + inv_off[item] + (int64_t)k * TE;
   for (int idx = tid; idx < TE; idx += blockDim.x) {
-    const int r = idx & (TS - 1), cc = idx >> 6;
-    if (r < cc) sA[cc * LDT + r] = (T)0;
+    const int r = idx & (TS - 1), c = idx >> 6;
+    if ((r >> 4) != (c >> 4)) gA[idx] = r > c ? sA[c * LDT + r] : (T)0;
+    gI[idx] = r >= c ? sA[r * LDT + c] : (T)0;
   }
-  __syncthreads();
-  for (int idx = tid; idx < TE; idx += blockDim.x) g[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
-  if (tid < TS) dinv[tid] = (T)1 / sA[tid * LDT + tid];
-  __syncthreads();
-  // inverse
-  const int c = tid >> 2, p = tid & 3;
-  T w[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) w[m] = (T)0;
-  for (int r = 0; r < TS; ++r) {
-    T s0 = 0, s1 = 0;
-#pragma unroll
-    for (int m = 0; m < 16; m += 2) {
-      s0 += sA[(p + 4 * m) * LDT + r] * w[m];
-      s1 += sA[(p + 4 * m + 4) * LDT + r] * w[m + 1];
-    }
-    T s = s0 + s1;
-    s += quad_perm<DPP_XOR1>(s);
-    s += quad_perm<DPP_XOR2>(s);
-    const T v = ((r == c ? (T)1 : (T)0) - s) * dinv[r];
-#pragma unroll
-    for (int m = 0; m < 16; ++m)
-      if (p + 4 * m == r) w[m] = v;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < 16; ++m) sA[c * LDT + p + 4 * m] = w[m];
-  __syncthreads();
-  T* gi = Inv + inv_off[item] + (int64_t)k * TE;
-  for (int idx = tid; idx < TE; idx += blockDim.x) gi[idx] = sA[(idx >> 6) * LDT + (idx & (TS - 1))];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_panel(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
-                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off, T* A,
-                                               const T* __restrict__ Inv) {
-  __shared__ T sR[TS * LDT];
-  __shared__ T sS[TS * LDT];
-  const uint64_t t = tasks[blockIdx.x];
-  const int item = task_item(t), r = task_r(t), k = task_s(t);
-  const int nt = ntv[item];
-  T* g = A + off[item] + tile_index(r, k, nt) * TE;
-  stage_tile<T, T>(sR, g, false);
-  stage_tile<T, T>(sS, Inv + inv_off[item] + (int64_t)k * TE, false);
-  __syncthreads();
-  typename Mfma<T>::acc_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
-  tile_nt<T>(acc, sR, sS);
-  for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = v; });
-}
-
-// Register staging of one 64x64 tile: each of the 256 threads holds 16
-// elements as 16-byte vectors (coalesced loads), then stores them to LDS.
-template <typename T>
-struct TileRegs {
+// Register staging of NE consecutive elements of a column-major 64x64 tile
+// (the whole tile, or the 32 columns of one half): each of the 256 threads
+// holds NE/256 elements as 16-byte vectors (coalesced loads), then stores
+// them to LDS with leading dimension LD.
+template <typename T, int NE>
+struct ChunkRegs {
   static constexpr int V = 16 / sizeof(T);          // elements per 16-byte vector
-  static constexpr int N = TE / (256 * V);          // vectors per thread
+  static constexpr int N = NE / (256 * V);          // vectors per thread
   typedef T vec __attribute__((ext_vector_type(V)));
   vec v[N];
   __device__ void load(const T* __restrict__ g) {
@@ -280,14 +344,14 @@ struct TileRegs {
   }
 };
 
-// acc(i, j) += sum_k R(i, k) S(j, k) from LDS tiles with leading dimension LD.
-template <typename T, int LD>
+// acc(i, j) += sum_k R(i, k) S(j, k) over KN staged columns k (LDS leading dimension LD).
+template <typename T, int LD, int KN>
 __device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T* __restrict__ sR, const T* __restrict__ sS) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
   const int l16 = lane & 15, kq = lane >> 4;
 #pragma unroll
-  for (int k0 = 0; k0 < TS; k0 += 4) {
+  for (int k0 = 0; k0 < KN; k0 += 4) {
     const int kk = k0 + kq;
     T a[2], b[2];
 #pragma unroll
@@ -302,22 +366,55 @@ __device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T*
 }
 
 constexpr int LDU = TS + 16;  // keeps the four k-groups of a fragment read on distinct LDS banks
+constexpr int KH = TS / 2;    // columns of a tile staged at a time
 
-// A_rs <- A_rs - sum_{kk=kf..klast} A_{r,kk} A_{s,kk}^T.  The output tile is
-// prefetched into registers at the start; the next pair of k-tiles is loaded
-// into registers while the current pair is multiplied from LDS.
-template <typename T>
-__global__ void __launch_bounds__(256) k_update(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
-                                                const int32_t* __restrict__ ntv, int klast, T* A) {
-  __shared__ T sR[TS * LDU];
-  __shared__ T sS[TS * LDU];
+// Tile products on MFMA, one 64x64 output tile per workgroup:
+//   UPDATE  A_rs <- A_rs - sum_{kk=kf..klast} A_{r,kk} A_{s,kk}^T
+//   PANEL   A_rk <- A_rk inv(L_kk)^T
+// The k dimension advances in half tiles (32 columns; 2 x 32 x LDU values of
+// LDS, so that four workgroups share a CU).  The next pair of half tiles is
+// loaded into registers while the current pair is multiplied from LDS; during
+// the last pair the registers freed by that prefetch receive the output tile
+// of an UPDATE.
+template <typename T, bool PANEL>
+__global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
+                                                    int klast, T* A, const T* __restrict__ Inv) {
+  __shared__ T sR[KH * LDU];
+  __shared__ T sS[KH * LDU];
   const uint64_t t = tasks[blockIdx.x];
-  const int item = task_item(t), r = task_r(t), s = task_s(t), kf = task_kf(t);
+  const int item = task_item(t), r = task_r(t), s = task_s(t);
+  const int kf = PANEL ? s : task_kf(t);
+  const int nsteps = PANEL ? 2 : 2 * (klast - kf + 1);
   const int nt = ntv[item];
   T* base = A + off[item];
   T* g = base + tile_index(r, s, nt) * TE;
+  const bool same = !PANEL && r == s;
+  auto rsrc = [&](int q) { return base + tile_index(r, kf + (q >> 1), nt) * TE + (q & 1) * (TE / 2); };
+  auto ssrc = [&](int q) -> const T* {
+    return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q & 1) * (TE / 2)
+                 : base + tile_index(s, kf + (q >> 1), nt) * TE + (q & 1) * (TE / 2);
+  };
+  typename Mfma<T>::acc_t acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
+  ChunkRegs<T, TE / 2> pr, ps;
+  pr.load(rsrc(0));
+  if (!same) ps.load(ssrc(0));
+  for (int q = 0; q + 1 < nsteps; ++q) {
+    pr.template store<LDU>(sR);
+    if (!same) ps.template store<LDU>(sS);
+    __syncthreads();
+    pr.load(rsrc(q + 1));
+    if (!same) ps.load(ssrc(q + 1));
+    tile_nt_ld<T, LDU, KH>(acc, sR, same ? sR : sS);
+    __syncthreads();
+  }
+  pr.template store<LDU>(sR);
+  if (!same) ps.template store<LDU>(sS);
+  __syncthreads();
   T creg[16];
-  {
+  if (!PANEL) {
     int n = 0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
@@ -331,26 +428,10 @@ __global__ void __launch_bounds__(256) k_update(const uint64_t* __restrict__ tas
           creg[n++] = g[j * TS + i];
         }
   }
-  typename Mfma<T>::acc_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
-  TileRegs<T> pr, ps;
-  const bool diag = r == s;
-  pr.load(base + tile_index(r, kf, nt) * TE);
-  if (!diag) ps.load(base + tile_index(s, kf, nt) * TE);
-  for (int kk = kf; kk <= klast; ++kk) {
-    pr.template store<LDU>(sR);
-    if (!diag) ps.template store<LDU>(sS);
-    __syncthreads();
-    if (kk < klast) {
-      pr.load(base + tile_index(r, kk + 1, nt) * TE);
-      if (!diag) ps.load(base + tile_index(s, kk + 1, nt) * TE);
-    }
-    tile_nt_ld<T, LDU>(acc, sR, diag ? sR : sS);
-    __syncthreads();
-  }
+  tile_nt_ld<T, LDU, KH>(acc, sR, same ? sR : sS);
   int n = 0;
-  for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - v; });
+  if (PANEL) for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = v; });
+  else for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - v; });
 }
 
 template <typename T>
@@ -492,10 +573,10 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
   dim3 grid((unsigned)count), blk(256);
   switch (kind) {
     case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A); break;
-    case L_INPANEL: hipLaunchKernelGGL(k_update<T>, grid, blk, 0, st, tk, a.off, a.nt, k - 1, A); break;
+    case L_INPANEL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, k - 1, A, Inv); break;
     case L_DIAG: hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv); break;
-    case L_PANEL: hipLaunchKernelGGL(k_panel<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
-    case L_TRAIL: hipLaunchKernelGGL(k_update<T>, grid, blk, 0, st, tk, a.off, a.nt, k, A); break;
+    case L_PANEL: hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, 0, A, Inv); break;
+    case L_TRAIL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, k, A, Inv); break;
   }
 }
 

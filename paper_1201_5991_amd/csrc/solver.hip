@@ -1345,6 +1345,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->device = 0;
   o->panel_tiles_precond = 0;
   o->tune_table = nullptr;
+  o->lookahead = 1;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stream) {
@@ -1373,6 +1374,7 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stre
   }
   auto* h = new mlbddc_handle_s();
   h->h.opt = o;
+  h->h.lookahead = o.lookahead != 0;
   if (o.tune_table) {
     std::ifstream in(o.tune_table);
     std::string line;
