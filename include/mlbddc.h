@@ -100,8 +100,11 @@ typedef struct {
   double rel_res;      /* final ||r^|| / ||g^|| (recursive residual) */
   double lambda_min;   /* Lanczos estimates of the spectrum of M S^ */
   double lambda_max;
-  double t_plan;       /* seconds: host planning in the last setup */
-  double t_setup_num;  /* seconds: numeric set-up (device) in the last setup/update */
+  double t_plan;       /* seconds: host planning and preparation in the last setup (the device
+                          already factorizes the parts prepared first meanwhile) */
+  double t_setup_num;  /* seconds: device set-up still running when the host preparation ended
+                          (setup), or the whole numeric set-up (update_coefficients);
+                          t_plan + t_setup_num is the set-up wall time */
   double t_solve;      /* seconds: condensation + PCG + interior recovery */
 } mlbddc_stats;
 

@@ -97,24 +97,30 @@ __device__ inline void for_acc(typename Mfma<T>::acc_t (&acc)[2][2], F f) {
 }
 
 // ------------------------------------------------------------------ assembly
+// One workgroup per element: A += scale * Ke on the lower tiles of the
+// owning subdomain's matrix.  el_local holds, per element node, the local
+// index of the node's first DOF (its nd DOFs are consecutive) or -1.
 template <typename T>
 __global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ elems, const int32_t* __restrict__ el_local_ptr,
-                                                  const int32_t* __restrict__ el_local, const int32_t* __restrict__ el_sub,
+                                                  const int32_t* __restrict__ el_local, int nd, const int32_t* __restrict__ el_sub,
                                                   const int64_t* __restrict__ sub_off, const int32_t* __restrict__ sub_nt,
                                                   const double* __restrict__ Kref, const double* __restrict__ scale,
                                                   const int64_t* __restrict__ ekc_off, const double* __restrict__ ekc, T* A) {
   const int64_t e = elems[blockIdx.x];
   const int b = el_sub[e];
   const int32_t base = el_local_ptr[e];
-  const int nloc = el_local_ptr[e + 1] - base;
+  const int nloc = (el_local_ptr[e + 1] - base) * nd;
   const int64_t off = sub_off[b];
   const int nt = sub_nt[b];
   const double sc = Kref ? scale[e] : 1.0;
   const double* M = Kref ? Kref : ekc + ekc_off[e];
   for (int idx = threadIdx.x; idx < nloc * nloc; idx += blockDim.x) {
-    int a = idx / nloc, c = idx - a * nloc;
-    int p = el_local[base + a], q = el_local[base + c];
-    if (p < 0 || q < 0 || p / TS < q / TS) continue;
+    const int a = idx / nloc, c = idx - a * nloc;
+    const int na = a / nd, nc = c / nd;
+    const int ka = el_local[base + na], kc = el_local[base + nc];
+    if (ka < 0 || kc < 0) continue;
+    const int p = ka + (a - na * nd), q = kc + (c - nc * nd);
+    if (p / TS < q / TS) continue;
     A[off + packed_offset(p, q, nt)] += (T)(sc * M[idx]);
   }
 }
@@ -552,10 +558,10 @@ __global__ void k_compact_kc(const int64_t* __restrict__ kc_off, const int32_t* 
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr, const int32_t* el_local,
-                     const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt, const double* Kref,
+                     int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt, const double* Kref,
                      const double* scale, const int64_t* ekc_off, const double* ekc, T* A) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)n), dim3(256), 0, st, elems, el_local_ptr, el_local, el_sub, sub_off,
+  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)n), dim3(256), 0, st, elems, el_local_ptr, el_local, nd, el_sub, sub_off,
                      sub_nt, Kref, scale, ekc_off, ekc, A);
 }
 
@@ -608,7 +614,7 @@ void launch_compact_kc(hipStream_t st, const int64_t* kc_off, const int32_t* ntc
 }
 
 #define INST_T(T)                                                                                                         \
-  template void launch_assemble<T>(hipStream_t, const int64_t*, int64_t, const int32_t*, const int32_t*, const int32_t*, \
+  template void launch_assemble<T>(hipStream_t, const int64_t*, int64_t, const int32_t*, const int32_t*, int, const int32_t*, \
                                    const int64_t*, const int32_t*, const double*, const double*, const int64_t*,        \
                                    const double*, T*);                                                                  \
   template void launch_set_diag<T>(hipStream_t, const DiagSeg*, int64_t, int32_t, T*);                                 \

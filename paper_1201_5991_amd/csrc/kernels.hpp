@@ -18,7 +18,7 @@ namespace mlbddc {
 // scale[e] * Kref (Kref != null) or ekc[ekc_off[e] ...] (row-major, nloc^2).
 template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr,
-                     const int32_t* el_local, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
+                     const int32_t* el_local, int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
                      const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A);
 
 // Set entries A[row0+i][col0+i] = val for every segment (tile-packed matrices).

@@ -62,14 +62,19 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
   // --- subdomain node sets and elements
   std::vector<std::vector<int64_t>> sub_nodes(ns);
   L.subs.assign(ns, SubPlan());
-  for (int64_t e = 0; e < ne; ++e) {
-    int32_t b = L.el_sub[e];
-    if (b < 0 || b >= ns) return fail(err, MLBDDC_E_ARG, "element assigned to a non-existent subdomain");
-    L.subs[b].elems.push_back(e);
-  }
   {
+    std::vector<int64_t> cnt(ns, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+      int32_t b = L.el_sub[e];
+      if (b < 0 || b >= ns) return fail(err, MLBDDC_E_ARG, "element assigned to a non-existent subdomain");
+      cnt[b]++;
+    }
+    for (int32_t b = 0; b < ns; ++b) L.subs[b].elems.reserve(cnt[b]);
+    for (int64_t e = 0; e < ne; ++e) L.subs[L.el_sub[e]].elems.push_back(e);
+  }
+  parallel_ranges(ns, [&](int32_t b0, int32_t b1) {
     std::vector<int32_t> stamp(L.n_nodes, -1);  // last subdomain that listed the node
-    for (int32_t b = 0; b < ns; ++b) {
+    for (int32_t b = b0; b < b1; ++b) {
       auto& v = sub_nodes[b];
       for (int64_t e : L.subs[b].elems)
         for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
@@ -80,10 +85,11 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
           }
         }
       std::sort(v.begin(), v.end());
-      if (L.subs[b].elems.empty() || v.empty())
-        return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " is empty");
     }
-  }
+  });
+  for (int32_t b = 0; b < ns; ++b)
+    if (L.subs[b].elems.empty() || sub_nodes[b].empty())
+      return fail(err, MLBDDC_E_ARG, "level " + std::to_string(L.level) + ": subdomain " + std::to_string(b) + " is empty");
 
   mark("subdomain node sets");
   // --- node -> subdomains (CSR, sorted by subdomain)
@@ -173,10 +179,11 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
       for (int32_t b : L.globs[gi].subs) sub_globs[b].push_back((int32_t)gi);
 
   // --- local orderings, element maps, envelopes, constraints
-  L.el_local_ptr.assign(ne + 1, 0);
-  for (int64_t e = 0; e < ne; ++e) L.el_local_ptr[e + 1] = L.el_local_ptr[e] + (int32_t)((L.el_ptr[e + 1] - L.el_ptr[e]) * nd);
-  L.el_local.assign(L.el_local_ptr[ne], -1);
-  L.el_color.assign(ne, 0);
+  if (L.el_ptr[ne] >= INT32_MAX) return fail(err, MLBDDC_E_ARG, "too many element nodes on one level");
+  L.el_local_ptr.resize(ne + 1);
+  for (int64_t e = 0; e <= ne; ++e) L.el_local_ptr[e] = (int32_t)L.el_ptr[e];
+  L.el_local.resize(L.el_ptr[ne]);  // every entry is written by the subdomain owning the element
+  L.el_color.resize(ne);
   std::vector<int32_t> sub_colors(ns, 0);
   std::vector<int32_t> sub_fail(ns, 0);
 
@@ -244,23 +251,17 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
       for (int64_t p = S.nIp + S.nGp; p < nK; ++p) first[p] = p - (S.nIp + S.nGp);
     for (int64_t e : S.elems) {
       int64_t mn = INT64_MAX;
-      int32_t base = L.el_local_ptr[e];
-      int k = 0;
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
         int64_t n = L.el_nodes[j];
-        for (int c = 0; c < nd; ++c, ++k) {
-          if (n < 0) { L.el_local[base + k] = -1; continue; }
-          int64_t p = kidx(n, c);
-          L.el_local[base + k] = (int32_t)p;
-          mn = std::min(mn, p);
-        }
+        int64_t p = n < 0 ? -1 : kidx(n, 0);
+        L.el_local[j] = (int32_t)p;
+        if (p >= 0) mn = std::min(mn, p);
       }
-      k = 0;
-      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
-        for (int c = 0; c < nd; ++c, ++k) {
-          int32_t p = L.el_local[base + k];
-          if (p >= 0) first[p] = std::min(first[p], mn);
-        }
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+        int32_t p = L.el_local[j];
+        if (p >= 0)
+          for (int c = 0; c < nd; ++c) first[p + c] = std::min(first[p + c], mn);
+      }
     }
     S.envK.assign(ntK, 0);
     for (int64_t r = 0; r < ntK; ++r) {

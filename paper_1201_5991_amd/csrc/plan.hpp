@@ -63,8 +63,9 @@ struct LevelPlan {
   std::vector<int64_t> el_ptr, el_nodes;
   std::vector<int32_t> el_sub;
   // per element and element DOF: position in the padded local K ordering (-1 = none)
-  std::vector<int32_t> el_local_ptr;    // start of an element's DOF map in el_local
-  std::vector<int32_t> el_local;
+  std::vector<int32_t> el_local_ptr;    // start of an element's node entries in el_local (= el_ptr)
+  std::vector<int32_t> el_local;        // per element node: local matrix index of the node's first DOF
+                                        // (its ndof DOFs are consecutive), -1 for an eliminated node
   std::vector<int32_t> el_color;
   int32_t n_colors = 0;
   std::vector<SubPlan> subs;

@@ -34,6 +34,7 @@
 #include <cstring>
 #include <array>
 #include <fstream>
+#include <future>
 #include <map>
 #include <sstream>
 #include <memory>
@@ -238,15 +239,58 @@ struct Handle {
     for (auto& kv : pool) (void)hipFree(kv.second);
     pool.clear();
   }
+  // Host-to-device copies of set-up data: staged in pinned host memory kept
+  // by the handle (chunks reused by every set-up) and copied asynchronously on
+  // their own stream, so that the host goes on preparing while the device
+  // factorizes the parts already prepared.  upload_fence() orders the
+  // library stream after every copy issued so far.
+  hipStream_t ustream = nullptr;
+  hipEvent_t ev_upl = nullptr;
+  std::vector<std::pair<char*, size_t>> staging;  // pinned chunks
+  size_t stage_chunk = 0, stage_used = 0;
+  mlbddc_status stage_reset() {
+    if (ustream) HIPCHK(hipStreamSynchronize(ustream));
+    stage_chunk = 0;
+    stage_used = 0;
+    return MLBDDC_OK;
+  }
+  mlbddc_status stage(size_t bytes, char** out) {
+    bytes = (bytes + 255) / 256 * 256;
+    while (stage_chunk < staging.size() && stage_used + bytes > staging[stage_chunk].second) {
+      ++stage_chunk;
+      stage_used = 0;
+    }
+    if (stage_chunk == staging.size()) {
+      const size_t cap = std::max<size_t>(bytes, (size_t)16 << 20);
+      char* q = nullptr;
+      HIPCHK(hipHostMalloc((void**)&q, cap, hipHostMallocDefault));
+      staging.push_back({q, cap});
+      stage_used = 0;
+    }
+    *out = staging[stage_chunk].first + stage_used;
+    stage_used += bytes;
+    return MLBDDC_OK;
+  }
   template <typename T>
   mlbddc_status upload(T** p, const std::vector<T>& v) {
     mlbddc_status st = dalloc(p, (int64_t)v.size());
     if (st) return st;
     if (!v.empty()) {
-      // synchronous: the host vector may be a temporary
-      HIPCHK(hipMemcpyAsync(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, stream));
-      HIPCHK(hipStreamSynchronize(stream));
+      if (!ustream) {
+        HIPCHK(hipStreamCreateWithFlags(&ustream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev_upl, hipEventDisableTiming));
+      }
+      char* h = nullptr;
+      if ((st = stage(sizeof(T) * v.size(), &h))) return st;
+      std::memcpy(h, v.data(), sizeof(T) * v.size());
+      HIPCHK(hipMemcpyAsync(*p, h, sizeof(T) * v.size(), hipMemcpyHostToDevice, ustream));
     }
+    return MLBDDC_OK;
+  }
+  mlbddc_status upload_fence() {
+    if (!ustream) return MLBDDC_OK;
+    HIPCHK(hipEventRecord(ev_upl, ustream));
+    HIPCHK(hipStreamWaitEvent(stream, ev_upl, 0));
     return MLBDDC_OK;
   }
   // keep = true: device blocks go to a size-keyed pool that the next set-up
@@ -264,8 +308,6 @@ struct Handle {
       trim_pool();
     }
     allocs.clear();
-    if (h_s) (void)hipHostFree(h_s);
-    h_s = nullptr;
     lev.clear();
     ready = false;
   }
@@ -275,7 +317,10 @@ struct Handle {
   }
 
   mlbddc_status setup(const mlbddc_mesh* mesh, const mlbddc_partition* part);
-  mlbddc_status validate();
+  mlbddc_status validate_level(int li, int part);
+  mlbddc_status enqueue_K(int li);
+  mlbddc_status enqueue_rest(int li);
+  mlbddc_status finish_numeric();
   mlbddc_status numeric();
   bool lookahead = true;
   std::vector<std::array<int, 4>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel)
@@ -421,10 +466,8 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
     HIPCHK(hipStreamWaitEvent(stream, ev_b, 0));
   }
   HIPCHK(hipGetLastError());
-  int32_t e[2];
-  HIPCHK(hipMemcpyAsync(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
   if (prof) {
+    HIPCHK(hipStreamSynchronize(stream));
     pdata.job_time_s[precond ? 1 : 0] += now() - tj0;
     for (size_t i = 0; i < nl; ++i) {
       const FactorLaunch& L = J.sched.launches[i];
@@ -440,12 +483,7 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
       pdata.tiles[c] += L.count;
     }
   }
-  if (e[0] != 0) {
-    int sub = e[0] - 1;
-    if (precond)
-      return fail(MLBDDC_E_SINGULAR_CONSTRAINTS, "constrained local problem is singular", level, sub, e[1]);
-    return fail(MLBDDC_E_NOT_SPD, "non-positive pivot in a subdomain factorization", level, sub, e[1]);
-  }
+  (void)level;
   return MLBDDC_OK;
 }
 
@@ -455,12 +493,27 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if (!mesh->elem_matrix_ref || !mesh->elem_scale) return fail(MLBDDC_E_ARG, "missing element matrix or scales");
   double t0 = now();
   HIPCHK(hipStreamSynchronize(stream));
+  if (mlbddc_status sr = stage_reset()) return sr;
   free_all(true);
   const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
   double tm = now();
   auto mark = [&](const char* what) {
     if (verbose) std::fprintf(stderr, "[mlbddc setup] %-28s %8.2f ms\n", what, (now() - tm) * 1e3);
     tm = now();
+  };
+  // Queuing a factorization can block the host once the launch queue is
+  // full, so each level's numeric work is queued by a worker thread while
+  // this thread prepares the next part.  At most one part is being queued at
+  // a time (join() before the next upload fence and enqueue), so the library
+  // stream sees the same order as a sequential set-up.
+  std::future<mlbddc_status> pending;
+  auto join = [&]() -> mlbddc_status { return pending.valid() ? pending.get() : MLBDDC_OK; };
+  auto enqueue_async = [&](int li, bool kjob) {
+    const int dev = opt.device;
+    pending = std::async(std::launch::async, [this, li, kjob, dev]() -> mlbddc_status {
+      if (hipSetDevice(dev) != hipSuccess) return herr("hipSetDevice", hipGetLastError());
+      return kjob ? enqueue_K(li) : enqueue_rest(li);
+    });
   };
   PlanInput in;
   in.dim = mesh->dim;
@@ -527,6 +580,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
     if ((st = prepare_job(D.K, D.kfp32))) return st;
     flops_K += D.K.sched.flops;
+    mark("  K job layout + schedule");
 
     // diagonal segments of the K matrices: padding and identity block
     for (int b = 0; b < ns; ++b) {
@@ -544,12 +598,14 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
 
     // assembly data
     {
-      std::vector<int64_t> byc;
+      // elements grouped by colour (counting sort, element order kept within a colour)
       D.color_ptr.assign(P.n_colors + 1, 0);
-      for (int c = 0; c < P.n_colors; ++c) {
-        for (size_t el = 0; el < P.el_color.size(); ++el)
-          if (P.el_color[el] == c) byc.push_back((int64_t)el);
-        D.color_ptr[c + 1] = (int64_t)byc.size();
+      for (int32_t c : P.el_color) D.color_ptr[c + 1]++;
+      for (int c = 0; c < P.n_colors; ++c) D.color_ptr[c + 1] += D.color_ptr[c];
+      std::vector<int64_t> byc(P.el_color.size());
+      {
+        std::vector<int64_t> pos(D.color_ptr.begin(), D.color_ptr.end() - 1);
+        for (size_t el = 0; el < P.el_color.size(); ++el) byc[pos[P.el_color[el]]++] = (int64_t)el;
       }
       if ((st = upload(&D.d_elems_by_color, byc))) return st;
       if ((st = upload(&D.d_el_local_ptr, P.el_local_ptr))) return st;
@@ -562,6 +618,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
     }
 
+    mark("  assembly maps");
     // flat layouts
     D.gofs.assign(ns + 1, 0);
     D.iofs.assign(ns + 1, 0);
@@ -636,6 +693,13 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     if ((st = dalloc(&D.gd2, std::max<int64_t>(D.nG_flat, 1)))) return st;
     if ((st = dalloc(&D.wI, std::max<int64_t>(D.nI_flat, 1)))) return st;
 
+    mark("  flat layouts + vectors");
+    // the device assembles and factors this level's K job while the host goes on
+    if ((st = validate_level(li, 0))) return st;
+    mark("  validate (K job)");
+    if ((st = join())) return st;
+    if ((st = upload_fence())) return st;
+    enqueue_async(li, true);
     // K-job tile mat-vecs
     {
       std::vector<MvDesc> s, pre, lgi;
@@ -687,6 +751,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
     }
 
+    mark("  K mat-vec sets");
     // ---- preconditioner job and coarse matrices
     if (!P.top) {
       D.M.nt.resize(ns);
@@ -715,6 +780,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
       if ((st = prepare_job(D.M, D.mfp32, 1))) return st;
       flops_M += D.M.sched.flops;
+      mark("  M job layout + schedule");
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
         int tG = (int)(S.nGp / TS);
@@ -807,6 +873,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     for (MvSet* s : {&D.mvS, &D.mvG, &D.mvPsiN, &D.mvPsiT, &D.mvPre, &D.mvPreT, &D.mvPostN, &D.mvLgi, &D.mvLgiT})
       pmax = std::max(pmax, s->partial_elems);
     if ((st = dalloc((double**)&D.partial, pmax))) return st;
+    mark("  constraints, coarse, M mat-vecs");
+    if ((st = validate_level(li, 1))) return st;
+    mark("  validate (rest)");
+    if ((st = join())) return st;
+    if ((st = upload_fence())) return st;
+    enqueue_async(li, false);
   }
 
   // PCG vectors
@@ -819,214 +891,260 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if ((st = dalloc(&d_hist, 2 * (int64_t)max_hist))) return st;
   if ((st = dalloc(&d_dotp, DOT_BLOCKS))) return st;
   if ((st = dalloc(&d_it, 1))) return st;
-  HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+  if (!h_s) HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
   (void)ndofs;
-  HIPCHK(hipStreamSynchronize(stream));
-  mark("layouts, schedules, uploads");
-  trim_pool();
-  mark("release unused blocks");
-  if ((st = validate())) return st;
-  mark("validate");
+  mark("PCG vectors");
+  if ((st = join())) return st;
+  if ((st = upload_fence())) return st;
+  // host preparation done; the device may still be factorizing the last parts
   t_plan = now() - t0;
-  return numeric();
+  st = finish_numeric();
+  t_setup = now() - t0 - t_plan;
+  mark("device work after the host preparation");
+  trim_pool();
+  if (st) return st;
+  ready = true;
+  return MLBDDC_OK;
 }
 
 // Host check of every index the kernels will use against the buffers they
 // address, run once per set-up before any kernel touches the data.
-mlbddc_status Handle::validate() {
+mlbddc_status Handle::validate_level(int li, int part) {
   auto bad = [&](const std::string& what) { return fail(MLBDDC_E_ARG, "internal layout check failed: " + what); };
-  for (size_t li = 0; li < lev.size(); ++li) {
-    LevelDev& D = lev[li];
-    LevelPlan& P = *D.P;
-    const std::string L = "level " + std::to_string(li + 1) + ": ";
-    for (Job* J : {&D.K, &D.M}) {
-      if (J->nt.empty()) continue;
-      const size_t ni = J->nt.size();
-      for (size_t i = 0; i < ni; ++i) {
-        if (J->off[i] + packed_tiles(J->nt[i]) * TE > J->elems) return bad(L + "job matrix extent");
-        if (J->inv_off[i] + (int64_t)(J->items[i].e1 + J->items[i].e2) * TE > std::max<int64_t>(J->inv_elems, 1))
-          return bad(L + "inverse tile extent");
-        if (J->items[i].e1 + J->items[i].e2 > J->nt[i]) return bad(L + "elimination beyond the matrix");
-        if ((int)J->env[i].size() != J->nt[i]) return bad(L + "envelope size");
-        if (J->nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
-      }
-      if (ni >= (1u << 24)) return bad(L + "too many matrices for the task encoding");
-      for (const FactorLaunch& F : J->sched.launches) {
-        for (int64_t q = F.first; q < F.first + F.count; ++q) {
-          uint64_t t = J->sched.tasks[q];
-          size_t it = (size_t)task_item(t);
-          int r = task_r(t), c = task_s(t), kf = task_kf(t);
-          if (it >= ni) return bad(L + "task item");
-          int nt = J->nt[it], ee = J->items[it].e1 + J->items[it].e2;
-          if (r >= nt || c > r) return bad(L + "task tile");
-          switch (F.kind) {
-            case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return bad(L + "diag task"); break;
-            case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return bad(L + "panel task"); break;
-            case L_INPANEL: if (c != F.k || kf >= F.k) return bad(L + "in-panel task"); break;
-            case L_TRAIL: if (c <= F.k || kf > F.k) return bad(L + "trailing task"); break;
-            case L_NEGATE: if (c < J->items[it].e1) return bad(L + "negate task"); break;
-            default: return bad(L + "task kind");
-          }
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
+  const std::string L = "level " + std::to_string(li + 1) + ": ";
+  auto job_ok = [&](const Job& J) -> mlbddc_status {
+    if (J.nt.empty()) return MLBDDC_OK;
+    const size_t ni = J.nt.size();
+    for (size_t i = 0; i < ni; ++i) {
+      if (J.off[i] + packed_tiles(J.nt[i]) * TE > J.elems) return bad(L + "job matrix extent");
+      if (J.inv_off[i] + (int64_t)(J.items[i].e1 + J.items[i].e2) * TE > std::max<int64_t>(J.inv_elems, 1))
+        return bad(L + "inverse tile extent");
+      if (J.items[i].e1 + J.items[i].e2 > J.nt[i]) return bad(L + "elimination beyond the matrix");
+      if ((int)J.env[i].size() != J.nt[i]) return bad(L + "envelope size");
+      if (J.nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
+    }
+    if (ni >= (1u << 24)) return bad(L + "too many matrices for the task encoding");
+    for (const FactorLaunch& F : J.sched.launches) {
+      for (int64_t q = F.first; q < F.first + F.count; ++q) {
+        uint64_t t = J.sched.tasks[q];
+        size_t it = (size_t)task_item(t);
+        int r = task_r(t), c = task_s(t), kf = task_kf(t);
+        if (it >= ni) return bad(L + "task item");
+        int nt = J.nt[it], ee = J.items[it].e1 + J.items[it].e2;
+        if (r >= nt || c > r) return bad(L + "task tile");
+        switch (F.kind) {
+          case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return bad(L + "diag task"); break;
+          case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return bad(L + "panel task"); break;
+          case L_INPANEL: if (c != F.k || kf >= F.k) return bad(L + "in-panel task"); break;
+          case L_TRAIL: if (c <= F.k || kf > F.k) return bad(L + "trailing task"); break;
+          case L_NEGATE: if (c < J.items[it].e1) return bad(L + "negate task"); break;
+          default: return bad(L + "task kind");
         }
       }
     }
-    // element maps
+    return MLBDDC_OK;
+  };
+  auto seg_ok = [&](const std::vector<DiagSeg>& v) {
+    for (const DiagSeg& g : v)
+      if (g.row0 < g.col0 || (int64_t)g.row0 + g.count > (int64_t)g.nt * TS || (int64_t)g.col0 + g.count > (int64_t)g.nt * TS)
+        return false;
+    return true;
+  };
+  mlbddc_status st;
+  if (part == 0) {  // what assembly, weights and the K job use
+    if ((st = job_ok(D.K))) return st;
     for (int64_t e = 0; e + 1 < (int64_t)P.el_local_ptr.size(); ++e) {
       int b = P.el_sub[e];
       int64_t nK = (int64_t)D.K.nt[b] * TS;
       for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
-        if (P.el_local[j] >= nK) return bad(L + "element map");
+        if (P.el_local[j] < -1 || (int64_t)P.el_local[j] + P.ndof > nK) return bad(L + "element map");
       if (li > 0) {
         const LevelPlan& PP = *lev[li - 1].P;
-        int64_t nloc = P.el_local_ptr[e + 1] - P.el_local_ptr[e];
+        int64_t nloc = (int64_t)(P.el_local_ptr[e + 1] - P.el_local_ptr[e]) * P.ndof;
         const SubPlan& S = PP.subs[e];
         if (nloc != S.nc || lev[li - 1].kc_off[e] + nloc * nloc > (int64_t)lev[li - 1].kc_off.back() + (int64_t)PP.subs.back().nc * PP.subs.back().nc)
           return bad(L + "coarse element matrix");
       }
     }
-    auto seg_ok = [&](const std::vector<DiagSeg>& v) {
-      for (const DiagSeg& g : v)
-        if (g.row0 < g.col0 || (int64_t)g.row0 + g.count > (int64_t)g.nt * TS || (int64_t)g.col0 + g.count > (int64_t)g.nt * TS)
-          return false;
-      return true;
-    };
-    if (!seg_ok(D.ksegs_h) || !seg_ok(D.msegs_h)) return bad(L + "diagonal segment");
-    auto mv_ok = [&](const MvSet& s, const Job& J, int64_t xlen, int64_t ylen) {
-      for (const MvDesc& d : s.h) {
-        if (d.r0 + d.nr > d.a_nt || d.c0 + d.nc > d.a_nt) return false;
-        if (s.mode == MV_SYM && (d.r0 != d.c0 || d.nr != d.nc)) return false;
-        if (s.mode != MV_SYM && d.r0 < d.c0 + d.nc) return false;
-        if (d.a_off + packed_tiles(d.a_nt) * TE > J.elems) return false;
-        int64_t nx = (s.mode == MV_T ? d.nr : d.nc) * (int64_t)TS, ny = (s.mode == MV_T ? d.nc : d.nr) * (int64_t)TS;
-        if (d.x_off + nx > xlen || d.y_off + ny > ylen) return false;
-        if (d.p_off + (int64_t)d.nr * d.nc * TS > s.partial_elems) return false;
-      }
-      return true;
-    };
-    if (li == 0) {
-      if (!mv_ok(D.mvS, D.K, D.nG_flat, D.nG_flat)) return bad(L + "S mat-vec");
-      if (!mv_ok(D.mvLgi, D.K, D.nI_flat, D.nG_flat)) return bad(L + "L_GI mat-vec");
-      if (!mv_ok(D.mvLgiT, D.K, D.nG_flat, D.nI_flat)) return bad(L + "L_GI^T mat-vec");
-      for (const TrsvDesc& t : D.trsv_h)
-        if (t.nti > t.a_nt || t.v_off + (int64_t)t.nti * TS > D.nI_flat || t.inv_off + (int64_t)t.nti * TE > D.K.inv_elems + (t.nti == 0))
-          return bad(L + "triangular solve");
-    } else {
-      if (!mv_ok(D.mvPre, D.K, D.nI_flat, D.nI_flat)) return bad(L + "interior mat-vec");
-      if (!P.top && (!mv_ok(D.mvPreT, D.K, D.nI_flat, D.nG_flat) || !mv_ok(D.mvPostN, D.K, D.nG_flat, D.nI_flat)))
-        return bad(L + "correction mat-vec");
-    }
-    if (!P.top) {
-      if (!mv_ok(D.mvG, D.M, D.nG_flat, D.nG_flat)) return bad(L + "G mat-vec");
-      if (!mv_ok(D.mvPsiN, D.M, D.nG_flat, D.nC_flat)) return bad(L + "Psi^T mat-vec");
-      if (!mv_ok(D.mvPsiT, D.M, D.nC_flat, D.nG_flat)) return bad(L + "Psi mat-vec");
-      int64_t tsz = 0, ksz = 0;
-      for (const KcDesc& k : D.kcd_h) {
-        tsz = std::max(tsz, k.t_off + (int64_t)k.ntg * k.ntc * TE);
-        ksz = std::max(ksz, k.kc_off + (int64_t)k.ntc * k.ntc * TE);
-        if (k.k_g0 + k.ntg > k.k_nt || k.p_c0 + k.ntc > k.p_nt || k.p_d0 + k.ntg > k.p_nt || k.p_c0 < k.p_d0 + k.ntg)
-          return bad(L + "coarse matrix descriptor");
-      }
-      for (const CopyDesc& c : D.copy_h)
-        if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt) return bad(L + "copy descriptor");
-      for (size_t b = 0; b < P.subs.size(); ++b) {
-        const SubPlan& S = P.subs[b];
-        for (int32_t col : S.crow_col)
-          if (col >= S.nG) return bad(L + "constraint column");
-        for (int32_t g : S.iface)
-          if (g < 0 || g >= (int64_t)P.iface_dofs.size()) return bad(L + "interface map");
-        for (int32_t c : S.coarse)
-          if (c < 0 || c >= P.n_coarse) return bad(L + "coarse map");
-        if (S.nGp + S.nc > (int64_t)D.M.nt[b] * TS) return bad(L + "constraint rows");
-      }
-    }
-    for (size_t b = 0; b < P.subs.size(); ++b)
+    if (!seg_ok(D.ksegs_h)) return bad(L + "diagonal segment");
+    for (size_t b = 0; b < P.subs.size(); ++b) {
       for (int64_t d : P.subs[b].dofI)
         if (d < 0 || d >= P.n_dofs) return bad(L + "interior map");
+      for (int32_t g : P.subs[b].iface)
+        if (g < 0 || g >= (int64_t)P.iface_dofs.size()) return bad(L + "interface map");
+    }
     for (int64_t d : P.iface_dofs)
       if (d < 0 || d >= P.n_dofs) return bad(L + "interface DOF");
+    return MLBDDC_OK;
+  }
+  // M job, products of the apply, coarse matrices
+  if ((st = job_ok(D.M))) return st;
+  if (!seg_ok(D.msegs_h)) return bad(L + "diagonal segment");
+  auto mv_ok = [&](const MvSet& s, const Job& J, int64_t xlen, int64_t ylen) {
+    for (const MvDesc& d : s.h) {
+      if (d.r0 + d.nr > d.a_nt || d.c0 + d.nc > d.a_nt) return false;
+      if (s.mode == MV_SYM && (d.r0 != d.c0 || d.nr != d.nc)) return false;
+      if (s.mode != MV_SYM && d.r0 < d.c0 + d.nc) return false;
+      if (d.a_off + packed_tiles(d.a_nt) * TE > J.elems) return false;
+      int64_t nx = (s.mode == MV_T ? d.nr : d.nc) * (int64_t)TS, ny = (s.mode == MV_T ? d.nc : d.nr) * (int64_t)TS;
+      if (d.x_off + nx > xlen || d.y_off + ny > ylen) return false;
+      if (d.p_off + (int64_t)d.nr * d.nc * TS > s.partial_elems) return false;
+    }
+    return true;
+  };
+  if (li == 0) {
+    if (!mv_ok(D.mvS, D.K, D.nG_flat, D.nG_flat)) return bad(L + "S mat-vec");
+    if (!mv_ok(D.mvLgi, D.K, D.nI_flat, D.nG_flat)) return bad(L + "L_GI mat-vec");
+    if (!mv_ok(D.mvLgiT, D.K, D.nG_flat, D.nI_flat)) return bad(L + "L_GI^T mat-vec");
+    for (const TrsvDesc& t : D.trsv_h)
+      if (t.nti > t.a_nt || t.v_off + (int64_t)t.nti * TS > D.nI_flat || t.inv_off + (int64_t)t.nti * TE > D.K.inv_elems + (t.nti == 0))
+        return bad(L + "triangular solve");
+  } else {
+    if (!mv_ok(D.mvPre, D.K, D.nI_flat, D.nI_flat)) return bad(L + "interior mat-vec");
+    if (!P.top && (!mv_ok(D.mvPreT, D.K, D.nI_flat, D.nG_flat) || !mv_ok(D.mvPostN, D.K, D.nG_flat, D.nI_flat)))
+      return bad(L + "correction mat-vec");
+  }
+  if (!P.top) {
+    if (!mv_ok(D.mvG, D.M, D.nG_flat, D.nG_flat)) return bad(L + "G mat-vec");
+    if (!mv_ok(D.mvPsiN, D.M, D.nG_flat, D.nC_flat)) return bad(L + "Psi^T mat-vec");
+    if (!mv_ok(D.mvPsiT, D.M, D.nC_flat, D.nG_flat)) return bad(L + "Psi mat-vec");
+    for (const KcDesc& k : D.kcd_h)
+      if (k.k_g0 + k.ntg > k.k_nt || k.p_c0 + k.ntc > k.p_nt || k.p_d0 + k.ntg > k.p_nt || k.p_c0 < k.p_d0 + k.ntg)
+        return bad(L + "coarse matrix descriptor");
+    for (const CopyDesc& c : D.copy_h)
+      if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt) return bad(L + "copy descriptor");
+    for (size_t b = 0; b < P.subs.size(); ++b) {
+      const SubPlan& S = P.subs[b];
+      for (int32_t col : S.crow_col)
+        if (col >= S.nG) return bad(L + "constraint column");
+      for (int32_t c : S.coarse)
+        if (c < 0 || c >= P.n_coarse) return bad(L + "coarse map");
+      if (S.nGp + S.nc > (int64_t)D.M.nt[b] * TS) return bad(L + "constraint rows");
+    }
   }
   return MLBDDC_OK;
 }
 
+// Numeric set-up of level li, first part: assemble K (FP64 or FP32), take
+// the interface weights from its diagonal, factor the K job.  Queued on the
+// library stream only; errors are collected by finish_numeric().
+mlbddc_status Handle::enqueue_K(int li) {
+  mlbddc_status st;
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
+  // assemble K
+  HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
+  for (int c = 0; c < P.n_colors; ++c) {
+    int64_t n = D.color_ptr[c + 1] - D.color_ptr[c];
+    const int64_t* el = D.d_elems_by_color + D.color_ptr[c];
+    const double* kref = li == 0 ? d_Kref : nullptr;
+    const double* ekc = li == 0 ? nullptr : lev[li - 1].kc_compact;
+    if (D.kfp32)
+      launch_assemble<float>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
+                             d_scale, D.d_ekc_off, ekc, (float*)D.K.buf);
+    else
+      launch_assemble<double>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
+                              d_scale, D.d_ekc_off, ekc, (double*)D.K.buf);
+  }
+  if (D.kfp32)
+    launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf);
+  else
+    launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
+  HIPCHK(hipGetLastError());
+  // weights from the assembled interface diagonal (before factorization)
+  if (!P.top) {
+    const int64_t nif = (int64_t)P.iface_dofs.size();
+    if (opt.weights == MLBDDC_W_MULTIPLICITY) {
+      launch_fill(stream, D.nG_flat, 1.0, D.gd);
+    } else {
+      // gd[i] = K[gdiag_pos[i]]: the assembled (sub-assembled) diagonal at the interface
+      if (D.kfp32) launch_gather64<float>(stream, D.nG_flat, D.d_gdiag_pos, (const float*)D.K.buf, D.gd);
+      else launch_gather64<double>(stream, D.nG_flat, D.d_gdiag_pos, (const double*)D.K.buf, D.gd);
+    }
+    // sum over subdomains per interface DOF, then w = d / sum
+    launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd, D.rhat, 0.0);
+    launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.rhat, D.gd2);
+    launch_ratio(stream, D.nG_flat, D.gd, D.gd2, D.d_gidx, D.d_w);
+  }
+  if ((st = factor(D.K, P.level, false))) return st;
+  return MLBDDC_OK;
+}
+
+// Second part: the constrained local problems (M job) and the coarse
+// matrices Psi^T S Psi that the next level assembles.
+mlbddc_status Handle::enqueue_rest(int li) {
+  mlbddc_status st;
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
+  if (P.top) return MLBDDC_OK;
+  // preconditioner matrices
+  HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
+  if (D.kfp32) {  // K is FP32 only when M is FP32
+    launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
+    launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
+                                     (float*)D.M.buf);
+    launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
+  } else if (D.mfp32) {
+    launch_copy_block<double, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (float*)D.M.buf);
+    launch_constraints<double, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
+                                      (float*)D.M.buf);
+    launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
+  } else {
+    launch_copy_block<double, double>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (double*)D.M.buf);
+    launch_constraints<double, double>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
+                                       (double*)D.M.buf);
+    launch_set_diag<double>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (double*)D.M.buf);
+  }
+  HIPCHK(hipGetLastError());
+  if ((st = factor(D.M, P.level, true))) return st;
+  // K_Ci = Psi^T S Psi
+  if (D.kfp32) {
+    launch_coarse_matrix<float, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const float*)D.K.buf,
+                                       (const float*)D.M.buf, D.Tscr, D.KCt);
+  } else if (D.mfp32) {
+    launch_coarse_matrix<double, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
+                                (const float*)D.M.buf, D.Tscr, D.KCt);
+  } else {
+    launch_coarse_matrix<double, double>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
+                                 (const double*)D.M.buf, D.Tscr, D.KCt);
+  }
+  launch_compact_kc(stream, D.d_kct_off, D.d_ntc, D.d_nc, D.d_kc_off, P.n_sub, D.max_nc, D.KCt, D.kc_compact);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+// Wait for the queued numeric set-up and report the first factorization
+// that met a non-positive pivot (levels in order, K job before M job).
+mlbddc_status Handle::finish_numeric() {
+  HIPCHK(hipStreamSynchronize(stream));
+  for (size_t li = 0; li < lev.size(); ++li)
+    for (int j = 0; j < 2; ++j) {
+      const Job& J = j == 0 ? lev[li].K : lev[li].M;
+      if (!J.d_err) continue;
+      int32_t e[2] = {0, 0};
+      HIPCHK(hipMemcpy(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost));
+      if (e[0] != 0) {
+        const int level = lev[li].P->level, sub = e[0] - 1;
+        if (j == 1) return fail(MLBDDC_E_SINGULAR_CONSTRAINTS, "constrained local problem is singular", level, sub, e[1]);
+        return fail(MLBDDC_E_NOT_SPD, "non-positive pivot in a subdomain factorization", level, sub, e[1]);
+      }
+    }
+  return MLBDDC_OK;
+}
+
+// Whole numeric set-up on an existing plan (coefficient updates).
 mlbddc_status Handle::numeric() {
   double t0 = now();
   mlbddc_status st;
-  const int nlev = (int)lev.size();
-  for (int li = 0; li < nlev; ++li) {
-    LevelDev& D = lev[li];
-    LevelPlan& P = *D.P;
-    // assemble K
-    HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
-    for (int c = 0; c < P.n_colors; ++c) {
-      int64_t n = D.color_ptr[c + 1] - D.color_ptr[c];
-      const int64_t* el = D.d_elems_by_color + D.color_ptr[c];
-      const double* kref = li == 0 ? d_Kref : nullptr;
-      const double* ekc = li == 0 ? nullptr : lev[li - 1].kc_compact;
-      if (D.kfp32)
-        launch_assemble<float>(stream, el, n, D.d_el_local_ptr, D.d_el_local, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                               d_scale, D.d_ekc_off, ekc, (float*)D.K.buf);
-      else
-        launch_assemble<double>(stream, el, n, D.d_el_local_ptr, D.d_el_local, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                                d_scale, D.d_ekc_off, ekc, (double*)D.K.buf);
-    }
-    if (D.kfp32)
-      launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf);
-    else
-      launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
-    HIPCHK(hipGetLastError());
-    // weights from the assembled interface diagonal (before factorization)
-    if (!P.top) {
-      const int64_t nif = (int64_t)P.iface_dofs.size();
-      if (opt.weights == MLBDDC_W_MULTIPLICITY) {
-        launch_fill(stream, D.nG_flat, 1.0, D.gd);
-      } else {
-        // gd[i] = K[gdiag_pos[i]]: the assembled (sub-assembled) diagonal at the interface
-        if (D.kfp32) launch_gather64<float>(stream, D.nG_flat, D.d_gdiag_pos, (const float*)D.K.buf, D.gd);
-        else launch_gather64<double>(stream, D.nG_flat, D.d_gdiag_pos, (const double*)D.K.buf, D.gd);
-      }
-      // sum over subdomains per interface DOF, then w = d / sum
-      launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd, D.rhat, 0.0);
-      launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.rhat, D.gd2);
-      launch_ratio(stream, D.nG_flat, D.gd, D.gd2, D.d_gidx, D.d_w);
-    }
-    if ((st = factor(D.K, P.level, false))) return st;
-    if (P.top) continue;
-    // preconditioner matrices
-    HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
-    if (D.kfp32) {  // K is FP32 only when M is FP32
-      launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
-      launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
-                                       (float*)D.M.buf);
-      launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
-    } else if (D.mfp32) {
-      launch_copy_block<double, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (float*)D.M.buf);
-      launch_constraints<double, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
-                                        (float*)D.M.buf);
-      launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
-    } else {
-      launch_copy_block<double, double>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (double*)D.M.buf);
-      launch_constraints<double, double>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
-                                         (double*)D.M.buf);
-      launch_set_diag<double>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (double*)D.M.buf);
-    }
-    HIPCHK(hipGetLastError());
-    if ((st = factor(D.M, P.level, true))) return st;
-    // K_Ci = Psi^T S Psi
-    if (D.kfp32) {
-      launch_coarse_matrix<float, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const float*)D.K.buf,
-                                         (const float*)D.M.buf, D.Tscr, D.KCt);
-    } else if (D.mfp32) {
-      launch_coarse_matrix<double, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
-                                  (const float*)D.M.buf, D.Tscr, D.KCt);
-    } else {
-      launch_coarse_matrix<double, double>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
-                                   (const double*)D.M.buf, D.Tscr, D.KCt);
-    }
-    launch_compact_kc(stream, D.d_kct_off, D.d_ntc, D.d_nc, D.d_kc_off, P.n_sub, D.max_nc, D.KCt, D.kc_compact);
-    HIPCHK(hipGetLastError());
+  for (int li = 0; li < (int)lev.size(); ++li) {
+    if ((st = enqueue_K(li))) return st;
+    if ((st = enqueue_rest(li))) return st;
   }
-  HIPCHK(hipStreamSynchronize(stream));
+  st = finish_numeric();
   t_setup = now() - t0;
+  if (st) return st;
   ready = true;
   return MLBDDC_OK;
 }
@@ -1525,6 +1643,13 @@ mlbddc_status mlbddc_destroy(mlbddc_t h) {
     (void)hipStreamSynchronize(h->h.fstream);
     (void)hipStreamDestroy(h->h.fstream);
   }
+  if (h->h.ustream) {
+    (void)hipStreamSynchronize(h->h.ustream);
+    (void)hipStreamDestroy(h->h.ustream);
+  }
+  if (h->h.h_s) (void)hipHostFree(h->h.h_s);
+  for (auto& c : h->h.staging) (void)hipHostFree(c.first);
+  if (h->h.ev_upl) (void)hipEventDestroy(h->h.ev_upl);
   if (h->h.ev_a) (void)hipEventDestroy(h->h.ev_a);
   if (h->h.ev_b) (void)hipEventDestroy(h->h.ev_b);
   if (h->h.ev_in) (void)hipEventDestroy(h->h.ev_in);
