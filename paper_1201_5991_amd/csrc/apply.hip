@@ -273,10 +273,17 @@ __global__ void __launch_bounds__(256) k_dot_final(int nb, const double* __restr
 // replayed from a captured graph): alpha_j goes to hist[2j]; beta_j, computed
 // at the start of iteration j+1, to hist[2j+1], after which the counter moves on.
 __global__ void k_pcg_alpha(double* s, double* hist, const int* it) {
+  if (s[S_DONE] != 0.0) return;
   s[S_ALPHA] = s[S_RZ] / s[S_PQ];
   if (hist) hist[2 * (*it)] = s[S_ALPHA];
 }
+__global__ void k_pcg_check(double* s, double rtol2) {
+  const double pq = s[S_PQ];
+  const bool stop = !(pq > 0.0) || !(pq < INFINITY) || s[S_RR] < rtol2 * s[S_GG];
+  if (s[S_DONE] != 0.0 || stop) s[S_DONE] = 1.0;
+}
 __global__ void k_pcg_beta(double* s, double* hist, int* it) {
+  if (s[S_DONE] != 0.0) return;
   s[S_BETA] = s[S_RZNEW] / s[S_RZ];
   s[S_RZ] = s[S_RZNEW];
   if (hist) hist[2 * (*it) + 1] = s[S_BETA];
@@ -285,6 +292,7 @@ __global__ void k_pcg_beta(double* s, double* hist, int* it) {
 __global__ void k_set_int(int* p, int v) { *p = v; }
 __global__ void k_pcg_update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                                 const double* __restrict__ q, const double* __restrict__ s) {
+  if (s[S_DONE] != 0.0) return;
   const double a = s[S_ALPHA];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     x[i] += a * p[i];
@@ -292,6 +300,7 @@ __global__ void k_pcg_update_xr(int64_t n, double* __restrict__ x, double* __res
   }
 }
 __global__ void k_pcg_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ s) {
+  if (s[S_DONE] != 0.0) return;
   const double b = s[S_BETA];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = z[i] + b * p[i];
@@ -390,6 +399,7 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
 void launch_pcg_alpha(hipStream_t st, double* s, double* hist, const int* it) {
   hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, st, s, hist, it);
 }
+void launch_pcg_check(hipStream_t st, double* s, double rtol2) { hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, st, s, rtol2); }
 void launch_pcg_beta(hipStream_t st, double* s, double* hist, int* it) {
   hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s, hist, it);
 }

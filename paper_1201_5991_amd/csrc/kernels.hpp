@@ -102,12 +102,16 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
 constexpr int DOT_BLOCKS = 1024;
 
 // Scalars used by the PCG kernels (device array).
-enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_NSCAL = 8 };
+// S_DONE: set (sticky) once the iteration converged or broke down; the
+// PCG update kernels then leave x, r, p and the history untouched.
+enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_DONE = 7, S_NSCAL = 8 };
 void launch_pcg_alpha(hipStream_t st, double* s, double* hist, const int* it);  // alpha = rz / pq
 void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
                           const double* s);                                    // x += a p, r -= a q
 void launch_pcg_beta(hipStream_t st, double* s, double* hist, int* it);         // beta = rznew / rz, rz = rznew, ++it
 void launch_set_int(hipStream_t st, int* p, int v);
+// s[S_DONE] = 1 if p^T S p <= 0 or not finite, or r^T r < rtol2 * g^T g (stays 1 once set).
+void launch_pcg_check(hipStream_t st, double* s, double rtol2);
 void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s);  // p = z + beta p
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
 

@@ -179,7 +179,8 @@ struct Handle {
   double* d_s = nullptr;           // scalars
   double* d_hist = nullptr;        // alpha/beta history
   double* d_dotp = nullptr;
-  double* h_s = nullptr;           // pinned mirror of the scalars
+  double* h_s = nullptr;           // pinned mirror of the scalars, then two per-iteration snapshots
+  hipEvent_t ev_snap[2] = {nullptr, nullptr};
   int32_t* d_it = nullptr;         // device iteration counter
   // HIP graph of one PCG iteration (captured on an internal stream)
   hipStream_t cap = nullptr;
@@ -891,7 +892,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if ((st = dalloc(&d_hist, 2 * (int64_t)max_hist))) return st;
   if ((st = dalloc(&d_dotp, DOT_BLOCKS))) return st;
   if ((st = dalloc(&d_it, 1))) return st;
-  if (!h_s) HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+  if (!h_s) HIPCHK(hipHostMalloc((void**)&h_s, sizeof(double) * 3 * S_NSCAL, hipHostMallocDefault));
   (void)ndofs;
   mark("PCG vectors");
   if ((st = join())) return st;
@@ -1313,6 +1314,7 @@ mlbddc_status Handle::pcg_body(bool first) {
   launch_pcg_alpha(stream, d_s, d_hist, d_it);
   launch_pcg_update_xr(stream, n, d_x, d_r, d_p, d_q, d_s);
   launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
+  launch_pcg_check(stream, d_s, opt.rtol * opt.rtol);
   if ((st = apply_interface(0, d_r, d_z))) return st;
   launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZNEW);
   HIPCHK(hipGetLastError());
@@ -1370,9 +1372,17 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
     launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZ);
     HIPCHK(hipMemcpyAsync(d_p, d_z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
     launch_set_int(stream, d_it, 0);
-    while (it < opt.max_iter) {
-      if (it == 0 || !opt.use_graph) {
-        if ((st = pcg_body(it == 0))) return st;
+    launch_fill(stream, 1, 0.0, d_s + S_DONE);
+    for (hipEvent_t& e : ev_snap)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // Iteration k+1 is queued before the host reads iteration k's scalars
+    // (snapshot k&1), so the device never waits for the host; once the
+    // device flags convergence or breakdown the queued iteration changes
+    // nothing (its products recompute the same scalars).
+    auto issue = [&](int k) -> mlbddc_status {
+      mlbddc_status sb;
+      if (k == 0 || !opt.use_graph) {
+        if ((sb = pcg_body(k == 0))) return sb;
       } else {
         if (!gexec) {
           hipGraph_t graph = nullptr;
@@ -1390,12 +1400,23 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
         }
         HIPCHK(hipGraphLaunch(gexec, stream));
       }
-      HIPCHK(hipMemcpyAsync(h_s, d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
+      HIPCHK(hipMemcpyAsync(h_s + S_NSCAL * (1 + (k & 1)), d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipEventRecord(ev_snap[k & 1], stream));
+      return MLBDDC_OK;
+    };
+    if ((st = issue(0))) return st;
+    while (true) {
+      if (it + 1 < opt.max_iter && (st = issue(it + 1))) return st;
+      HIPCHK(hipEventSynchronize(ev_snap[it & 1]));
+      const double* hs = h_s + S_NSCAL * (1 + (it & 1));
       ++it;
-      if (!(h_s[S_PQ] > 0.0) || !std::isfinite(h_s[S_PQ])) { breakdown = true; break; }
-      rel = std::sqrt(h_s[S_RR]) / gnorm;
-      if (rel < opt.rtol) { conv = true; break; }
+      rel = std::sqrt(hs[S_RR]) / gnorm;
+      if (hs[S_DONE] != 0.0) {
+        if (!(hs[S_PQ] > 0.0) || !std::isfinite(hs[S_PQ])) breakdown = true;
+        else conv = true;
+        break;
+      }
+      if (it >= opt.max_iter) break;
     }
   }
   if ((st = recover(d_x, u))) return st;
@@ -1648,6 +1669,8 @@ mlbddc_status mlbddc_destroy(mlbddc_t h) {
     (void)hipStreamDestroy(h->h.ustream);
   }
   if (h->h.h_s) (void)hipHostFree(h->h.h_s);
+  for (hipEvent_t e : h->h.ev_snap)
+    if (e) (void)hipEventDestroy(e);
   for (auto& c : h->h.staging) (void)hipHostFree(c.first);
   if (h->h.ev_upl) (void)hipEventDestroy(h->h.ev_upl);
   if (h->h.ev_a) (void)hipEventDestroy(h->h.ev_a);
