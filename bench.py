@@ -76,7 +76,7 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed PMC summary, or None."""
-    path = os.path.join(ROOT, "profiles", "k_update_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_tile_mm_traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):

@@ -374,6 +374,16 @@ __device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T*
 constexpr int LDU = TS + 16;  // keeps the four k-groups of a fragment read on distinct LDS banks
 constexpr int KH = TS / 2;    // columns of a tile staged at a time
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin by launch
+// index; this maps launch index b to a task index so that each XCD receives
+// one contiguous slice of the task list (tasks of the same matrix, which
+// share panel tiles, then meet in the same L2).
+__device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
+  constexpr int64_t NX = 8;
+  const int64_t x = b % NX, j = b / NX, q = n / NX, rem = n % NX;
+  return x * q + (x < rem ? x : rem) + j;
+}
+
 // Tile products on MFMA, one 64x64 output tile per workgroup:
 //   UPDATE  A_rs <- A_rs - sum_{kk=kf..klast} A_{r,kk} A_{s,kk}^T
 //   PANEL   A_rk <- A_rk inv(L_kk)^T
@@ -388,7 +398,7 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
                                                     int klast, T* A, const T* __restrict__ Inv) {
   __shared__ T sR[KH * LDU];
   __shared__ T sS[KH * LDU];
-  const uint64_t t = tasks[blockIdx.x];
+  const uint64_t t = tasks[xcd_slice(blockIdx.x, gridDim.x)];
   const int item = task_item(t), r = task_r(t), s = task_s(t);
   const int kf = PANEL ? s : task_kf(t);
   const int nsteps = PANEL ? 2 : 2 * (klast - kf + 1);
