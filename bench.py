@@ -74,15 +74,16 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, or None."""
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    (also when the summary was taken on another workload or kernel source)."""
     path = os.path.join(ROOT, "profiles", "k_tile_mm_traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     k = d.get("kernels", {}).get(kernel)
-    if not k or d.get("source_hash") != kernel_source_hash():
+    if not k or d.get("source_hash") != kernel_source_hash() or d.get("workload_name") != workload:
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -252,7 +253,7 @@ def main():
             "flops_per_launch": dprof["flops"] / max(dprof["launches"], 1),
             # lower bound on a launch's HBM bytes: each updated 64x64 tile read and written once
             "c_tile_bytes_per_launch": dprof["tiles"] / max(dprof["launches"], 1) * 2 * 64 * 64 * (4 if prec == "fp32" else 8)}
-    roof["traffic"] = measured_traffic(roof["kernel"])
+    roof["traffic"] = measured_traffic(roof["kernel"], w.name)
     line = {
         "metric": METRIC,
         "value": R["tts_s"],
