@@ -28,24 +28,29 @@ int classify(size_t n_subs, size_t n_nodes, int dim) {
   return G_EDGE;
 }
 
-// Run work(begin, end) over [0, n) split into contiguous ranges on up to 16 threads.
-template <typename F>
-void parallel_ranges(int32_t n, F&& work) {
+// Threads used for n work items (at most 16, at least 4 items per thread).
+int plan_threads(int64_t n) {
   unsigned hw = std::thread::hardware_concurrency();
   int T = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
-  T = std::min<int>(T, std::max(1, n / 4));
-  if (T <= 1) { work(0, n); return; }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(T, n / 4));
+}
+
+// Run work(t, begin, end) over [0, n) split into plan_threads(n) contiguous ranges.
+template <typename F>
+void parallel_ranges(int64_t n, F&& work) {
+  const int T = plan_threads(n);
+  if (T <= 1) { work(0, (int64_t)0, n); return; }
   std::vector<std::thread> th;
   for (int t = 0; t < T; ++t) {
-    int32_t b0 = (int32_t)((int64_t)n * t / T), b1 = (int32_t)((int64_t)n * (t + 1) / T);
-    th.emplace_back([&, b0, b1] { work(b0, b1); });
+    int64_t b0 = n * t / T, b1 = n * (t + 1) / T;
+    th.emplace_back([&, t, b0, b1] { work(t, b0, b1); });
   }
   for (auto& x : th) x.join();
 }
 
 // Build one level from its elements (node lists, -1 = eliminated node) and
 // the subdomain of every element.
-mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
+mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan) {
   const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
   auto t_last = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) {
@@ -72,9 +77,12 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     for (int32_t b = 0; b < ns; ++b) L.subs[b].elems.reserve(cnt[b]);
     for (int64_t e = 0; e < ne; ++e) L.subs[L.el_sub[e]].elems.push_back(e);
   }
-  parallel_ranges(ns, [&](int32_t b0, int32_t b1) {
-    std::vector<int32_t> stamp(L.n_nodes, -1);  // last subdomain that listed the node
-    for (int32_t b = b0; b < b1; ++b) {
+  if ((int)plan.scratch.size() < plan_threads(ns)) plan.scratch.resize(plan_threads(ns));
+  parallel_ranges(ns, [&](int t, int64_t b0, int64_t b1) {
+    PlanScratch& W = plan.scratch[t];
+    W.ensure(L.n_nodes);
+    std::vector<int32_t>& stamp = W.stamp;  // last subdomain that listed the node
+    for (int32_t b = (int32_t)b0; b < (int32_t)b1; ++b) {
       auto& v = sub_nodes[b];
       for (int64_t e : L.subs[b].elems)
         for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
@@ -84,6 +92,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
             v.push_back(n);
           }
         }
+      for (int64_t n : v) stamp[n] = -1;
       std::sort(v.begin(), v.end());
     }
   });
@@ -93,14 +102,18 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
 
   mark("subdomain node sets");
   // --- node -> subdomains (CSR, sorted by subdomain)
-  std::vector<int32_t> cnt(L.n_nodes + 1, 0);
+  std::vector<int32_t>& cnt = plan.w_cnt;
+  cnt.assign(L.n_nodes + 1, 0);
   for (int32_t b = 0; b < ns; ++b)
     for (int64_t n : sub_nodes[b]) cnt[n + 1]++;
-  std::vector<int64_t> nptr(L.n_nodes + 1, 0);
+  std::vector<int64_t>& nptr = plan.w_nptr;
+  nptr.assign(L.n_nodes + 1, 0);
   for (int64_t n = 0; n < L.n_nodes; ++n) nptr[n + 1] = nptr[n] + cnt[n + 1];
-  std::vector<int32_t> nsub(nptr[L.n_nodes]);
+  std::vector<int32_t>& nsub = plan.w_nsub;
+  nsub.resize(nptr[L.n_nodes]);
   {
-    std::vector<int64_t> pos(nptr.begin(), nptr.end() - 1);
+    std::vector<int64_t>& pos = plan.w_pos;
+    pos.assign(nptr.begin(), nptr.end() - 1);
     for (int32_t b = 0; b < ns; ++b)
       for (int64_t n : sub_nodes[b]) nsub[pos[n]++] = b;
   }
@@ -112,7 +125,8 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
   if (!L.top)
     for (int64_t n = 0; n < L.n_nodes; ++n)
       if (mult(n) >= 2) iface_nodes.push_back(n);
-  std::vector<int64_t> node_iface(L.n_nodes, -1);
+  std::vector<int64_t>& node_iface = plan.w_node_iface;
+  node_iface.assign(L.n_nodes, -1);
   for (size_t i = 0; i < iface_nodes.size(); ++i) node_iface[iface_nodes[i]] = (int64_t)i;
   L.iface_dofs.resize(iface_nodes.size() * nd);
   for (size_t i = 0; i < iface_nodes.size(); ++i)
@@ -187,13 +201,21 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
   std::vector<int32_t> sub_colors(ns, 0);
   std::vector<int32_t> sub_fail(ns, 0);
 
+  // interface flag of every node (a property of the level)
+  std::vector<char>& node_is_g = plan.w_is_g;
+  node_is_g.assign(L.n_nodes, 0);
+  if (!L.top)
+    for (int64_t n = 0; n < L.n_nodes; ++n) node_is_g[n] = mult(n) >= 2;
+
   // Per-subdomain work is independent: split the subdomains over threads, each
   // with its own node-indexed scratch (reset only where it was touched).
-  auto work = [&](int32_t b_begin, int32_t b_end) {
-  std::vector<int64_t> node_local(L.n_nodes, -1);  // node -> local node slot (interior or interface)
-  std::vector<char> node_is_g(L.n_nodes, 0);
-  std::vector<uint64_t> node_mask(L.n_nodes, 0);
-  for (int32_t b = b_begin; b < b_end; ++b) {
+  if ((int)plan.scratch.size() < plan_threads(ns)) plan.scratch.resize(plan_threads(ns));
+  auto work = [&](int t, int64_t b_begin, int64_t b_end) {
+  PlanScratch& W = plan.scratch[t];
+  W.ensure(L.n_nodes);
+  std::vector<int32_t>& node_local = W.node_local;  // node -> local node slot (interior or interface)
+  std::vector<uint64_t>& node_mask = W.node_mask;
+  for (int32_t b = (int32_t)b_begin; b < (int32_t)b_end; ++b) {
     SubPlan& S = L.subs[b];
     std::vector<int64_t> inodes, gnodes;
     for (int64_t n : sub_nodes[b]) (mult(n) >= 2 && !L.top ? gnodes : inodes).push_back(n);
@@ -201,17 +223,17 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     S.nG = (int64_t)gnodes.size() * nd;
     S.nIp = round_up(S.nI, TS);
     S.nGp = round_up(S.nG, TS);
-    for (size_t i = 0; i < inodes.size(); ++i) node_local[inodes[i]] = (int64_t)i;
+    for (size_t i = 0; i < inodes.size(); ++i) node_local[inodes[i]] = (int32_t)i;
 
     // interface nodes sorted by the first interior node they couple to, so that
     // the tile envelope of the interface rows is tight
     std::vector<int64_t> key(gnodes.size(), INT64_MAX);
-    for (size_t i = 0; i < gnodes.size(); ++i) { node_local[gnodes[i]] = (int64_t)i; node_is_g[gnodes[i]] = 1; }
+    for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int32_t)i;
     for (int64_t e : S.elems) {
       int64_t mn = INT64_MAX;
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
         int64_t n = L.el_nodes[j];
-        if (n >= 0 && !node_is_g[n]) mn = std::min(mn, node_local[n]);
+        if (n >= 0 && !node_is_g[n]) mn = std::min(mn, (int64_t)node_local[n]);
       }
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
         int64_t n = L.el_nodes[j];
@@ -226,7 +248,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     std::vector<int64_t> gsorted(gnodes.size());
     for (size_t i = 0; i < order.size(); ++i) gsorted[i] = gnodes[order[i]];
     gnodes.swap(gsorted);
-    for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int64_t)i;
+    for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int32_t)i;
 
     S.dofI.resize(S.nI);
     for (size_t i = 0; i < inodes.size(); ++i)
@@ -241,7 +263,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
 
     // local K index of a level DOF of this subdomain
     auto kidx = [&](int64_t n, int c) -> int64_t {
-      return node_is_g[n] ? S.nIp + node_local[n] * nd + c : node_local[n] * nd + c;
+      return node_is_g[n] ? S.nIp + (int64_t)node_local[n] * nd + c : (int64_t)node_local[n] * nd + c;
     };
     const int64_t nK = S.nIp + S.nGp + (L.augmentK ? S.nIp : 0);
     const int64_t ntK = nK / TS;
@@ -277,7 +299,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     for (int32_t gi : sub_globs[b]) {
       const Glob& g = L.globs[gi];
       for (int c = 0; c < nd; ++c) {
-        for (int64_t n : g.nodes) S.crow_col.push_back((int32_t)(node_local[n] * nd + c));
+        for (int64_t n : g.nodes) S.crow_col.push_back((int32_t)((int64_t)node_local[n] * nd + c));
         S.crow_ptr.push_back((int32_t)S.crow_col.size());
         S.coarse.push_back((int32_t)(g.coarse_node * nd + c));
       }
@@ -302,7 +324,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err) {
     }
     sub_colors[b] = ncol;
 
-    for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_is_g[n] = 0; node_mask[n] = 0; }
+    for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_mask[n] = 0; }
   }
   };
   parallel_ranges(ns, work);
@@ -327,46 +349,82 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
     return fail(err, MLBDDC_E_ARG, "empty mesh or missing arrays");
   if (in.n_levels > 2 && !in.sub_to_parent) return fail(err, MLBDDC_E_ARG, "sub_to_parent missing");
 
+  const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
+  auto t_last = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    auto t = std::chrono::steady_clock::now();
+    if (verbose)
+      std::fprintf(stderr, "[mlbddc plan] %-30s %8.2f ms\n", what, std::chrono::duration<double, std::milli>(t - t_last).count());
+    t_last = t;
+  };
+  // level storage of the previous plan is reused (capacity kept)
+  std::vector<LevelPlan> old = std::move(plan.levels);
   plan.levels.clear();
+  auto take_level = [&](size_t i) {
+    LevelPlan L;
+    if (i < old.size()) {
+      L.el_ptr.swap(old[i].el_ptr);
+      L.el_nodes.swap(old[i].el_nodes);
+      L.el_sub.swap(old[i].el_sub);
+      L.el_local_ptr.swap(old[i].el_local_ptr);
+      L.el_local.swap(old[i].el_local);
+      L.el_color.swap(old[i].el_color);
+      L.el_nodes.clear();
+    }
+    return L;
+  };
   plan.node_to_free.assign(in.n_nodes, -1);
   int64_t nf = 0;
   for (int64_t n = 0; n < in.n_nodes; ++n)
     if (!in.dirichlet || !in.dirichlet[n]) plan.node_to_free[n] = nf++;
   plan.n_free_nodes = nf;
 
-  // ---- level 1 from the mesh
-  LevelPlan L1;
+  // ---- level 1 from the mesh (element ranges on threads)
+  LevelPlan L1 = take_level(0);
   L1.level = 1;
   L1.dim = in.dim;
   L1.ndof = in.ndof;
   L1.n_nodes = nf;
   L1.n_dofs = nf * in.ndof;
-  int32_t nsub = 0;
+  const int npe = in.nodes_per_elem;
   L1.el_ptr.resize(in.n_elems + 1);
-  L1.el_nodes.resize(in.n_elems * in.nodes_per_elem);
+  L1.el_nodes.resize(in.n_elems * npe);
   L1.el_sub.resize(in.n_elems);
-  for (int64_t e = 0; e < in.n_elems; ++e) {
-    L1.el_ptr[e] = e * in.nodes_per_elem;
-    for (int a = 0; a < in.nodes_per_elem; ++a) {
-      int32_t n = in.elem_nodes[e * in.nodes_per_elem + a];
-      if (n < 0 || n >= in.n_nodes) return fail(err, MLBDDC_E_ARG, "element node out of range");
-      L1.el_nodes[e * in.nodes_per_elem + a] = plan.node_to_free[n];
+  std::vector<int32_t> t_nsub(plan_threads(in.n_elems), 0);
+  std::vector<char> t_bad(t_nsub.size(), 0);
+  parallel_ranges(in.n_elems, [&](int t, int64_t e0, int64_t e1) {
+    int32_t nsub_t = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+      L1.el_ptr[e] = e * npe;
+      for (int a = 0; a < npe; ++a) {
+        int32_t n = in.elem_nodes[e * npe + a];
+        if (n < 0 || n >= in.n_nodes) { t_bad[t] = 1; n = 0; }
+        L1.el_nodes[e * npe + a] = plan.node_to_free[n];
+      }
+      int32_t s = in.elem_to_sub[e];
+      if (s < 0) { t_bad[t] = 2; s = 0; }
+      L1.el_sub[e] = s;
+      nsub_t = std::max(nsub_t, s + 1);
     }
-    int32_t s = in.elem_to_sub[e];
-    if (s < 0) return fail(err, MLBDDC_E_ARG, "element without a subdomain");
-    L1.el_sub[e] = s;
-    nsub = std::max(nsub, s + 1);
+    t_nsub[t] = nsub_t;
+  });
+  for (char b : t_bad) {
+    if (b == 1) return fail(err, MLBDDC_E_ARG, "element node out of range");
+    if (b == 2) return fail(err, MLBDDC_E_ARG, "element without a subdomain");
   }
-  L1.el_ptr[in.n_elems] = in.n_elems * in.nodes_per_elem;
+  int32_t nsub = 0;
+  for (int32_t x : t_nsub) nsub = std::max(nsub, x);
+  L1.el_ptr[in.n_elems] = in.n_elems * npe;
   L1.n_sub = nsub;
-  mlbddc_status st = build_level(L1, in.constraints, err);
+  mark("level-1 element arrays");
+  mlbddc_status st = build_level(L1, in.constraints, err, plan);
   if (st != MLBDDC_OK) return st;
   plan.levels.push_back(std::move(L1));
 
   // ---- levels 2..L-1 and the top level from the pseudo-mesh
   for (int l = 2; l <= in.n_levels; ++l) {
     const LevelPlan& P = plan.levels.back();
-    LevelPlan L;
+    LevelPlan L = take_level(l - 1);
     L.level = l;
     L.dim = in.dim;
     L.ndof = in.ndof;
@@ -395,7 +453,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
       }
     }
     L.n_sub = ns;
-    st = build_level(L, L.top ? 0 : (in.constraints & ~MLBDDC_ALL_PRIMAL), err);
+    st = build_level(L, L.top ? 0 : (in.constraints & ~MLBDDC_ALL_PRIMAL), err, plan);
     if (st != MLBDDC_OK) return st;
     plan.levels.push_back(std::move(L));
   }

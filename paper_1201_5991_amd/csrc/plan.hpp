@@ -87,10 +87,32 @@ struct PlanInput {
   int constraints = MLBDDC_CORNERS | MLBDDC_EDGES | MLBDDC_FACES;
 };
 
+// Per-thread host scratch of the planner, kept by the plan between set-ups.
+// The node-indexed arrays are left clean after use (every touched entry is
+// reset), so a repeated set-up of the same mesh touches no new pages.
+struct PlanScratch {
+  std::vector<int32_t> node_local;      // node -> local slot in the current subdomain, -1
+  std::vector<uint64_t> node_mask;      // node -> colours of the subdomain's elements at the node, 0
+  std::vector<int32_t> stamp;           // node -> last subdomain that listed the node, -1
+  void ensure(int64_t n) {
+    if ((int64_t)node_local.size() < n) {
+      node_local.resize(n, -1);
+      node_mask.resize(n, 0);
+      stamp.resize(n, -1);
+    }
+  }
+};
+
 struct Plan {
   std::vector<LevelPlan> levels;        // BDDC levels 1..L-1, then the top (coarse) level
   std::vector<int64_t> node_to_free;    // mesh node -> free node (-1 for Dirichlet)
   int64_t n_free_nodes = 0;
+  // planner work space reused by the next build_plan on the same plan
+  std::vector<PlanScratch> scratch;
+  std::vector<int32_t> w_cnt;
+  std::vector<int64_t> w_nptr, w_pos, w_node_iface;
+  std::vector<int32_t> w_nsub;
+  std::vector<char> w_is_g;
 };
 
 // Build the whole plan.  Returns MLBDDC_OK or an error with a message.

@@ -323,7 +323,7 @@ struct Handle {
   mlbddc_status enqueue_rest(int li);
   mlbddc_status finish_numeric();
   mlbddc_status numeric();
-  bool lookahead = true;
+  bool lookahead = false;
   std::vector<std::array<int, 4>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel)
   int pick_panel(int job, bool fp32, int ntmax) const;
   mlbddc_status prepare_job(Job& J, bool fp32, int job = 0);
@@ -1484,7 +1484,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->device = 0;
   o->panel_tiles_precond = 0;
   o->tune_table = nullptr;
-  o->lookahead = 1;
+  o->lookahead = 0;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stream) {

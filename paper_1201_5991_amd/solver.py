@@ -113,7 +113,7 @@ class Solver:
 
     def __init__(self, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000, weights: str = "stiffness",
                  device: int = 0, panel_tiles: int = 0, use_graph: bool = False, panel_tiles_precond: int = 0,
-                 tune_table: Optional[str] = TUNE_TABLE, lookahead: bool = True):
+                 tune_table: Optional[str] = TUNE_TABLE, lookahead: bool = False):
         lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the BDDC library needs a HIP device")
