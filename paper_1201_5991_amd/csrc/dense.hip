@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) k_copy_block(const CopyDesc* __restrict__
 // S~ += (rho / m^2) 1 1^T on those DOFs; C row entries 1/m.
 template <typename TK, typename TP>
 __global__ void __launch_bounds__(256) k_constraints(const ConsDesc* __restrict__ d, const int32_t* __restrict__ cols,
-                                                     const TK* __restrict__ K, TP* P) {
+                                                     const TK* __restrict__ K, TP* P, double* rho_out) {
   const ConsDesc c = d[blockIdx.x];
   const int m = c.ptr1 - c.ptr0;
   __shared__ double red[256];
@@ -490,6 +490,7 @@ __global__ void __launch_bounds__(256) k_constraints(const ConsDesc* __restrict_
     __syncthreads();
   }
   const double rho = red[0];  // m * mean = sum of the diagonal entries
+  if (threadIdx.x == 0) rho_out[blockIdx.x] = rho;
   const double add = rho / ((double)m * (double)m);
   for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
     int a = idx / m, b = idx - a * m;
@@ -501,65 +502,22 @@ __global__ void __launch_bounds__(256) k_constraints(const ConsDesc* __restrict_
     P[c.p_off + packed_offset(c.c_row0, cols[c.ptr0 + i], c.p_nt)] = (TP)(1.0 / m);
 }
 
-// T_{i,c} = sum_s S_{i,s} Psi_{s,c}: S from the FP64 K matrix (symmetric,
-// lower tiles), Psi^T tile (c, s) from the preconditioner matrix.
-template <typename TK, typename TP>
-__global__ void __launch_bounds__(256) k_kc_stage1(const KcDesc* __restrict__ d, const TK* __restrict__ K,
-                                                   const TP* __restrict__ P, double* Tscr) {
-  __shared__ double sR[TS * LDT];
-  __shared__ double sS[TS * LDT];
-  const KcDesc c = d[blockIdx.z];
-  const int i = blockIdx.x, cc = blockIdx.y;
-  if (i >= c.ntg || cc >= c.ntc) return;
-  typename Mfma<double>::acc_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::zero();
-  for (int s = 0; s < c.ntg; ++s) {
-    if (i >= s) stage_tile<double, TK>(sR, K + c.k_off + tile_index(c.k_g0 + i, c.k_g0 + s, c.k_nt) * TE, false);
-    else stage_tile<double, TK>(sR, K + c.k_off + tile_index(c.k_g0 + s, c.k_g0 + i, c.k_nt) * TE, true);
-    stage_tile<double, TP>(sS, P + c.p_off + tile_index(c.p_c0 + cc, c.p_d0 + s, c.p_nt) * TE, false);
-    __syncthreads();
-    tile_nt<double>(acc, sR, sS);
-    __syncthreads();
-  }
-  double* g = Tscr + c.t_off + ((int64_t)cc * c.ntg + i) * TE;
-  for_acc<double>(acc, [&](int a, int b, double v) { g[b * TS + a] = v; });
-}
-
-// KC_{c1,c2} = sum_s Psi^T_{c1,s} T_{s,c2}
+// K_Ci = A_i^{-1} - W_i: after both elimination phases the coarse block of
+// the constrained-problem matrix holds -A_i^{-1} (A_i = C S~^{-1} C^T); since
+// C Psi = I, Psi^T S Psi = Psi^T S~ Psi - W = A^{-1} - W.  Lower triangle
+// read, full row-major block written.
 template <typename TP>
-__global__ void __launch_bounds__(256) k_kc_stage2(const KcDesc* __restrict__ d, const TP* __restrict__ P,
-                                                   const double* __restrict__ Tscr, double* KC) {
-  __shared__ double sR[TS * LDT];
-  __shared__ double sS[TS * LDT];
-  const KcDesc c = d[blockIdx.z];
-  const int c1 = blockIdx.x, c2 = blockIdx.y;
-  if (c1 >= c.ntc || c2 >= c.ntc) return;
-  typename Mfma<double>::acc_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<double>::zero();
-  for (int s = 0; s < c.ntg; ++s) {
-    stage_tile<double, TP>(sR, P + c.p_off + tile_index(c.p_c0 + c1, c.p_d0 + s, c.p_nt) * TE, false);
-    stage_tile<double, double>(sS, Tscr + c.t_off + ((int64_t)c2 * c.ntg + s) * TE, true);
-    __syncthreads();
-    tile_nt<double>(acc, sR, sS);
-    __syncthreads();
-  }
-  double* g = KC + c.kc_off + ((int64_t)c2 * c.ntc + c1) * TE;
-  for_acc<double>(acc, [&](int a, int b, double v) { g[b * TS + a] = v; });
-}
-
-__global__ void k_compact_kc(const int64_t* __restrict__ kc_off, const int32_t* __restrict__ ntc, const int32_t* __restrict__ ncv,
-                             const int64_t* __restrict__ out_off, const double* __restrict__ KC, double* out) {
-  const int item = blockIdx.y;
-  const int nc = ncv[item], nt = ntc[item];
+__global__ void k_coarse_from_M(const KcDesc* __restrict__ d, const TP* __restrict__ P, const double* __restrict__ rho,
+                                double* __restrict__ out) {
+  const KcDesc c = d[blockIdx.y];
+  const int nc = c.nc;
+  const int64_t c0 = (int64_t)c.p_c0 * TS;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nc * nc; idx += gridDim.x * blockDim.x) {
-    int a = idx / nc, b = idx - a * nc;  // row-major output (a, b)
-    int64_t tile = (int64_t)(b / TS) * nt + a / TS;
-    double v1 = KC[kc_off[item] + tile * TE + (b % TS) * TS + (a % TS)];
-    int64_t tile2 = (int64_t)(a / TS) * nt + b / TS;
-    double v2 = KC[kc_off[item] + tile2 * TE + (a % TS) * TS + (b % TS)];
-    out[out_off[item] + idx] = 0.5 * (v1 + v2);  // symmetrize rounding
+    const int a = idx / nc, b = idx - a * nc;
+    const int hi = a > b ? a : b, lo = a > b ? b : a;
+    double v = -(double)P[c.p_off + packed_offset(c0 + hi, c0 + lo, c.p_nt)];
+    if (a == b) v -= rho[c.rho_off + a];
+    out[c.out_off + idx] = v;
   }
 }
 
@@ -603,24 +561,18 @@ void launch_copy_block(hipStream_t st, const CopyDesc* d, int32_t nitems, int32_
 }
 
 template <typename TK, typename TP>
-void launch_constraints(hipStream_t st, const ConsDesc* d, int64_t nrows, const int32_t* cols, const TK* K, TP* P) {
+void launch_constraints(hipStream_t st, const ConsDesc* d, int64_t nrows, const int32_t* cols, const TK* K, TP* P,
+                        double* rho) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL((k_constraints<TK, TP>), dim3((unsigned)nrows), dim3(256), 0, st, d, cols, K, P);
+  hipLaunchKernelGGL((k_constraints<TK, TP>), dim3((unsigned)nrows), dim3(256), 0, st, d, cols, K, P, rho);
 }
 
-template <typename TK, typename TP>
-void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32_t max_ntg, int32_t max_ntc, const TK* K,
-                          const TP* P, double* Tscr, double* KC) {
-  if (nitems <= 0) return;
-  hipLaunchKernelGGL((k_kc_stage1<TK, TP>), dim3(max_ntg, max_ntc, nitems), dim3(256), 0, st, d, K, P, Tscr);
-  hipLaunchKernelGGL(k_kc_stage2<TP>, dim3(max_ntc, max_ntc, nitems), dim3(256), 0, st, d, P, Tscr, KC);
-}
-
-void launch_compact_kc(hipStream_t st, const int64_t* kc_off, const int32_t* ntc, const int32_t* nc, const int64_t* out_off,
-                       int32_t nitems, int32_t max_nc, const double* KC, double* out) {
-  if (nitems <= 0) return;
+template <typename TP>
+void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32_t max_nc, const TP* P, const double* rho,
+                          double* out) {
+  if (nitems <= 0 || max_nc <= 0) return;
   unsigned gx = (unsigned)std::max(1, std::min(64, (max_nc * max_nc + 255) / 256));
-  hipLaunchKernelGGL(k_compact_kc, dim3(gx, nitems), dim3(256), 0, st, kc_off, ntc, nc, out_off, KC, out);
+  hipLaunchKernelGGL((k_coarse_from_M<TP>), dim3(gx, (unsigned)nitems), dim3(256), 0, st, d, P, rho, out);
 }
 
 #define INST_T(T)                                                                                                         \
@@ -635,12 +587,14 @@ INST_T(float)
 #undef INST_T
 #define INST_KP(TK, TP)                                                                                              \
   template void launch_copy_block<TK, TP>(hipStream_t, const CopyDesc*, int32_t, int32_t, const TK*, TP*);          \
-  template void launch_constraints<TK, TP>(hipStream_t, const ConsDesc*, int64_t, const int32_t*, const TK*, TP*);  \
-  template void launch_coarse_matrix<TK, TP>(hipStream_t, const KcDesc*, int32_t, int32_t, int32_t, const TK*,      \
-                                             const TP*, double*, double*);
+  template void launch_constraints<TK, TP>(hipStream_t, const ConsDesc*, int64_t, const int32_t*, const TK*, TP*,   \
+                                           double*);
 INST_KP(double, double)
 INST_KP(double, float)
 INST_KP(float, float)
 #undef INST_KP
+template void launch_coarse_matrix<double>(hipStream_t, const KcDesc*, int32_t, int32_t, const double*, const double*,
+                                           double*);
+template void launch_coarse_matrix<float>(hipStream_t, const KcDesc*, int32_t, int32_t, const float*, const double*, double*);
 
 }  // namespace mlbddc

@@ -44,25 +44,25 @@ struct CopyDesc { int64_t src_off; int32_t src_nt, src_t0; int64_t dst_off; int3
 template <typename TK, typename TP>
 void launch_copy_block(hipStream_t st, const CopyDesc* d, int32_t nitems, int32_t max_blk, const TK* K, TP* P);
 
-// Add the constraint penalty rho_c c_c^T c_c to the S block and write the C rows.
+// Add the constraint penalty rho_c c_c^T c_c to the S block and write the C
+// rows; rho_c (the sum of the glob's diagonal entries of S) goes to rho[row].
 struct ConsDesc { int64_t kdiag_off; int32_t k_nt, k_g0; int64_t p_off; int32_t p_nt, c_row0; int32_t ptr0, ptr1; };
 template <typename TK, typename TP>
-void launch_constraints(hipStream_t st, const ConsDesc* d, int64_t nrows, const int32_t* cols, const TK* K, TP* P);
+void launch_constraints(hipStream_t st, const ConsDesc* d, int64_t nrows, const int32_t* cols, const TK* K, TP* P,
+                        double* rho);
 
-// Coarse matrices K_Ci = Psi_i^T S_i Psi_i (FP64 result, dense ncp x ncp per item).
+// Coarse matrices K_Ci = Psi_i^T S_i Psi_i = A_i^{-1} - W_i, read from the
+// eliminated constrained problem (its coarse block holds -A_i^{-1}) and the
+// penalties W_i = diag(rho); written row-major nc x nc (FP64) at out_off.
 struct KcDesc {
-  int64_t k_off; int32_t k_nt, k_g0;     // S: tile block starting at k_g0 in the K matrix (FP64)
-  int64_t p_off; int32_t p_nt, p_c0, p_d0; // Psi^T: tile rows p_c0.., tile cols p_d0.. in the preconditioner matrix
-  int32_t ntg, ntc;                      // tiles of the interface and of the coarse space
-  int64_t t_off;                         // scratch for S Psi: ntg x ntc tiles
-  int64_t kc_off;                        // output: ntc x ntc tiles
+  int64_t p_off; int32_t p_nt, p_c0;    // preconditioner matrix; first tile of its coarse block
+  int32_t nc;                           // coarse DOFs of the subdomain
+  int64_t out_off;                      // output offset (nc x nc)
+  int64_t rho_off;                      // first constraint row of the subdomain
 };
-template <typename TK, typename TP>
-void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32_t max_ntg, int32_t max_ntc,
-                          const TK* K, const TP* P, double* Tscr, double* KC);
-// Compact K_C tiles into row-major nc x nc blocks.
-void launch_compact_kc(hipStream_t st, const int64_t* kc_off, const int32_t* ntc, const int32_t* nc, const int64_t* out_off,
-                       int32_t nitems, int32_t max_nc, const double* KC, double* out);
+template <typename TP>
+void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32_t max_nc, const TP* P, const double* rho,
+                          double* out);
 
 // ------------------------------------------------------------------ apply
 // Batched tile-block matrix-vector products  y = alpha * op(A_blk) x (+ y).

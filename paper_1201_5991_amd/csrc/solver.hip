@@ -128,14 +128,10 @@ struct LevelDev {
   double* kc_compact = nullptr;
   std::vector<int64_t> kc_off;
   int64_t* d_kc_off = nullptr;
-  double* KCt = nullptr; double* Tscr = nullptr;
   std::vector<KcDesc> kcd_h;
   KcDesc* d_kcd = nullptr;
-  int32_t kc_max_ntg = 0, kc_max_ntc = 0, max_nc = 0;
-  std::vector<int64_t> kct_off_h;
-  int64_t* d_kct_off = nullptr;
-  int32_t* d_ntc = nullptr;
-  int32_t* d_nc = nullptr;
+  int32_t max_nc = 0;
+  double* d_rho = nullptr;  // constraint penalties rho_c, one per constraint row
   std::vector<CopyDesc> copy_h;
   CopyDesc* d_copy = nullptr;
   int32_t copy_max = 0;
@@ -816,44 +812,27 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
       if ((st = upload(&D.d_cons, D.cons_h))) return st;
       if ((st = upload(&D.d_ccols, ccols))) return st;
-      // coarse matrices
-      int64_t toff = 0, kcoff = 0, cmp = 0;
-      std::vector<int32_t> ntc(ns), ncv(ns);
+      // coarse matrices (read from the eliminated constrained problems)
+      int64_t cmp = 0, roff = 0;
       D.kc_off.resize(ns);
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
         int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
         KcDesc kd;
-        kd.k_off = D.K.off[b];
-        kd.k_nt = D.K.nt[b];
-        kd.k_g0 = (int32_t)(S.nIp / TS);
         kd.p_off = D.M.off[b];
         kd.p_nt = D.M.nt[b];
         kd.p_c0 = 2 * tG + tC;
-        kd.p_d0 = tG + tC;
-        kd.ntg = tG;
-        kd.ntc = tC;
-        kd.t_off = toff;
-        toff += (int64_t)tG * tC * TE;
-        kd.kc_off = kcoff;
-        D.kct_off_h.push_back(kcoff);
-        kcoff += (int64_t)tC * tC * TE;
+        kd.nc = S.nc;
+        kd.out_off = cmp;
+        kd.rho_off = roff;
         D.kcd_h.push_back(kd);
-        D.kc_max_ntg = std::max(D.kc_max_ntg, tG);
-        D.kc_max_ntc = std::max(D.kc_max_ntc, tC);
         D.max_nc = std::max(D.max_nc, S.nc);
-        ntc[b] = tC;
-        ncv[b] = S.nc;
         D.kc_off[b] = cmp;
         cmp += (int64_t)S.nc * S.nc;
+        roff += S.nc;
       }
       if ((st = upload(&D.d_kcd, D.kcd_h))) return st;
-      if ((st = upload(&D.d_kct_off, D.kct_off_h))) return st;
-      if ((st = upload(&D.d_ntc, ntc))) return st;
-      if ((st = upload(&D.d_nc, ncv))) return st;
-      if ((st = upload(&D.d_kc_off, D.kc_off))) return st;
-      if ((st = dalloc(&D.Tscr, std::max<int64_t>(toff, 1)))) return st;
-      if ((st = dalloc(&D.KCt, std::max<int64_t>(kcoff, 1)))) return st;
+      if ((st = dalloc(&D.d_rho, std::max<int64_t>(roff, 1)))) return st;
       if ((st = dalloc(&D.kc_compact, std::max<int64_t>(cmp, 1)))) return st;
       // M-job tile mat-vecs
       std::vector<MvDesc> g, pn, pt;
@@ -1011,9 +990,18 @@ mlbddc_status Handle::validate_level(int li, int part) {
     if (!mv_ok(D.mvG, D.M, D.nG_flat, D.nG_flat)) return bad(L + "G mat-vec");
     if (!mv_ok(D.mvPsiN, D.M, D.nG_flat, D.nC_flat)) return bad(L + "Psi^T mat-vec");
     if (!mv_ok(D.mvPsiT, D.M, D.nC_flat, D.nG_flat)) return bad(L + "Psi mat-vec");
-    for (const KcDesc& k : D.kcd_h)
-      if (k.k_g0 + k.ntg > k.k_nt || k.p_c0 + k.ntc > k.p_nt || k.p_d0 + k.ntg > k.p_nt || k.p_c0 < k.p_d0 + k.ntg)
-        return bad(L + "coarse matrix descriptor");
+    {
+      int64_t rows = 0, cmp = 0;
+      for (size_t b = 0; b < D.kcd_h.size(); ++b) {
+        const KcDesc& k = D.kcd_h[b];
+        if ((int64_t)k.p_c0 * TS + k.nc > (int64_t)k.p_nt * TS || k.nc > D.max_nc || k.rho_off != rows || k.out_off != cmp ||
+            k.p_off + packed_tiles(k.p_nt) * TE > D.M.elems || k.p_nt != D.M.nt[b])
+          return bad(L + "coarse matrix descriptor");
+        rows += k.nc;
+        cmp += (int64_t)k.nc * k.nc;
+      }
+      if (rows != (int64_t)D.cons_h.size()) return bad(L + "constraint rows vs coarse DOFs");
+    }
     for (const CopyDesc& c : D.copy_h)
       if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt) return bad(L + "copy descriptor");
     for (size_t b = 0; b < P.subs.size(); ++b) {
@@ -1085,33 +1073,24 @@ mlbddc_status Handle::enqueue_rest(int li) {
   if (D.kfp32) {  // K is FP32 only when M is FP32
     launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
     launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
-                                     (float*)D.M.buf);
+                                     (float*)D.M.buf, D.d_rho);
     launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
   } else if (D.mfp32) {
     launch_copy_block<double, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (float*)D.M.buf);
     launch_constraints<double, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
-                                      (float*)D.M.buf);
+                                      (float*)D.M.buf, D.d_rho);
     launch_set_diag<float>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (float*)D.M.buf);
   } else {
     launch_copy_block<double, double>(stream, D.d_copy, P.n_sub, D.copy_max, (const double*)D.K.buf, (double*)D.M.buf);
     launch_constraints<double, double>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const double*)D.K.buf,
-                                       (double*)D.M.buf);
+                                       (double*)D.M.buf, D.d_rho);
     launch_set_diag<double>(stream, D.d_msegs, (int64_t)D.msegs_h.size(), D.mseg_max, (double*)D.M.buf);
   }
   HIPCHK(hipGetLastError());
   if ((st = factor(D.M, P.level, true))) return st;
-  // K_Ci = Psi^T S Psi
-  if (D.kfp32) {
-    launch_coarse_matrix<float, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const float*)D.K.buf,
-                                       (const float*)D.M.buf, D.Tscr, D.KCt);
-  } else if (D.mfp32) {
-    launch_coarse_matrix<double, float>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
-                                (const float*)D.M.buf, D.Tscr, D.KCt);
-  } else {
-    launch_coarse_matrix<double, double>(stream, D.d_kcd, P.n_sub, D.kc_max_ntg, D.kc_max_ntc, (const double*)D.K.buf,
-                                 (const double*)D.M.buf, D.Tscr, D.KCt);
-  }
-  launch_compact_kc(stream, D.d_kct_off, D.d_ntc, D.d_nc, D.d_kc_off, P.n_sub, D.max_nc, D.KCt, D.kc_compact);
+  // K_Ci = Psi^T S Psi = A^{-1} - W
+  if (D.mfp32) launch_coarse_matrix<float>(stream, D.d_kcd, P.n_sub, D.max_nc, (const float*)D.M.buf, D.d_rho, D.kc_compact);
+  else launch_coarse_matrix<double>(stream, D.d_kcd, P.n_sub, D.max_nc, (const double*)D.M.buf, D.d_rho, D.kc_compact);
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
