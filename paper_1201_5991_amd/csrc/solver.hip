@@ -268,15 +268,19 @@ struct Handle {
     stage_used += bytes;
     return MLBDDC_OK;
   }
+  mlbddc_status ensure_ustream() {
+    if (!ustream) {
+      HIPCHK(hipStreamCreateWithFlags(&ustream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ev_upl, hipEventDisableTiming));
+    }
+    return MLBDDC_OK;
+  }
   template <typename T>
   mlbddc_status upload(T** p, const std::vector<T>& v) {
     mlbddc_status st = dalloc(p, (int64_t)v.size());
     if (st) return st;
     if (!v.empty()) {
-      if (!ustream) {
-        HIPCHK(hipStreamCreateWithFlags(&ustream, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&ev_upl, hipEventDisableTiming));
-      }
+      if ((st = ensure_ustream())) return st;
       char* h = nullptr;
       if ((st = stage(sizeof(T) * v.size(), &h))) return st;
       std::memcpy(h, v.data(), sizeof(T) * v.size());
@@ -315,8 +319,8 @@ struct Handle {
 
   mlbddc_status setup(const mlbddc_mesh* mesh, const mlbddc_partition* part);
   mlbddc_status validate_level(int li, int part);
-  mlbddc_status enqueue_K(int li);
-  mlbddc_status enqueue_rest(int li);
+  mlbddc_status enqueue_K(int li, bool zero);
+  mlbddc_status enqueue_rest(int li, bool zero);
   mlbddc_status finish_numeric();
   mlbddc_status numeric();
   bool lookahead = false;
@@ -405,7 +409,10 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   if (st) return st;
   J.buf = b;
   J.inv = iv;
-  (void)esz;
+  // zero the matrices on the upload stream now, while the host keeps preparing
+  // (the upload fence orders it before the assembly)
+  if ((st = ensure_ustream())) return st;
+  HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
@@ -509,7 +516,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     const int dev = opt.device;
     pending = std::async(std::launch::async, [this, li, kjob, dev]() -> mlbddc_status {
       if (hipSetDevice(dev) != hipSuccess) return herr("hipSetDevice", hipGetLastError());
-      return kjob ? enqueue_K(li) : enqueue_rest(li);
+      return kjob ? enqueue_K(li, false) : enqueue_rest(li, false);
     });
   };
   PlanInput in;
@@ -906,24 +913,40 @@ mlbddc_status Handle::validate_level(int li, int part) {
       if (J.nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
     }
     if (ni >= (1u << 24)) return bad(L + "too many matrices for the task encoding");
-    for (const FactorLaunch& F : J.sched.launches) {
-      for (int64_t q = F.first; q < F.first + F.count; ++q) {
-        uint64_t t = J.sched.tasks[q];
-        size_t it = (size_t)task_item(t);
-        int r = task_r(t), c = task_s(t), kf = task_kf(t);
-        if (it >= ni) return bad(L + "task item");
-        int nt = J.nt[it], ee = J.items[it].e1 + J.items[it].e2;
-        if (r >= nt || c > r) return bad(L + "task tile");
-        switch (F.kind) {
-          case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return bad(L + "diag task"); break;
-          case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return bad(L + "panel task"); break;
-          case L_INPANEL: if (c != F.k || kf >= F.k) return bad(L + "in-panel task"); break;
-          case L_TRAIL: if (c <= F.k || kf > F.k) return bad(L + "trailing task"); break;
-          case L_NEGATE: if (c < J.items[it].e1) return bad(L + "negate task"); break;
-          default: return bad(L + "task kind");
+    // every task against its launch kind and its matrix (launches split over threads)
+    auto check = [&](size_t l0, size_t l1) -> const char* {
+      for (size_t l = l0; l < l1; ++l) {
+        const FactorLaunch& F = J.sched.launches[l];
+        if (F.first < 0 || F.count < 0 || F.first + F.count > (int64_t)J.sched.tasks.size()) return "task range";
+        for (int64_t q = F.first; q < F.first + F.count; ++q) {
+          uint64_t t = J.sched.tasks[q];
+          size_t it = (size_t)task_item(t);
+          int r = task_r(t), c = task_s(t), kf = task_kf(t);
+          if (it >= ni) return "task item";
+          int nt = J.nt[it], ee = J.items[it].e1 + J.items[it].e2;
+          if (r >= nt || c > r) return "task tile";
+          switch (F.kind) {
+            case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return "diag task"; break;
+            case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return "panel task"; break;
+            case L_INPANEL: if (c != F.k || kf >= F.k) return "in-panel task"; break;
+            case L_TRAIL: if (c <= F.k || kf > F.k) return "trailing task"; break;
+            case L_NEGATE: if (c < J.items[it].e1) return "negate task"; break;
+            default: return "task kind";
+          }
         }
       }
+      return nullptr;
+    };
+    const size_t nl = J.sched.launches.size();
+    const size_t T = std::min<size_t>(8, std::max<size_t>(1, J.sched.tasks.size() / 100000));
+    std::vector<std::future<const char*>> parts;
+    for (size_t t = 1; t < T; ++t) parts.push_back(std::async(std::launch::async, check, nl * t / T, nl * (t + 1) / T));
+    const char* why = check(0, nl / T);
+    for (auto& f : parts) {
+      const char* w = f.get();
+      if (!why) why = w;
     }
+    if (why) return bad(L + why);
     return MLBDDC_OK;
   };
   auto seg_ok = [&](const std::vector<DiagSeg>& v) {
@@ -1019,12 +1042,12 @@ mlbddc_status Handle::validate_level(int li, int part) {
 // Numeric set-up of level li, first part: assemble K (FP64 or FP32), take
 // the interface weights from its diagonal, factor the K job.  Queued on the
 // library stream only; errors are collected by finish_numeric().
-mlbddc_status Handle::enqueue_K(int li) {
+mlbddc_status Handle::enqueue_K(int li, bool zero) {
   mlbddc_status st;
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   // assemble K
-  HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
+  if (zero) HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
   for (int c = 0; c < P.n_colors; ++c) {
     int64_t n = D.color_ptr[c + 1] - D.color_ptr[c];
     const int64_t* el = D.d_elems_by_color + D.color_ptr[c];
@@ -1063,13 +1086,13 @@ mlbddc_status Handle::enqueue_K(int li) {
 
 // Second part: the constrained local problems (M job) and the coarse
 // matrices Psi^T S Psi that the next level assembles.
-mlbddc_status Handle::enqueue_rest(int li) {
+mlbddc_status Handle::enqueue_rest(int li, bool zero) {
   mlbddc_status st;
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   if (P.top) return MLBDDC_OK;
   // preconditioner matrices
-  HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
+  if (zero) HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
   if (D.kfp32) {  // K is FP32 only when M is FP32
     launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
     launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
@@ -1119,8 +1142,8 @@ mlbddc_status Handle::numeric() {
   double t0 = now();
   mlbddc_status st;
   for (int li = 0; li < (int)lev.size(); ++li) {
-    if ((st = enqueue_K(li))) return st;
-    if ((st = enqueue_rest(li))) return st;
+    if ((st = enqueue_K(li, true))) return st;
+    if ((st = enqueue_rest(li, true))) return st;
   }
   st = finish_numeric();
   t_setup = now() - t0;
