@@ -465,11 +465,28 @@ namespace {
 enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_N = 6 };
 
 // All tasks of one item, in (tile column, step kind) order: emit(k, kind, task, flops).
+// Rows enter a sorted active list when the elimination reaches their
+// envelope, so the loops visit only rows whose tiles are in use.
 template <typename F>
 void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
   const double t3 = (double)TS * TS * TS;
   const int e1 = it.e1, e2 = it.e2, nt = it.nt;
   const int32_t* env = it.env;
+  // rows bucketed by envelope (counting sort, rows increasing within a bucket)
+  std::vector<int32_t> start(nt + 1, 0), rows(nt);
+  for (int r = 0; r < nt; ++r) start[std::min(std::max(env[r], 0), nt - 1) + 1]++;
+  for (int e = 0; e < nt; ++e) start[e + 1] += start[e];
+  {
+    std::vector<int32_t> pos(start.begin(), start.end() - 1);
+    for (int r = 0; r < nt; ++r) rows[pos[std::min(std::max(env[r], 0), nt - 1)]++] = r;
+  }
+  std::vector<int32_t> act;  // rows with env <= current column, increasing
+  act.reserve(nt);
+  auto admit = [&](int e) {
+    if (e >= nt) return;
+    for (int q = start[e]; q < start[e + 1]; ++q) act.insert(std::upper_bound(act.begin(), act.end(), rows[q]), rows[q]);
+  };
+  admit(0);
   for (int k = 0; k < e1 + e2; ++k) {
     int ph0 = k < e1 ? 0 : e1, ph1 = k < e1 ? e1 : e1 + e2;
     int k0 = ph0 + ((k - ph0) / panel) * panel;
@@ -477,22 +494,23 @@ void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookah
     if (k == e1 && e2 > 0)
       for (int s = e1; s < nt; ++s)
         for (int r = s; r < nt; ++r) emit(k, SK_NEG, pack_task(b, r, s, 0), 0.0);
-    if (k > k0)
-      for (int r = k; r < nt; ++r)
-        if (std::max(env[r], env[k]) <= k - 1) emit(k, SK_INP, pack_task(b, r, k, k0), 2.0 * t3 * (k - k0));
+    // act holds the rows with env <= k - 1 here
+    if (k > k0 && env[k] <= k - 1)
+      for (auto q = std::lower_bound(act.begin(), act.end(), k); q != act.end(); ++q)
+        emit(k, SK_INP, pack_task(b, *q, k, k0), 2.0 * t3 * (k - k0));
+    if (k > 0) admit(k);  // now env <= k
     emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
-    for (int r = k + 1; r < nt; ++r)
-      if (env[r] <= k) emit(k, SK_PAN, pack_task(b, r, k, 0), 2.0 * t3);
+    const auto first_after_k = std::upper_bound(act.begin(), act.end(), k);
+    for (auto q = first_after_k; q != act.end(); ++q) emit(k, SK_PAN, pack_task(b, *q, k, 0), 2.0 * t3);
     if (k == kend - 1) {
       // columns of the item's next panel (same phase): with look-ahead they are
       // updated first, on the critical stream
       int nxt_end = k + 1;
       if (lookahead && k + 1 < ph1) nxt_end = std::min(k + 1 + panel, ph1);
-      for (int s = k + 1; s < nt; ++s) {
-        if (env[s] > k) continue;
+      for (auto qs = first_after_k; qs != act.end(); ++qs) {
+        const int s = *qs;
         const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
-        for (int r = s; r < nt; ++r)
-          if (env[r] <= k) emit(k, dst, pack_task(b, r, s, k0), 2.0 * t3 * (k - k0 + 1));
+        for (auto qr = qs; qr != act.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0), 2.0 * t3 * (k - k0 + 1));
       }
     }
   }
