@@ -151,90 +151,110 @@ __global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* 
 
 // ------------------------------------------------------------------ trsv
 // Blocked triangular solve with the interior factor of one subdomain per
-// workgroup.  Block row k: the four wavefronts split the envelope tiles of
-// the row (tile s goes to wave s mod 4); lane a accumulates entry a of
-// sum_s L_ks v_s (or, transposed, entry b of sum_r L_rk^T u_r from a tile
-// staged in the wave's own LDS slot so that global loads stay coalesced);
-// wavefront 0 then applies the stored inverse of the diagonal tile.
-constexpr int LDV = TS + 1;
+// workgroup of eight wavefronts.  Block row k:
+//   v_k <- W_k (v_k - sum_{s<k} L_ks v_s)          (forward, W_k = L_kk^{-1})
+//   v_k <- W_k^T (v_k - sum_{r>k} L_rk^T v_r)      (backward)
+// Wavefronts 1..7 take the envelope tiles of the block row in turn; each
+// loads a whole tile (64 values per lane in flight) and the matching block of
+// v (broadcast through LDS).  Wavefront 0 meanwhile stages W_k in LDS, so the
+// product with the diagonal inverse at the end of the step waits on no global
+// load.
+// Forward: lane a holds row a of a tile (coalesced columns); backward: lane b
+// holds column b (16-byte loads along the column).
+constexpr int TRSV_WAVES = 8;
 
-__device__ inline double tile_dot_col(const double* __restrict__ L, const double* __restrict__ v, int lane) {
-  // sum_b L(lane, b) v[b] (L column-major in global memory, v broadcast from LDS)
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll 4
+__device__ inline void load_tile_rows(const double* __restrict__ g, int lane, double (&a)[TS]) {
+#pragma unroll
+  for (int b = 0; b < TS; ++b) a[b] = g[b * TS + lane];
+}
+__device__ inline void load_tile_cols(const double* __restrict__ g, int lane, double (&a)[TS]) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* c = reinterpret_cast<const d2*>(g + lane * TS);
+#pragma unroll
+  for (int q = 0; q < TS / 2; ++q) {
+    const d2 v = c[q];
+    a[2 * q] = v[0];
+    a[2 * q + 1] = v[1];
+  }
+}
+__device__ inline double dot64(const double (&a)[TS], const double* __restrict__ x) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* x2 = reinterpret_cast<const d2*>(x);
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
   for (int b = 0; b < TS; b += 4) {
-    a0 += L[(b + 0) * TS + lane] * v[b + 0];
-    a1 += L[(b + 1) * TS + lane] * v[b + 1];
-    a2 += L[(b + 2) * TS + lane] * v[b + 2];
-    a3 += L[(b + 3) * TS + lane] * v[b + 3];
+    const d2 u = x2[b / 2], v = x2[b / 2 + 1];
+    s0 += a[b] * u[0];
+    s1 += a[b + 1] * u[1];
+    s2 += a[b + 2] * v[0];
+    s3 += a[b + 3] * v[1];
   }
-  return (a0 + a1) + (a2 + a3);
+  return (s0 + s1) + (s2 + s3);
 }
 
-__device__ inline double tile_dot_row_lds(const double* __restrict__ sT, const double* __restrict__ v, int lane) {
-  // sum_a T(a, lane) v[a] with T staged column-major in LDS (leading dimension LDV)
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll 4
-  for (int q = 0; q < TS; q += 4) {
-    a0 += sT[lane * LDV + q + 0] * v[q + 0];
-    a1 += sT[lane * LDV + q + 1] * v[q + 1];
-    a2 += sT[lane * LDV + q + 2] * v[q + 2];
-    a3 += sT[lane * LDV + q + 3] * v[q + 3];
-  }
-  return (a0 + a1) + (a2 + a3);
-}
-
-__device__ inline void stage_wave(double* __restrict__ sT, const double* __restrict__ g, int lane) {
-#pragma unroll 8
-  for (int b = 0; b < TS; ++b) sT[b * LDV + lane] = g[b * TS + lane];
-}
-
-__global__ void __launch_bounds__(256) k_trsv(int trans, const TrsvDesc* __restrict__ d, const double* __restrict__ A,
-                                              const double* __restrict__ Inv, double* v) {
+__global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvDesc* __restrict__ d,
+                                                         const double* __restrict__ A, const double* __restrict__ Inv,
+                                                         double* v) {
   const TrsvDesc D = d[blockIdx.x];
-  __shared__ double sT[4][TS * LDV];
-  __shared__ double sv[4][TS];
-  __shared__ double red[4][TS];
+  constexpr int LDW = TS + 1;
+  __shared__ double sw[TS * LDW];
+  __shared__ double sv[TRSV_WAVES][TS];
+  __shared__ double red[TRSV_WAVES][TS];
   __shared__ double acc[TS];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const double* base = A + D.a_off;
   double* vv = v + D.v_off;
   for (int step = 0; step < D.nti; ++step) {
     const int k = trans ? D.nti - 1 - step : step;
     double part = 0.0;
-    if (!trans) {
+    double a[TS];
+    if (w == 0) {
+      // stage W_k (column-major, padded) while the other wavefronts work
+      load_tile_rows(Inv + D.inv_off + (int64_t)k * TE, lane, a);
+#pragma unroll
+      for (int b = 0; b < TS; ++b) sw[b * LDW + lane] = a[b];
+    } else if (!trans) {
       const int s0 = D.env ? D.env[k] : 0;
-      for (int s = s0 + w; s < k; s += 4) {
+      for (int s = s0 + w - 1; s < k; s += TRSV_WAVES - 1) {
         sv[w][lane] = vv[(int64_t)s * TS + lane];
+        load_tile_rows(base + tile_index(k, s, D.a_nt) * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
-        part += tile_dot_col(base + tile_index(k, s, D.a_nt) * TE, sv[w], lane);
+        part += dot64(a, sv[w]);
         __builtin_amdgcn_wave_barrier();
       }
     } else {
-      for (int r = k + 1 + w; r < D.nti; r += 4) {
+      for (int r = k + w; r < D.nti; r += TRSV_WAVES - 1) {
         if (D.env && D.env[r] > k) continue;
         sv[w][lane] = vv[(int64_t)r * TS + lane];
-        stage_wave(sT[w], base + tile_index(r, k, D.a_nt) * TE, lane);
+        load_tile_cols(base + tile_index(r, k, D.a_nt) * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
-        part += tile_dot_row_lds(sT[w], sv[w], lane);
+        part += dot64(a, sv[w]);
         __builtin_amdgcn_wave_barrier();
       }
     }
     red[w][lane] = part;
     __syncthreads();
     if (w == 0) {
-      acc[lane] = vv[(int64_t)k * TS + lane] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 1; q < TRSV_WAVES; ++q) sum += red[q][lane];
+      acc[lane] = vv[(int64_t)k * TS + lane] - sum;
       __builtin_amdgcn_wave_barrier();
-      const double* W = Inv + D.inv_off + (int64_t)k * TE;
-      double x;
+      double s0 = 0, s1 = 0;
       if (!trans) {
-        x = tile_dot_col(W, acc, lane);
+#pragma unroll
+        for (int b = 0; b < TS; b += 2) {
+          s0 += sw[b * LDW + lane] * acc[b];
+          s1 += sw[(b + 1) * LDW + lane] * acc[b + 1];
+        }
       } else {
-        stage_wave(sT[0], W, lane);
-        __builtin_amdgcn_wave_barrier();
-        x = tile_dot_row_lds(sT[0], acc, lane);
+#pragma unroll
+        for (int q = 0; q < TS; q += 2) {
+          s0 += sw[lane * LDW + q] * acc[q];
+          s1 += sw[lane * LDW + q + 1] * acc[q + 1];
+        }
       }
-      vv[(int64_t)k * TS + lane] = x;
+      vv[(int64_t)k * TS + lane] = s0 + s1;
     }
     __syncthreads();
   }
@@ -388,7 +408,7 @@ void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in,
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
                  double* v) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(256), 0, st, transposed ? 1 : 0, d, A, Inv, v);
+  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(TRSV_WAVES * 64), 0, st, transposed ? 1 : 0, d, A, Inv, v);
 }
 
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out) {

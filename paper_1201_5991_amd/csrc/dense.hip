@@ -146,6 +146,19 @@ __device__ inline float row_bcast(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, false));
 }
 
+// 1/sqrt(x) for a positive finite pivot: the hardware estimate refined by one
+// Newton step y <- y + y (1/2 - x y^2 / 2) (relative error ~3e-14 in FP64).
+__device__ inline double rsqrt_pivot(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double r = fma(-0.5 * x * y, y, 0.5);
+  return fma(y, r, y);
+}
+__device__ inline float rsqrt_pivot(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float r = fmaf(-0.5f * x * y, y, 0.5f);
+  return fmaf(y, r, y);
+}
+
 // Compile-time loop: f(integral_constant<J>) for J = B..E-1.
 template <int B, int E, typename F>
 __device__ inline void static_for(F&& f) {
@@ -213,7 +226,7 @@ __device__ inline void store16t(const typename Mfma<T>::acc_t& acc, T* O) {
 // non-positive pivot is reported in err (first failing item, then its
 // column) and turns the rest of the tile into NaN.
 template <typename T>
-__global__ void __launch_bounds__(256, 4) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
+__global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
@@ -249,7 +262,7 @@ __global__ void __launch_bounds__(256, 4) k_diag(const uint64_t* __restrict__ ta
         const bool ok = piv > (T)0;
         badcol = (!ok && badcol < 0) ? j0 + j : badcol;
         piv = ok ? piv : (T)NAN;
-        const T sq = sqrt(piv), inv = (T)1 / sq;
+        const T inv = rsqrt_pivot(piv), sq = piv * inv;
         d[j] = i > j ? d[j] * inv : (i == j ? sq : (T)0);
         static_for<j + 1, 16>([&](auto M) {
           constexpr int m = decltype(M)::value;
