@@ -99,21 +99,37 @@ __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __rest
   }
 }
 
+// Sum of the partial tiles of one output tile: the four wavefronts take every
+// fourth partial (two accumulators each, loads unrolled), then wavefront 0
+// adds the four sums in a fixed order.
 template <typename TA, typename TY>
-__global__ void __launch_bounds__(64) k_mv_reduce(int mode, const MvDesc* __restrict__ d, const TA* __restrict__ P, TY* y,
-                                                  double alpha, int accumulate) {
+__global__ void __launch_bounds__(256) k_mv_reduce(int mode, const MvDesc* __restrict__ d, const TA* __restrict__ P, TY* y,
+                                                   double alpha, int accumulate) {
   const MvDesc D = d[blockIdx.y];
   const int i = blockIdx.x;
   const int nout = mode == MV_T ? D.nc : D.nr;
   const int nsum = mode == MV_N ? D.nc : D.nr;
   if (i >= nout) return;
-  const TA* p = P + D.p_off + (int64_t)i * nsum * TS + threadIdx.x;
-  double acc = 0.0;
-  for (int j = 0; j < nsum; ++j) acc += (double)p[(int64_t)j * TS];
-  TY* yy = y + D.y_off + (int64_t)i * TS + threadIdx.x;
-  double v = alpha * acc;
-  if (accumulate) v += (double)*yy;
-  *yy = (TY)v;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  __shared__ double red[4][TS];
+  const TA* p = P + D.p_off + (int64_t)i * nsum * TS + lane;
+  double a0 = 0.0, a1 = 0.0;
+  int j = q;
+#pragma unroll 4
+  for (; j + 4 < nsum; j += 8) {
+    a0 += (double)p[(int64_t)j * TS];
+    a1 += (double)p[(int64_t)(j + 4) * TS];
+  }
+  if (j < nsum) a0 += (double)p[(int64_t)j * TS];
+  red[q][lane] = a0 + a1;
+  __syncthreads();
+  if (q == 0) {
+    const double acc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    TY* yy = y + D.y_off + (int64_t)i * TS + lane;
+    double v = alpha * acc;
+    if (accumulate) v += (double)*yy;
+    *yy = (TY)v;
+  }
 }
 
 // --------------------------------------------------------- gather / scatter
@@ -382,7 +398,7 @@ void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, i
   if (nitems <= 0 || total_tiles <= 0) return;
   hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
                      partials);
-  hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(64), 0, st, mode, d,
+  hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d,
                      partials, y, alpha, accumulate ? 1 : 0);
 }
 
