@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <iterator>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -46,6 +47,224 @@ void parallel_ranges(int64_t n, F&& work) {
     th.emplace_back([&, t, b0, b1] { work(t, b0, b1); });
   }
   for (auto& x : th) x.join();
+}
+
+// ------------------------------------------------------ nested dissection
+// Interior DOFs below which a subdomain keeps one group in node order, and
+// the largest part left undivided (in DOFs).
+constexpr int64_t ND_MIN_DOFS = 16 * TS;
+constexpr int64_t ND_LEAF_DOFS = 20 * TS;
+
+// Nested-dissection order of a subdomain's interior nodes 0..n-1 (adjacency
+// CSR ptr / adj).  The separators are level sets of breadth-first distances
+// grown from the interior nodes next to one side of the subdomain (dist[s],
+// one array per side, INT32_MAX where unreached): adjacent nodes differ by at
+// most one level, so every level set separates the nodes below it from the
+// nodes above it, and on box subdomains the level sets are planes parallel to
+// the side.  A part of more than `leaf` nodes is cut at the level set that
+// leaves both halves at most 70% of the part with the smallest separator (else
+// the best balance); the order is [half A][half B][separator], and every
+// undivided part and every separator is one group (sizes in gsize).
+struct NdOrder {
+  const std::vector<std::vector<int32_t>>& dist;
+  int64_t leaf;
+  std::vector<int32_t>& order;
+  std::vector<int32_t>& gsize;
+  std::vector<int32_t> hist;
+  void leaf_group(std::vector<int32_t>& X) {
+    std::sort(X.begin(), X.end());
+    order.insert(order.end(), X.begin(), X.end());
+    gsize.push_back((int32_t)X.size());
+  }
+  void run(std::vector<int32_t> X) {
+    if ((int64_t)X.size() <= leaf) { leaf_group(X); return; }
+    const int64_t nx = (int64_t)X.size();
+    int best_s = -1, best_L = 0;
+    int64_t best_sep = 0, best_big = 0;
+    bool best_bal = false;
+    for (size_t s = 0; s < dist.size(); ++s) {
+      const std::vector<int32_t>& d = dist[s];
+      int32_t lo = INT32_MAX, hi = -1;
+      bool all = true;
+      for (int32_t x : X) {
+        if (d[x] == INT32_MAX) { all = false; break; }
+        lo = std::min(lo, d[x]);
+        hi = std::max(hi, d[x]);
+      }
+      if (!all || hi - lo < 2) continue;
+      hist.assign((size_t)(hi - lo + 1), 0);
+      for (int32_t x : X) hist[d[x] - lo]++;
+      int64_t below = hist[0];
+      for (int32_t L = lo + 1; L < hi; ++L) {
+        const int64_t sep = hist[L - lo], above = nx - below - sep;
+        const int64_t big = std::max(below, above);
+        const bool bal = 10 * big <= 7 * nx;
+        bool better;
+        if (best_s < 0) better = true;
+        else if (bal != best_bal) better = bal;
+        else if (bal) better = sep < best_sep || (sep == best_sep && big < best_big);
+        else better = big < best_big || (big == best_big && sep < best_sep);
+        if (better) { best_s = (int)s; best_L = L; best_sep = sep; best_big = big; best_bal = bal; }
+        below += sep;
+      }
+    }
+    if (best_s < 0) { leaf_group(X); return; }
+    const std::vector<int32_t>& d = dist[best_s];
+    std::vector<int32_t> A, B, S;
+    for (int32_t x : X) (d[x] < best_L ? A : d[x] > best_L ? B : S).push_back(x);
+    X.clear();
+    X.shrink_to_fit();
+    run(std::move(A));
+    run(std::move(B));
+    leaf_group(S);
+  }
+};
+
+// Interior order of subdomain b by nested dissection.  node_local maps the
+// subdomain's interior nodes to 0..n-1 and its interface nodes to 0..ng-1;
+// sides are the neighbouring subdomains (interface nodes shared with them);
+// only sides whose adjacent interior layer has at least a quarter of the
+// largest layer's nodes grow distances.
+void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vector<int64_t>& inodes,
+                 const std::vector<int64_t>& gnodes, const std::vector<int32_t>& node_local,
+                 const std::vector<char>& node_is_g, const int64_t* nptr, const int32_t* nsub, int nd,
+                 std::vector<int32_t>& order, std::vector<int32_t>& gsize) {
+  const int32_t n = (int32_t)inodes.size(), ng = (int32_t)gnodes.size();
+  const int64_t ne = (int64_t)S.elems.size();
+  // element-local slots: interior nodes 0..n-1, interface nodes n..n+ng-1
+  std::vector<int32_t> eptr(ne + 1, 0), eslot;
+  eslot.reserve((size_t)ne * 8);
+  for (int64_t i = 0; i < ne; ++i) {
+    const int64_t e = S.elems[i];
+    for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+      const int64_t v = L.el_nodes[j];
+      if (v >= 0) eslot.push_back(node_is_g[v] ? n + node_local[v] : node_local[v]);
+    }
+    eptr[i + 1] = (int32_t)eslot.size();
+  }
+  // slot -> elements (CSR)
+  std::vector<int32_t> ecnt(n + ng + 1, 0);
+  for (int32_t x : eslot) ecnt[x + 1]++;
+  for (int32_t i = 0; i < n + ng; ++i) ecnt[i + 1] += ecnt[i];
+  std::vector<int32_t> elist(ecnt[n + ng]);
+  {
+    std::vector<int32_t> pos(ecnt.begin(), ecnt.end() - 1);
+    for (int64_t i = 0; i < ne; ++i)
+      for (int32_t q = eptr[i]; q < eptr[i + 1]; ++q) elist[pos[eslot[q]]++] = (int32_t)i;
+  }
+  // interior adjacency (CSR, no duplicates)
+  std::vector<int32_t> ptr(n + 1, 0), adj, stamp(n, -1);
+  adj.reserve((size_t)n * 27);
+  for (int32_t u = 0; u < n; ++u) {
+    stamp[u] = u;
+    for (int32_t q = ecnt[u]; q < ecnt[u + 1]; ++q) {
+      const int32_t i = elist[q];
+      for (int32_t r = eptr[i]; r < eptr[i + 1]; ++r) {
+        const int32_t w = eslot[r];
+        if (w < n && stamp[w] != u) { stamp[w] = u; adj.push_back(w); }
+      }
+    }
+    ptr[u + 1] = (int32_t)adj.size();
+  }
+  // sides: (neighbour, interface slot) pairs grouped by neighbour
+  std::vector<std::pair<int32_t, int32_t>> ns_pairs;
+  for (int32_t gi = 0; gi < ng; ++gi) {
+    const int64_t v = gnodes[gi];
+    for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
+      if (nsub[q] != b) ns_pairs.push_back({nsub[q], gi});
+  }
+  std::sort(ns_pairs.begin(), ns_pairs.end());
+  std::vector<std::vector<int32_t>> layer;
+  std::fill(stamp.begin(), stamp.end(), -1);
+  for (size_t q = 0; q < ns_pairs.size();) {
+    size_t q1 = q;
+    while (q1 < ns_pairs.size() && ns_pairs[q1].first == ns_pairs[q].first) ++q1;
+    const int32_t sid = (int32_t)layer.size();
+    layer.emplace_back();
+    std::vector<int32_t>& l = layer.back();
+    for (size_t t = q; t < q1; ++t) {
+      const int32_t gs = n + ns_pairs[t].second;
+      for (int32_t r = ecnt[gs]; r < ecnt[gs + 1]; ++r) {
+        const int32_t i = elist[r];
+        for (int32_t z = eptr[i]; z < eptr[i + 1]; ++z) {
+          const int32_t w = eslot[z];
+          if (w < n && stamp[w] != sid) { stamp[w] = sid; l.push_back(w); }
+        }
+      }
+    }
+    q = q1;
+  }
+  size_t maxl = 0;
+  for (auto& l : layer) maxl = std::max(maxl, l.size());
+  std::vector<std::vector<int32_t>> dist;
+  std::vector<int32_t> queue(n);
+  for (auto& l : layer) {
+    if (l.empty() || 4 * l.size() < maxl) continue;
+    dist.emplace_back(n, INT32_MAX);
+    std::vector<int32_t>& d = dist.back();
+    int32_t qh = 0, qt = 0;
+    for (int32_t x : l) { d[x] = 0; queue[qt++] = x; }
+    while (qh < qt) {
+      const int32_t u = queue[qh++];
+      const int32_t du = d[u] + 1;
+      for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q)
+        if (d[adj[q]] == INT32_MAX) { d[adj[q]] = du; queue[qt++] = adj[q]; }
+    }
+  }
+  order.clear();
+  gsize.clear();
+  std::vector<int32_t> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  NdOrder nd_rec{dist, std::max<int64_t>(1, ND_LEAF_DOFS / nd), order, gsize, {}};
+  nd_rec.run(std::move(all));
+}
+
+// Symbolic factorization at tile level: structure of L over the interior
+// tile columns 0..tI-1 of a matrix of nt tile rows, from the tiles every
+// element couples.  Column k's rows are passed on to its parent (its first
+// row below k) when k is eliminated.
+void tile_structure(const LevelPlan& L, const SubPlan& S, int nd, int tI, int nt, std::vector<int32_t>& sptr,
+                    std::vector<int32_t>& srow) {
+  const int W = (nt + 63) / 64;
+  std::vector<uint64_t> bits((size_t)tI * W, 0);
+  int32_t tl[64];
+  for (int64_t e : S.elems) {
+    int m = 0;
+    for (int64_t j = L.el_local_ptr[e]; j < L.el_local_ptr[e + 1]; ++j) {
+      const int32_t p = L.el_local[j];
+      if (p < 0) continue;
+      for (int t = p / TS; t <= (p + nd - 1) / TS; ++t) {  // tiles of the node's DOFs
+        int x = 0;
+        while (x < m && tl[x] != t) ++x;
+        if (x == m && m < 64) tl[m++] = t;
+      }
+    }
+    for (int x = 0; x < m; ++x) {
+      const int a = tl[x];
+      if (a >= tI) continue;
+      uint64_t* col = bits.data() + (size_t)a * W;
+      for (int y = 0; y < m; ++y)
+        if (tl[y] > a) col[tl[y] / 64] |= 1ull << (tl[y] % 64);
+    }
+  }
+  for (int k = 0; k < tI; ++k) {
+    uint64_t* col = bits.data() + (size_t)k * W;
+    int par = -1;
+    for (int w = 0; w < W && par < 0; ++w)
+      if (col[w]) par = w * 64 + __builtin_ctzll(col[w]);
+    if (par < 0 || par >= tI) continue;
+    uint64_t* pc = bits.data() + (size_t)par * W;
+    for (int w = 0; w < W; ++w) pc[w] |= col[w];
+    pc[par / 64] &= ~(1ull << (par % 64));
+  }
+  sptr.assign(tI + 1, 0);
+  srow.clear();
+  for (int k = 0; k < tI; ++k) {
+    const uint64_t* col = bits.data() + (size_t)k * W;
+    for (int w = 0; w < W; ++w)
+      for (uint64_t m = col[w]; m; m &= m - 1) srow.push_back(w * 64 + __builtin_ctzll(m));
+    sptr[k + 1] = (int32_t)srow.size();
+  }
 }
 
 // Build one level from its elements (node lists, -1 = eliminated node) and
@@ -221,14 +440,52 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
     for (int64_t n : sub_nodes[b]) (mult(n) >= 2 && !L.top ? gnodes : inodes).push_back(n);
     S.nI = (int64_t)inodes.size() * nd;
     S.nG = (int64_t)gnodes.size() * nd;
-    S.nIp = round_up(S.nI, TS);
     S.nGp = round_up(S.nG, TS);
     for (size_t i = 0; i < inodes.size(); ++i) node_local[inodes[i]] = (int32_t)i;
-
-    // interface nodes sorted by the first interior node they couple to, so that
-    // the tile envelope of the interface rows is tight
-    std::vector<int64_t> key(gnodes.size(), INT64_MAX);
     for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int32_t)i;
+
+    // interior numbering: nested dissection on level 1 (groups padded to whole
+    // tiles), else node order; node_local of an interior node becomes the
+    // local position of its first DOF
+    std::vector<int32_t> iorder, gsize;
+    const bool use_nd = L.level == 1 && !L.top && S.nI >= ND_MIN_DOFS;
+    if (use_nd) {
+      nd_interior(L, S, b, inodes, gnodes, node_local, node_is_g, nptr.data(), nsub.data(), nd, iorder, gsize);
+    } else {
+      iorder.resize(inodes.size());
+      std::iota(iorder.begin(), iorder.end(), 0);
+      gsize.assign(1, (int32_t)inodes.size());
+    }
+    S.padI.clear();
+    S.gtile.clear();
+    S.sptr.clear();
+    S.srow.clear();
+    {
+      std::vector<int32_t> ipos(inodes.size());
+      int64_t pos = 0;
+      size_t q = 0;
+      for (int32_t gs : gsize) {
+        if (use_nd) S.gtile.push_back((int32_t)(pos / TS));
+        for (int32_t i = 0; i < gs; ++i, ++q) ipos[iorder[q]] = (int32_t)(pos + (int64_t)i * nd);
+        const int64_t end = pos + (int64_t)gs * nd, pend = round_up(end, TS);
+        if (pend > end) {
+          S.padI.push_back((int32_t)end);
+          S.padI.push_back((int32_t)(pend - end));
+        }
+        pos = pend;
+      }
+      S.nIp = pos;
+      if (use_nd) S.gtile.push_back((int32_t)(pos / TS));
+      S.dofI.assign(S.nIp, -1);
+      for (size_t i = 0; i < inodes.size(); ++i) {
+        node_local[inodes[i]] = ipos[i];
+        for (int c = 0; c < nd; ++c) S.dofI[ipos[i] + c] = inodes[i] * nd + c;
+      }
+    }
+
+    // interface nodes sorted by the first interior position they couple to, so
+    // that the tile envelope of the interface rows is tight
+    std::vector<int64_t> key(gnodes.size(), INT64_MAX);
     for (int64_t e : S.elems) {
       int64_t mn = INT64_MAX;
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
@@ -250,9 +507,6 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
     gnodes.swap(gsorted);
     for (size_t i = 0; i < gnodes.size(); ++i) node_local[gnodes[i]] = (int32_t)i;
 
-    S.dofI.resize(S.nI);
-    for (size_t i = 0; i < inodes.size(); ++i)
-      for (int c = 0; c < nd; ++c) S.dofI[i * nd + c] = inodes[i] * nd + c;
     S.dofG.resize(S.nG);
     S.iface.resize(S.nG);
     for (size_t i = 0; i < gnodes.size(); ++i)
@@ -263,7 +517,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
 
     // local K index of a level DOF of this subdomain
     auto kidx = [&](int64_t n, int c) -> int64_t {
-      return node_is_g[n] ? S.nIp + (int64_t)node_local[n] * nd + c : (int64_t)node_local[n] * nd + c;
+      return node_is_g[n] ? S.nIp + (int64_t)node_local[n] * nd + c : (int64_t)node_local[n] + c;
     };
     const int64_t nK = S.nIp + S.nGp + (L.augmentK ? S.nIp : 0);
     const int64_t ntK = nK / TS;
@@ -291,6 +545,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
       for (int64_t p = r * TS; p < (r + 1) * TS; ++p) m = std::min(m, first[p]);
       S.envK[r] = (int32_t)(m / TS);
     }
+    if (use_nd) tile_structure(L, S, nd, (int)(S.nIp / TS), (int)ntK, S.sptr, S.srow);
 
     // constraint rows and R_Ci
     S.crow_ptr.assign(1, 0);
@@ -464,11 +719,68 @@ namespace {
 
 enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_N = 6 };
 
+// Tasks of an item with a tile structure (phase 1 only).  Panels start at
+// every group boundary.  Column k of a panel starting at k0 takes the
+// in-panel update from the panel's earlier columns j whose structure holds k
+// (rows: those columns' rows from k on), then its diagonal factor and the
+// panel solves of its rows; after the panel, every pair of rows r >= s beyond
+// it in the union of the panel's structures is updated.  Rows outside a
+// structure hold zero tiles, so the products they add are zero.
+template <typename F>
+void enumerate_item_tiles(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
+  const double t3 = (double)TS * TS * TS;
+  const int32_t *sp = it.sptr, *sr = it.srow, *gt = it.gtile;
+  std::vector<int32_t> U, V, rows;
+  for (int g = 0; g < it.ngroups; ++g) {
+    const int g0 = gt[g], g1 = gt[g + 1];
+    for (int k0 = g0; k0 < g1; k0 += panel) {
+      const int kend = std::min(k0 + panel, g1);
+      U.clear();
+      for (int k = k0; k < kend; ++k) {
+        if (k > k0) {
+          rows.clear();
+          for (int j = k0; j < k; ++j) {
+            const int32_t *c0 = sr + sp[j], *c1 = sr + sp[j + 1];
+            const int32_t* q = std::lower_bound(c0, c1, k);
+            if (q == c1 || *q != k) continue;
+            rows.insert(rows.end(), q, c1);
+          }
+          std::sort(rows.begin(), rows.end());
+          rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+          for (int32_t r : rows) emit(k, SK_INP, pack_task(b, r, k, k0), 2.0 * t3 * (k - k0));
+        }
+        emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
+        for (int32_t q = sp[k]; q < sp[k + 1]; ++q) emit(k, SK_PAN, pack_task(b, sr[q], k, 0), 2.0 * t3);
+        V.clear();
+        std::set_union(U.begin(), U.end(), sr + sp[k], sr + sp[k + 1], std::back_inserter(V));
+        U.swap(V);
+      }
+      const int k = kend - 1;
+      // with look-ahead the columns of the next panel are updated first
+      int nxt_end = k + 1;
+      if (lookahead) {
+        if (kend < g1) nxt_end = std::min(kend + panel, g1);
+        else if (g + 1 < it.ngroups) nxt_end = std::min(g1 + panel, (int)gt[g + 2]);
+      }
+      const auto first = std::upper_bound(U.begin(), U.end(), k);
+      for (auto qs = first; qs != U.end(); ++qs) {
+        const int s = *qs;
+        const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
+        for (auto qr = qs; qr != U.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0), 2.0 * t3 * (k - k0 + 1));
+      }
+    }
+  }
+}
+
 // All tasks of one item, in (tile column, step kind) order: emit(k, kind, task, flops).
 // Rows enter a sorted active list when the elimination reaches their
 // envelope, so the loops visit only rows whose tiles are in use.
 template <typename F>
 void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
+  if (it.sptr && it.e2 == 0) {
+    enumerate_item_tiles(it, b, panel, lookahead, emit);
+    return;
+  }
   const double t3 = (double)TS * TS * TS;
   const int e1 = it.e1, e2 = it.e2, nt = it.nt;
   const int32_t* env = it.env;

@@ -38,8 +38,15 @@ struct Glob {
 // One subdomain of one level.
 struct SubPlan {
   int64_t nI = 0, nG = 0;      // interior / interface DOFs
-  int64_t nIp = 0, nGp = 0;    // padded to the tile edge
-  std::vector<int64_t> dofI;   // level DOFs of the interior, local order
+  int64_t nIp = 0, nGp = 0;    // padded to the tile edge (nIp: every interior group padded)
+  std::vector<int64_t> dofI;   // level DOF of each interior position 0..nIp-1 (-1: padding)
+  std::vector<int32_t> padI;   // (start, count) runs of interior padding positions
+  // Level 1: interior numbered by nested dissection in groups (parts and
+  // separators) that each start on a tile; gtile holds the first tile column
+  // of every group, then nIp / 64.  sptr / srow: tile rows r > k with
+  // L(r, k) != 0 for every interior tile column k (symbolic factorization).
+  // All empty when the interior is one group in node order.
+  std::vector<int32_t> gtile, sptr, srow;
   std::vector<int64_t> dofG;   // level DOFs of the interface, local order
   std::vector<int32_t> iface;  // R_i: local interface position -> level interface index
   std::vector<int32_t> coarse; // R_Ci: local coarse DOF -> level coarse DOF
@@ -124,6 +131,13 @@ struct FactorItemDesc {
   int32_t nt = 0;                       // tiles per side
   int32_t e1 = 0, e2 = 0;               // tile columns eliminated per phase
   const int32_t* env = nullptr;         // first nonzero tile column per tile row (size nt)
+  // optional tile structure of the phase-1 columns (e2 == 0): rows of L per
+  // column (CSR over columns 0..e1-1) and group boundaries (ngroups + 1
+  // entries, last = e1) that panels do not cross; null: the envelope is used
+  const int32_t* sptr = nullptr;
+  const int32_t* srow = nullptr;
+  const int32_t* gtile = nullptr;
+  int32_t ngroups = 0;
 };
 
 struct FactorLaunch {

@@ -581,6 +581,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       D.K.items[b].e1 = (int32_t)(S.nIp / TS);
       D.K.items[b].e2 = 0;
       D.K.env[b] = S.envK;
+      if (!S.sptr.empty() && !P.augmentK) {  // nested-dissection interior: tile structure
+        D.K.items[b].sptr = S.sptr.data();
+        D.K.items[b].srow = S.srow.data();
+        D.K.items[b].gtile = S.gtile.data();
+        D.K.items[b].ngroups = (int32_t)S.gtile.size() - 1;
+      }
     }
     if ((st = prepare_job(D.K, D.kfp32))) return st;
     flops_K += D.K.sched.flops;
@@ -593,7 +599,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       auto add = [&](int64_t r0, int64_t c0, int64_t cnt, double v) {
         if (cnt > 0) D.ksegs_h.push_back(DiagSeg{D.K.off[b], nt, (int32_t)r0, (int32_t)c0, (int32_t)cnt, v});
       };
-      add(S.nI, S.nI, S.nIp - S.nI, 1.0);
+      for (size_t q = 0; q + 1 < S.padI.size(); q += 2) add(S.padI[q], S.padI[q], S.padI[q + 1], 1.0);
       add(S.nIp + S.nG, S.nIp + S.nG, S.nGp - S.nG, 1.0);
       if (P.augmentK) add(S.nIp + S.nGp, 0, S.nIp, 1.0);
     }
@@ -647,7 +653,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
           gcnt[S.iface[k] + 1]++;
         }
         for (int64_t k = 0; k < S.nGp; ++k) gdiag[D.gofs[b] + k] = D.K.off[b] + packed_offset(S.nIp + k, S.nIp + k, D.K.nt[b]);
-        for (int64_t k = 0; k < S.nI; ++k) iidx[D.iofs[b] + k] = (int32_t)S.dofI[k];
+        for (int64_t k = 0; k < S.nIp; ++k) iidx[D.iofs[b] + k] = (int32_t)S.dofI[k];
         for (int k = 0; k < S.nc; ++k) {
           cidx[D.cofs[b] + k] = S.coarse[k];
           ccnt[S.coarse[k] + 1]++;
@@ -973,8 +979,9 @@ mlbddc_status Handle::validate_level(int li, int part) {
     }
     if (!seg_ok(D.ksegs_h)) return bad(L + "diagonal segment");
     for (size_t b = 0; b < P.subs.size(); ++b) {
+      if ((int64_t)P.subs[b].dofI.size() != P.subs[b].nIp) return bad(L + "interior map size");
       for (int64_t d : P.subs[b].dofI)
-        if (d < 0 || d >= P.n_dofs) return bad(L + "interior map");
+        if (d < -1 || d >= P.n_dofs) return bad(L + "interior map");
       for (int32_t g : P.subs[b].iface)
         if (g < 0 || g >= (int64_t)P.iface_dofs.size()) return bad(L + "interface map");
     }
