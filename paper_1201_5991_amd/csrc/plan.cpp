@@ -122,9 +122,9 @@ struct NdOrder {
 
 // Interior order of subdomain b by nested dissection.  node_local maps the
 // subdomain's interior nodes to 0..n-1 and its interface nodes to 0..ng-1;
-// sides are the neighbouring subdomains (interface nodes shared with them);
-// only sides whose adjacent interior layer has at least a quarter of the
-// largest layer's nodes grow distances.
+// sides are the neighbouring subdomains (interface nodes shared with them).
+// Distances grow from at most three sides whose interior layers touch one
+// another, each layer at least a quarter of the largest.
 void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vector<int64_t>& inodes,
                  const std::vector<int64_t>& gnodes, const std::vector<int32_t>& node_local,
                  const std::vector<char>& node_is_g, const int64_t* nptr, const int32_t* nsub, int nd,
@@ -132,8 +132,10 @@ void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vec
   const int32_t n = (int32_t)inodes.size(), ng = (int32_t)gnodes.size();
   const int64_t ne = (int64_t)S.elems.size();
   // element-local slots: interior nodes 0..n-1, interface nodes n..n+ng-1
-  std::vector<int32_t> eptr(ne + 1, 0), eslot;
-  eslot.reserve((size_t)ne * 8);
+  // work arrays kept by the planning thread between subdomains
+  static thread_local std::vector<int32_t> eptr, eslot, ecnt, elist, ptr, adj, stamp, queue, pos;
+  eptr.assign(ne + 1, 0);
+  eslot.clear();
   for (int64_t i = 0; i < ne; ++i) {
     const int64_t e = S.elems[i];
     for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
@@ -143,28 +145,34 @@ void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vec
     eptr[i + 1] = (int32_t)eslot.size();
   }
   // slot -> elements (CSR)
-  std::vector<int32_t> ecnt(n + ng + 1, 0);
+  ecnt.assign(n + ng + 1, 0);
   for (int32_t x : eslot) ecnt[x + 1]++;
   for (int32_t i = 0; i < n + ng; ++i) ecnt[i + 1] += ecnt[i];
-  std::vector<int32_t> elist(ecnt[n + ng]);
+  elist.resize(ecnt[n + ng]);
   {
-    std::vector<int32_t> pos(ecnt.begin(), ecnt.end() - 1);
+    pos.assign(ecnt.begin(), ecnt.end() - 1);
     for (int64_t i = 0; i < ne; ++i)
       for (int32_t q = eptr[i]; q < eptr[i + 1]; ++q) elist[pos[eslot[q]]++] = (int32_t)i;
   }
-  // interior adjacency (CSR, no duplicates)
-  std::vector<int32_t> ptr(n + 1, 0), adj, stamp(n, -1);
-  adj.reserve((size_t)n * 27);
+  // interior adjacency (CSR, no duplicates; branch-free inner loop)
+  ptr.assign(n + 1, 0);
+  if (adj.size() < (size_t)n * 32 + 64) adj.resize((size_t)n * 32 + 64);
+  stamp.assign(n + ng, -1);
+  int64_t na = 0;
   for (int32_t u = 0; u < n; ++u) {
     stamp[u] = u;
     for (int32_t q = ecnt[u]; q < ecnt[u + 1]; ++q) {
       const int32_t i = elist[q];
+      if (na + (eptr[i + 1] - eptr[i]) > (int64_t)adj.size()) adj.resize(adj.size() * 2);
       for (int32_t r = eptr[i]; r < eptr[i + 1]; ++r) {
         const int32_t w = eslot[r];
-        if (w < n && stamp[w] != u) { stamp[w] = u; adj.push_back(w); }
+        const int32_t old = stamp[w];
+        stamp[w] = u;
+        adj[na] = w;
+        na += (w < n) & (old != u);
       }
     }
-    ptr[u + 1] = (int32_t)adj.size();
+    ptr[u + 1] = (int32_t)na;
   }
   // sides: (neighbour, interface slot) pairs grouped by neighbour
   std::vector<std::pair<int32_t, int32_t>> ns_pairs;
@@ -194,21 +202,41 @@ void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vec
     }
     q = q1;
   }
-  size_t maxl = 0;
-  for (auto& l : layer) maxl = std::max(maxl, l.size());
+  // up to three sides that touch one another (on a box: three perpendicular
+  // faces), largest layers first
+  std::vector<int32_t> by_size(layer.size());
+  std::iota(by_size.begin(), by_size.end(), 0);
+  std::sort(by_size.begin(), by_size.end(), [&](int32_t x, int32_t y) {
+    return layer[x].size() != layer[y].size() ? layer[x].size() > layer[y].size() : x < y;
+  });
+  std::vector<int32_t> chosen;
+  std::vector<uint8_t> in_chosen(n, 0);
+  for (int32_t c : by_size) {
+    if (chosen.size() == 3 || layer[c].empty()) break;
+    if (4 * layer[c].size() < layer[by_size[0]].size()) break;
+    uint8_t touch = 0;
+    for (int32_t x : layer[c]) touch |= in_chosen[x];
+    if (touch != (uint8_t)((1u << chosen.size()) - 1)) continue;  // must touch every side chosen so far
+    for (int32_t x : layer[c]) in_chosen[x] |= (uint8_t)(1u << chosen.size());
+    chosen.push_back(c);
+  }
   std::vector<std::vector<int32_t>> dist;
-  std::vector<int32_t> queue(n);
-  for (auto& l : layer) {
-    if (l.empty() || 4 * l.size() < maxl) continue;
+  queue.resize(n + 1);
+  for (int32_t c : chosen) {
     dist.emplace_back(n, INT32_MAX);
     std::vector<int32_t>& d = dist.back();
     int32_t qh = 0, qt = 0;
-    for (int32_t x : l) { d[x] = 0; queue[qt++] = x; }
+    for (int32_t x : layer[c]) { d[x] = 0; queue[qt++] = x; }
     while (qh < qt) {
       const int32_t u = queue[qh++];
       const int32_t du = d[u] + 1;
-      for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q)
-        if (d[adj[q]] == INT32_MAX) { d[adj[q]] = du; queue[qt++] = adj[q]; }
+      for (int32_t q = ptr[u]; q < ptr[u + 1]; ++q) {
+        const int32_t w = adj[q];
+        const bool fresh = d[w] == INT32_MAX;
+        d[w] = fresh ? du : d[w];
+        queue[qt] = w;
+        qt += fresh;
+      }
     }
   }
   order.clear();
