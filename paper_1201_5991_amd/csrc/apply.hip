@@ -166,11 +166,12 @@ __global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* 
 }
 
 // ------------------------------------------------------------------ trsv
-// Blocked triangular solve with the interior factor of one subdomain per
-// workgroup of eight wavefronts.  Block row k:
+// Blocked triangular solve with the interior factor over one group of tile
+// rows per workgroup of eight wavefronts (the nonzero tiles of a row or a
+// column come from host-built lists).  Block row k:
 //   v_k <- W_k (v_k - sum_{s<k} L_ks v_s)          (forward, W_k = L_kk^{-1})
 //   v_k <- W_k^T (v_k - sum_{r>k} L_rk^T v_r)      (backward)
-// Wavefronts 1..7 take the envelope tiles of the block row in turn; each
+// Wavefronts 1..7 take the nonzero tiles of the block row in turn; each
 // loads a whole tile (64 values per lane in flight) and the matching block of
 // v (broadcast through LDS).  Wavefront 0 meanwhile stages W_k in LDS, so the
 // product with the diagonal inverse at the end of the step waits on no global
@@ -210,6 +211,8 @@ __device__ inline double dot64(const double (&a)[TS], const double* __restrict__
 
 __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvDesc* __restrict__ d,
                                                          const double* __restrict__ A, const double* __restrict__ Inv,
+                                                         const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                                         const int32_t* __restrict__ cptr, const int32_t* __restrict__ crow,
                                                          double* v) {
   const TrsvDesc D = d[blockIdx.x];
   constexpr int LDW = TS + 1;
@@ -220,8 +223,8 @@ __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvD
   const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const double* base = A + D.a_off;
   double* vv = v + D.v_off;
-  for (int step = 0; step < D.nti; ++step) {
-    const int k = trans ? D.nti - 1 - step : step;
+  for (int step = 0; step < D.k1 - D.k0; ++step) {
+    const int k = trans ? D.k1 - 1 - step : D.k0 + step;
     double part = 0.0;
     double a[TS];
     if (w == 0) {
@@ -230,8 +233,9 @@ __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvD
 #pragma unroll
       for (int b = 0; b < TS; ++b) sw[b * LDW + lane] = a[b];
     } else if (!trans) {
-      const int s0 = D.env ? D.env[k] : 0;
-      for (int s = s0 + w - 1; s < k; s += TRSV_WAVES - 1) {
+      const int q0 = rptr[D.p_row + k], q1 = rptr[D.p_row + k + 1];
+      for (int q = q0 + w - 1; q < q1; q += TRSV_WAVES - 1) {
+        const int s = rcol[q];
         sv[w][lane] = vv[(int64_t)s * TS + lane];
         load_tile_rows(base + tile_index(k, s, D.a_nt) * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
@@ -239,8 +243,9 @@ __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvD
         __builtin_amdgcn_wave_barrier();
       }
     } else {
-      for (int r = k + w; r < D.nti; r += TRSV_WAVES - 1) {
-        if (D.env && D.env[r] > k) continue;
+      const int q0 = cptr[D.p_col + k], q1 = cptr[D.p_col + k + 1];
+      for (int q = q0 + w - 1; q < q1; q += TRSV_WAVES - 1) {
+        const int r = crow[q];
         sv[w][lane] = vv[(int64_t)r * TS + lane];
         load_tile_cols(base + tile_index(r, k, D.a_nt) * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
@@ -422,9 +427,10 @@ void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in,
 }
 
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
-                 double* v) {
+                 const int32_t* rptr, const int32_t* rcol, const int32_t* cptr, const int32_t* crow, double* v) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(TRSV_WAVES * 64), 0, st, transposed ? 1 : 0, d, A, Inv, v);
+  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(TRSV_WAVES * 64), 0, st, transposed ? 1 : 0, d, A, Inv, rptr, rcol, cptr,
+                     crow, v);
 }
 
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out) {

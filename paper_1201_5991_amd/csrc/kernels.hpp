@@ -91,10 +91,15 @@ template <typename TI, typename TO>
 void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out);
 
 // Blocked triangular solves with the interior factor of tile-packed FP64 K
-// matrices, one workgroup per item, using the stored inverse diagonal tiles.
-struct TrsvDesc { int64_t a_off; int32_t a_nt, nti; int64_t inv_off; int64_t v_off; const int32_t* env; };
+// matrices and the stored inverse diagonal tiles.  One workgroup per item: a
+// group of tile rows k0..k1-1 of one matrix; the items of one launch must not
+// depend on one another (groups of one height of a dissection tree).  Nonzero
+// interior tiles: row k holds columns rcol[rptr[p_row + k] .. rptr[p_row + k + 1])
+// (all < k), column k holds rows crow[cptr[p_col + k] .. cptr[p_col + k + 1])
+// (all > k and inside the interior).
+struct TrsvDesc { int64_t a_off; int32_t a_nt, k0, k1, p_row, p_col, pad; int64_t inv_off, v_off; };
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
-                 double* v);
+                 const int32_t* rptr, const int32_t* rcol, const int32_t* cptr, const int32_t* crow, double* v);
 
 // ------------------------------------------------------------------- PCG
 // Deterministic dot product: partial sums per block then a single-block finish.

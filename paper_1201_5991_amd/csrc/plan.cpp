@@ -70,14 +70,19 @@ struct NdOrder {
   int64_t leaf;
   std::vector<int32_t>& order;
   std::vector<int32_t>& gsize;
+  std::vector<int32_t>& gheight;
   std::vector<int32_t> hist;
-  void leaf_group(std::vector<int32_t>& X) {
+  int leaf_group(std::vector<int32_t>& X, int height) {
+    if (X.empty()) return -1;
     std::sort(X.begin(), X.end());
     order.insert(order.end(), X.begin(), X.end());
     gsize.push_back((int32_t)X.size());
+    gheight.push_back(height);
+    return height;
   }
-  void run(std::vector<int32_t> X) {
-    if ((int64_t)X.size() <= leaf) { leaf_group(X); return; }
+  // returns the height of the part's last group (-1 for an empty part)
+  int run(std::vector<int32_t> X) {
+    if ((int64_t)X.size() <= leaf) return leaf_group(X, 0);
     const int64_t nx = (int64_t)X.size();
     int best_s = -1, best_L = 0;
     int64_t best_sep = 0, best_big = 0;
@@ -108,15 +113,16 @@ struct NdOrder {
         below += sep;
       }
     }
-    if (best_s < 0) { leaf_group(X); return; }
+    if (best_s < 0) return leaf_group(X, 0);
     const std::vector<int32_t>& d = dist[best_s];
     std::vector<int32_t> A, B, S;
     for (int32_t x : X) (d[x] < best_L ? A : d[x] > best_L ? B : S).push_back(x);
     X.clear();
     X.shrink_to_fit();
-    run(std::move(A));
-    run(std::move(B));
-    leaf_group(S);
+    const int ha = run(std::move(A));
+    const int hb = run(std::move(B));
+    const int hs = leaf_group(S, std::max(ha, hb) + 1);
+    return hs >= 0 ? hs : std::max(ha, hb);
   }
 };
 
@@ -128,7 +134,7 @@ struct NdOrder {
 void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vector<int64_t>& inodes,
                  const std::vector<int64_t>& gnodes, const std::vector<int32_t>& node_local,
                  const std::vector<char>& node_is_g, const int64_t* nptr, const int32_t* nsub, int nd,
-                 std::vector<int32_t>& order, std::vector<int32_t>& gsize) {
+                 std::vector<int32_t>& order, std::vector<int32_t>& gsize, std::vector<int32_t>& gheight) {
   const int32_t n = (int32_t)inodes.size(), ng = (int32_t)gnodes.size();
   const int64_t ne = (int64_t)S.elems.size();
   // element-local slots: interior nodes 0..n-1, interface nodes n..n+ng-1
@@ -241,9 +247,10 @@ void nd_interior(const LevelPlan& L, const SubPlan& S, int32_t b, const std::vec
   }
   order.clear();
   gsize.clear();
+  gheight.clear();
   std::vector<int32_t> all(n);
   std::iota(all.begin(), all.end(), 0);
-  NdOrder nd_rec{dist, std::max<int64_t>(1, ND_LEAF_DOFS / nd), order, gsize, {}};
+  NdOrder nd_rec{dist, std::max<int64_t>(1, ND_LEAF_DOFS / nd), order, gsize, gheight, {}};
   nd_rec.run(std::move(all));
 }
 
@@ -478,11 +485,13 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
     std::vector<int32_t> iorder, gsize;
     const bool use_nd = L.level == 1 && !L.top && S.nI >= ND_MIN_DOFS;
     if (use_nd) {
-      nd_interior(L, S, b, inodes, gnodes, node_local, node_is_g, nptr.data(), nsub.data(), nd, iorder, gsize);
+      nd_interior(L, S, b, inodes, gnodes, node_local, node_is_g, nptr.data(), nsub.data(), nd, iorder, gsize,
+                  S.gheight);
     } else {
       iorder.resize(inodes.size());
       std::iota(iorder.begin(), iorder.end(), 0);
       gsize.assign(1, (int32_t)inodes.size());
+      S.gheight.assign(1, 0);
     }
     S.padI.clear();
     S.gtile.clear();

@@ -47,6 +47,9 @@ struct SubPlan {
   // L(r, k) != 0 for every interior tile column k (symbolic factorization).
   // All empty when the interior is one group in node order.
   std::vector<int32_t> gtile, sptr, srow;
+  // height of every group in the dissection tree (parts 0, a separator one
+  // more than the higher of its two halves); one group of height 0 otherwise
+  std::vector<int32_t> gheight;
   std::vector<int64_t> dofG;   // level DOFs of the interface, local order
   std::vector<int32_t> iface;  // R_i: local interface position -> level interface index
   std::vector<int32_t> coarse; // R_Ci: local coarse DOF -> level coarse DOF

@@ -122,8 +122,13 @@ struct LevelDev {
   void* partial = nullptr;
   // tile mat-vec sets
   MvSet mvS, mvG, mvPsiN, mvPsiT, mvPre, mvPreT, mvPostN, mvLgi, mvLgiT;
+  // triangular solves: items sorted by dissection height (trsv_lvl[h] = first
+  // item of height h, last entry = item count) and the tile lists
   std::vector<TrsvDesc> trsv_h;
+  std::vector<int32_t> trsv_lvl;
+  std::vector<int32_t> tr_rptr, tr_rcol, tr_cptr, tr_crow;
   TrsvDesc* d_trsv = nullptr;
+  int32_t *d_tr_rptr = nullptr, *d_tr_rcol = nullptr, *d_tr_cptr = nullptr, *d_tr_crow = nullptr;
   // coarse matrices of this level (inputs of the next level's assembly)
   double* kc_compact = nullptr;
   std::vector<int64_t> kc_off;
@@ -329,6 +334,8 @@ struct Handle {
   mlbddc_status prepare_job(Job& J, bool fp32, int job = 0);
   mlbddc_status factor(Job& J, int level, bool precond);
   mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
+  mlbddc_status build_trsv(LevelDev& D);
+  void run_trsv(LevelDev& D, bool transposed);
   template <typename TA, typename TX, typename TY>
   void run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial);
   mlbddc_status apply_interface(int li, const double* rhat, double* zhat);
@@ -367,6 +374,93 @@ template <typename TA, typename TX, typename TY>
 void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial) {
   launch_tile_mv<TA, TX, TY>(stream, s.mode, s.d, (int32_t)s.h.size(), s.tiles, s.d_prefix, (const TA*)J.buf, x, y, alpha,
                              acc, (TA*)partial, s.max_out);
+}
+
+// Lists of the nonzero interior tiles of every level-1 factor (from the
+// tile structure, else every tile of the envelope) and one triangular-solve
+// item per interior group, ordered by the group's height in the dissection
+// tree: the groups of one height depend only on lower groups (forward) or
+// higher groups (backward).
+mlbddc_status Handle::build_trsv(LevelDev& D) {
+  const LevelPlan& P = *D.P;
+  D.trsv_h.clear();
+  D.tr_rptr.clear();
+  D.tr_rcol.clear();
+  D.tr_cptr.clear();
+  D.tr_crow.clear();
+  std::vector<std::vector<TrsvDesc>> by_h;
+  std::vector<int32_t> rcnt;
+  for (int b = 0; b < P.n_sub; ++b) {
+    const SubPlan& S = P.subs[b];
+    const int tI = (int)(S.nIp / TS);
+    const int32_t p_col = (int32_t)D.tr_cptr.size(), p_row = (int32_t)D.tr_rptr.size();
+    // columns: rows r > k inside the interior
+    const size_t c0 = D.tr_crow.size();
+    for (int k = 0; k < tI; ++k) {
+      D.tr_cptr.push_back((int32_t)D.tr_crow.size());
+      if (!S.sptr.empty()) {
+        for (int32_t q = S.sptr[k]; q < S.sptr[k + 1]; ++q)
+          if (S.srow[q] < tI) D.tr_crow.push_back(S.srow[q]);
+      } else {
+        for (int r = k + 1; r < tI; ++r)
+          if (S.envK[r] <= k) D.tr_crow.push_back(r);
+      }
+    }
+    D.tr_cptr.push_back((int32_t)D.tr_crow.size());
+    // rows: the transpose (columns ascending)
+    rcnt.assign(tI + 1, 0);
+    for (size_t q = c0; q < D.tr_crow.size(); ++q) rcnt[D.tr_crow[q] + 1]++;
+    for (int r = 0; r < tI; ++r) rcnt[r + 1] += rcnt[r];
+    const int32_t r0 = (int32_t)D.tr_rcol.size();
+    D.tr_rcol.resize(D.tr_rcol.size() + (D.tr_crow.size() - c0));
+    for (int r = 0; r <= tI; ++r) D.tr_rptr.push_back(r0 + rcnt[r]);
+    for (int k = 0; k < tI; ++k)
+      for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) D.tr_rcol[r0 + rcnt[D.tr_crow[q]]++] = k;
+    // the items of one height must not depend on one another: a tile (r, k)
+    // below the diagonal couples k to a lower group of the tree or its own
+    if (!S.gtile.empty()) {
+      std::vector<int32_t> grp(tI, 0);
+      for (size_t g = 0; g + 1 < S.gtile.size(); ++g)
+        for (int k = S.gtile[g]; k < S.gtile[g + 1]; ++k) grp[k] = (int32_t)g;
+      for (int k = 0; k < tI; ++k)
+        for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) {
+          const int32_t gr = grp[D.tr_crow[q]], gk = grp[k];
+          if (gr != gk && S.gheight[gr] <= S.gheight[gk])
+            return fail(MLBDDC_E_ARG, "internal layout check failed: dissection groups couple out of order");
+        }
+    }
+    // items
+    auto add = [&](int k0, int k1, int h) {
+      if (k1 <= k0) return;
+      if ((int)by_h.size() <= h) by_h.resize(h + 1);
+      by_h[h].push_back(TrsvDesc{D.K.off[b], D.K.nt[b], k0, k1, p_row, p_col, 0, D.K.inv_off[b], D.iofs[b]});
+    };
+    if (!S.gtile.empty()) {
+      for (size_t g = 0; g + 1 < S.gtile.size(); ++g) add(S.gtile[g], S.gtile[g + 1], S.gheight[g]);
+    } else {
+      add(0, tI, 0);
+    }
+  }
+  D.trsv_lvl.assign(1, 0);
+  for (auto& v : by_h) {
+    D.trsv_h.insert(D.trsv_h.end(), v.begin(), v.end());
+    D.trsv_lvl.push_back((int32_t)D.trsv_h.size());
+  }
+  mlbddc_status st;
+  if ((st = upload(&D.d_trsv, D.trsv_h))) return st;
+  if ((st = upload(&D.d_tr_rptr, D.tr_rptr))) return st;
+  if ((st = upload(&D.d_tr_rcol, D.tr_rcol))) return st;
+  if ((st = upload(&D.d_tr_cptr, D.tr_cptr))) return st;
+  return upload(&D.d_tr_crow, D.tr_crow);
+}
+
+void Handle::run_trsv(LevelDev& D, bool transposed) {
+  const int nh = (int)D.trsv_lvl.size() - 1;
+  for (int i = 0; i < nh; ++i) {
+    const int h = transposed ? nh - 1 - i : i;
+    launch_trsv(stream, transposed, D.d_trsv + D.trsv_lvl[h], D.trsv_lvl[h + 1] - D.trsv_lvl[h], (const double*)D.K.buf,
+                (const double*)D.K.inv, D.d_tr_rptr, D.d_tr_rcol, D.d_tr_cptr, D.d_tr_crow, D.wI);
+  }
 }
 
 // Panel width of a factorization job: explicit option, else the tune table's
@@ -733,17 +827,8 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         for (size_t i = 0; i < lgi.size(); ++i) { lt[i].x_off = lgi[i].y_off; lt[i].y_off = lgi[i].x_off; }
         if ((st = build_mv(D.mvLgi, MV_N, lgi))) return st;
         if ((st = build_mv(D.mvLgiT, MV_T, lt))) return st;
-        std::vector<int32_t*> envs;
-        for (int b = 0; b < ns; ++b) {
-          const SubPlan& S = P.subs[b];
-          int32_t* de = nullptr;
-          if ((st = upload(&de, S.envK))) return st;
-          D.trsv_h.push_back(TrsvDesc{D.K.off[b], D.K.nt[b], (int32_t)(S.nIp / TS), D.K.inv_off[b], D.iofs[b], de});
-        }
-        // envelopes for the L_GI products
-        for (size_t i = 0; i < D.mvLgi.h.size(); ++i) {}
-        if ((st = upload(&D.d_trsv, D.trsv_h))) return st;
-      } else if (!P.top || true) {
+        if ((st = build_trsv(D))) return st;
+      } else {
         if ((st = build_mv(D.mvPre, MV_SYM, pre))) return st;
         if (!P.top) {
           std::vector<MvDesc> pt, pn;
@@ -1008,9 +1093,24 @@ mlbddc_status Handle::validate_level(int li, int part) {
     if (!mv_ok(D.mvS, D.K, D.nG_flat, D.nG_flat)) return bad(L + "S mat-vec");
     if (!mv_ok(D.mvLgi, D.K, D.nI_flat, D.nG_flat)) return bad(L + "L_GI mat-vec");
     if (!mv_ok(D.mvLgiT, D.K, D.nG_flat, D.nI_flat)) return bad(L + "L_GI^T mat-vec");
-    for (const TrsvDesc& t : D.trsv_h)
-      if (t.nti > t.a_nt || t.v_off + (int64_t)t.nti * TS > D.nI_flat || t.inv_off + (int64_t)t.nti * TE > D.K.inv_elems + (t.nti == 0))
+    for (const TrsvDesc& t : D.trsv_h) {
+      if (t.k0 < 0 || t.k1 <= t.k0 || t.k1 > t.a_nt || t.v_off + (int64_t)t.k1 * TS > D.nI_flat ||
+          t.inv_off + (int64_t)t.k1 * TE > D.K.inv_elems || t.p_row < 0 || t.p_col < 0 ||
+          t.p_row + t.k1 >= (int64_t)D.tr_rptr.size() || t.p_col + t.k1 >= (int64_t)D.tr_cptr.size())
         return bad(L + "triangular solve");
+      for (int k = t.k0; k < t.k1; ++k) {
+        const int32_t a0 = D.tr_rptr[t.p_row + k], a1 = D.tr_rptr[t.p_row + k + 1];
+        const int32_t b0 = D.tr_cptr[t.p_col + k], b1 = D.tr_cptr[t.p_col + k + 1];
+        if (a0 < 0 || a1 < a0 || a1 > (int64_t)D.tr_rcol.size() || b0 < 0 || b1 < b0 || b1 > (int64_t)D.tr_crow.size())
+          return bad(L + "triangular solve lists");
+        for (int32_t q = a0; q < a1; ++q)
+          if (D.tr_rcol[q] < 0 || D.tr_rcol[q] >= k) return bad(L + "triangular solve row list");
+        for (int32_t q = b0; q < b1; ++q)
+          if (D.tr_crow[q] <= k || D.tr_crow[q] >= t.a_nt || t.v_off + (int64_t)(D.tr_crow[q] + 1) * TS > D.nI_flat)
+            return bad(L + "triangular solve column list");
+      }
+    }
+    if (D.trsv_lvl.empty() || D.trsv_lvl.back() != (int32_t)D.trsv_h.size()) return bad(L + "triangular solve heights");
   } else {
     if (!mv_ok(D.mvPre, D.K, D.nI_flat, D.nI_flat)) return bad(L + "interior mat-vec");
     if (!P.top && (!mv_ok(D.mvPreT, D.K, D.nI_flat, D.nG_flat) || !mv_ok(D.mvPostN, D.K, D.nG_flat, D.nI_flat)))
@@ -1246,7 +1346,7 @@ mlbddc_status Handle::condense(const double* f, double* g) {
   LevelDev& D = lev[0];
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   launch_gather<double, double>(stream, D.nI_flat, D.d_iidx, nullptr, f, D.wI);
-  launch_trsv(stream, false, D.d_trsv, D.P->n_sub, (const double*)D.K.buf, (const double*)D.K.inv, D.wI);
+  run_trsv(D, false);
   launch_fill(stream, D.nG_flat, 0.0, D.tG);
   run_mv<double, double, double>(D.mvLgi, D.K, D.wI, D.tG, -1.0, false, D.partial);
   launch_gather<double, double>(stream, nif, D.d_iface_dofs, nullptr, f, g);
@@ -1260,7 +1360,7 @@ mlbddc_status Handle::recover(const double* uhat, double* u) {
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, uhat, D.gd);
   run_mv<double, double, double>(D.mvLgiT, D.K, D.gd, D.wI, -1.0, true, D.partial);
-  launch_trsv(stream, true, D.d_trsv, D.P->n_sub, (const double*)D.K.buf, (const double*)D.K.inv, D.wI);
+  run_trsv(D, true);
   launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, D.wI, u);
   launch_scatter_idx(stream, nif, D.d_iface_dofs, uhat, u);
   HIPCHK(hipGetLastError());
