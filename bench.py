@@ -74,9 +74,10 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, flops_per_launch: float):
     """HBM bytes per launch of `kernel` from the committed PMC summary, or None
-    (also when the summary was taken on another workload or kernel source)."""
+    (also when the summary was taken on another workload, another kernel
+    source or another factorization schedule: launches of another size)."""
     path = os.path.join(ROOT, "profiles", "k_tile_mm_traffic.json")
     try:
         d = json.load(open(path))
@@ -84,6 +85,9 @@ def measured_traffic(kernel: str, workload: str):
         return None
     k = d.get("kernels", {}).get(kernel)
     if not k or d.get("source_hash") != kernel_source_hash() or d.get("workload_name") != workload:
+        return None
+    f = k.get("flops_per_launch")
+    if not f or abs(f - flops_per_launch) > 0.01 * flops_per_launch:
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -253,7 +257,7 @@ def main():
             "flops_per_launch": dprof["flops"] / max(dprof["launches"], 1),
             # lower bound on a launch's HBM bytes: each updated 64x64 tile read and written once
             "c_tile_bytes_per_launch": dprof["tiles"] / max(dprof["launches"], 1) * 2 * 64 * 64 * (4 if prec == "fp32" else 8)}
-    roof["traffic"] = measured_traffic(roof["kernel"], w.name)
+    roof["traffic"] = measured_traffic(roof["kernel"], w.name, roof["flops_per_launch"])
     line = {
         "metric": METRIC,
         "value": R["tts_s"],
