@@ -34,14 +34,18 @@ __host__ __device__ inline int64_t packed_offset(int64_t p, int64_t q, int64_t n
 
 inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 
-// Factorization task packing: item (24 bits), r (13), s (13), kf (13).
-__host__ __device__ inline uint64_t pack_task(uint64_t item, uint64_t r, uint64_t s, uint64_t kf) {
-  return item | (r << 24) | (s << 37) | (kf << 50);
+// Factorization task packing: item (16 bits), r (13), s (13), kf (13) and
+// nk (8): an update task sums the products of tile columns kf .. kf + nk.
+constexpr int64_t MAX_TASK_ITEMS = 1 << 16;
+constexpr int MAX_TASK_NK = 255;
+__host__ __device__ inline uint64_t pack_task(uint64_t item, uint64_t r, uint64_t s, uint64_t kf, uint64_t nk = 0) {
+  return item | (r << 16) | (s << 29) | (kf << 42) | (nk << 55);
 }
-__host__ __device__ inline int task_item(uint64_t t) { return (int)(t & 0xFFFFFFull); }
-__host__ __device__ inline int task_r(uint64_t t) { return (int)((t >> 24) & 0x1FFF); }
-__host__ __device__ inline int task_s(uint64_t t) { return (int)((t >> 37) & 0x1FFF); }
-__host__ __device__ inline int task_kf(uint64_t t) { return (int)((t >> 50) & 0x1FFF); }
+__host__ __device__ inline int task_item(uint64_t t) { return (int)(t & 0xFFFFull); }
+__host__ __device__ inline int task_r(uint64_t t) { return (int)((t >> 16) & 0x1FFF); }
+__host__ __device__ inline int task_s(uint64_t t) { return (int)((t >> 29) & 0x1FFF); }
+__host__ __device__ inline int task_kf(uint64_t t) { return (int)((t >> 42) & 0x1FFF); }
+__host__ __device__ inline int task_nk(uint64_t t) { return (int)((t >> 55) & 0xFF); }
 
 // Kinds of factorization steps (one launch each).
 enum LaunchKind { L_NEGATE = 0, L_INPANEL = 1, L_DIAG = 2, L_PANEL = 3, L_TRAIL = 4 };

@@ -398,7 +398,7 @@ __device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
 }
 
 // Tile products on MFMA, one 64x64 output tile per workgroup:
-//   UPDATE  A_rs <- A_rs - sum_{kk=kf..klast} A_{r,kk} A_{s,kk}^T
+//   UPDATE  A_rs <- A_rs - sum_{kk=kf..kf+nk} A_{r,kk} A_{s,kk}^T   (kf, nk from the task)
 //   PANEL   A_rk <- A_rk inv(L_kk)^T
 // The k dimension advances in half tiles (32 columns; 2 x 32 x LDU values of
 // LDS, so that four workgroups share a CU).  The next pair of half tiles is
@@ -408,13 +408,13 @@ __device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
 template <typename T, bool PANEL>
 __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
-                                                    int klast, T* A, const T* __restrict__ Inv) {
+                                                    T* A, const T* __restrict__ Inv) {
   __shared__ T sR[KH * LDU];
   __shared__ T sS[KH * LDU];
   const uint64_t t = tasks[xcd_slice(blockIdx.x, gridDim.x)];
   const int item = task_item(t), r = task_r(t), s = task_s(t);
   const int kf = PANEL ? s : task_kf(t);
-  const int nsteps = PANEL ? 2 : 2 * (klast - kf + 1);
+  const int nsteps = PANEL ? 2 : 2 * (task_nk(t) + 1);
   const int nt = ntv[item];
   T* base = A + off[item];
   T* g = base + tile_index(r, s, nt) * TE;
@@ -555,15 +555,16 @@ void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t 
 
 template <typename T>
 void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv) {
+  (void)k;  // the tasks carry their tile columns
   if (count <= 0) return;
   const uint64_t* tk = a.tasks + first;
   dim3 grid((unsigned)count), blk(256);
   switch (kind) {
     case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A); break;
-    case L_INPANEL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, k - 1, A, Inv); break;
+    case L_INPANEL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
     case L_DIAG: hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv); break;
-    case L_PANEL: hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, 0, A, Inv); break;
-    case L_TRAIL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, k, A, Inv); break;
+    case L_PANEL: hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
+    case L_TRAIL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
   }
 }
 

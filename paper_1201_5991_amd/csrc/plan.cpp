@@ -754,7 +754,45 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
 
 namespace {
 
-enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_N = 6 };
+// Step kinds, in launch order within a step.  The trailing updates of the
+// sibling groups of one step (tile-structured items) each get their own kind,
+// SK_NXT for the first sibling and SK_SIB + j for sibling j: siblings update
+// shared separator and interface tiles, so they must not share a launch.
+constexpr int MAX_SIBLINGS = 32;
+enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_SIB = 5, SK_N = 5 + MAX_SIBLINGS };
+
+// Step layout of a tile-structured item: first step of every group and the
+// sibling index of the group among the groups of its height; false when the
+// groups cannot advance together (more siblings than launch kinds).
+bool tree_steps(const FactorItemDesc& it, std::vector<int32_t>& gstep, std::vector<int32_t>& gsib, int& nsteps) {
+  const int ng = it.ngroups;
+  int H = 0;
+  for (int g = 0; g < ng; ++g) H = std::max(H, (int)it.gheight[g] + 1);
+  std::vector<int32_t> width(H, 0), count(H, 0);
+  gsib.assign(ng, 0);
+  for (int g = 0; g < ng; ++g) {
+    const int h = it.gheight[g];
+    width[h] = std::max(width[h], it.gtile[g + 1] - it.gtile[g]);
+    gsib[g] = count[h]++;
+    if (count[h] > MAX_SIBLINGS) return false;
+  }
+  std::vector<int32_t> base(H + 1, 0);
+  for (int h = 0; h < H; ++h) base[h + 1] = base[h] + width[h];
+  gstep.assign(ng, 0);
+  for (int g = 0; g < ng; ++g) gstep[g] = base[it.gheight[g]];
+  nsteps = base[H];
+  return true;
+}
+
+// Steps of an item (the launch steps its tasks use).
+int item_steps(const FactorItemDesc& it) {
+  if (it.sptr && it.e2 == 0 && it.gheight) {
+    std::vector<int32_t> gstep, gsib;
+    int n = 0;
+    if (tree_steps(it, gstep, gsib, n)) return n;
+  }
+  return it.e1 + it.e2;
+}
 
 // Tasks of an item with a tile structure (phase 1 only).  Panels start at
 // every group boundary.  Column k of a panel starting at k0 takes the
@@ -762,14 +800,21 @@ enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, S
 // (rows: those columns' rows from k on), then its diagonal factor and the
 // panel solves of its rows; after the panel, every pair of rows r >= s beyond
 // it in the union of the panel's structures is updated.  Rows outside a
-// structure hold zero tiles, so the products they add are zero.
+// structure hold zero tiles, so the products they add are zero.  Groups of
+// one height of the dissection tree advance together: they couple only to
+// groups above them, and their trailing updates go to separate launches.
 template <typename F>
-void enumerate_item_tiles(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
+void enumerate_item_tiles(const FactorItemDesc& it, uint64_t b, int panel, F&& emit) {
   const double t3 = (double)TS * TS * TS;
   const int32_t *sp = it.sptr, *sr = it.srow, *gt = it.gtile;
+  std::vector<int32_t> gstep, gsib;
+  int nsteps = 0;
+  const bool tree = it.gheight && tree_steps(it, gstep, gsib, nsteps);
   std::vector<int32_t> U, V, rows;
   for (int g = 0; g < it.ngroups; ++g) {
     const int g0 = gt[g], g1 = gt[g + 1];
+    auto step = [&](int k) { return tree ? gstep[g] + (k - g0) : k; };
+    const int trail_kind = !tree || gsib[g] == 0 ? SK_NXT : SK_SIB + gsib[g];
     for (int k0 = g0; k0 < g1; k0 += panel) {
       const int kend = std::min(k0 + panel, g1);
       U.clear();
@@ -784,27 +829,19 @@ void enumerate_item_tiles(const FactorItemDesc& it, uint64_t b, int panel, bool 
           }
           std::sort(rows.begin(), rows.end());
           rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
-          for (int32_t r : rows) emit(k, SK_INP, pack_task(b, r, k, k0), 2.0 * t3 * (k - k0));
+          for (int32_t r : rows) emit(step(k), SK_INP, pack_task(b, r, k, k0, k - 1 - k0), 2.0 * t3 * (k - k0));
         }
-        emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
-        for (int32_t q = sp[k]; q < sp[k + 1]; ++q) emit(k, SK_PAN, pack_task(b, sr[q], k, 0), 2.0 * t3);
+        emit(step(k), SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
+        for (int32_t q = sp[k]; q < sp[k + 1]; ++q) emit(step(k), SK_PAN, pack_task(b, sr[q], k, 0), 2.0 * t3);
         V.clear();
         std::set_union(U.begin(), U.end(), sr + sp[k], sr + sp[k + 1], std::back_inserter(V));
         U.swap(V);
       }
       const int k = kend - 1;
-      // with look-ahead the columns of the next panel are updated first
-      int nxt_end = k + 1;
-      if (lookahead) {
-        if (kend < g1) nxt_end = std::min(kend + panel, g1);
-        else if (g + 1 < it.ngroups) nxt_end = std::min(g1 + panel, (int)gt[g + 2]);
-      }
       const auto first = std::upper_bound(U.begin(), U.end(), k);
-      for (auto qs = first; qs != U.end(); ++qs) {
-        const int s = *qs;
-        const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
-        for (auto qr = qs; qr != U.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0), 2.0 * t3 * (k - k0 + 1));
-      }
+      for (auto qs = first; qs != U.end(); ++qs)
+        for (auto qr = qs; qr != U.end(); ++qr)
+          emit(step(k), trail_kind, pack_task(b, *qr, *qs, k0, k - k0), 2.0 * t3 * (k - k0 + 1));
     }
   }
 }
@@ -815,7 +852,7 @@ void enumerate_item_tiles(const FactorItemDesc& it, uint64_t b, int panel, bool 
 template <typename F>
 void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookahead, F&& emit) {
   if (it.sptr && it.e2 == 0) {
-    enumerate_item_tiles(it, b, panel, lookahead, emit);
+    enumerate_item_tiles(it, b, panel, emit);
     return;
   }
   const double t3 = (double)TS * TS * TS;
@@ -846,7 +883,7 @@ void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookah
     // act holds the rows with env <= k - 1 here
     if (k > k0 && env[k] <= k - 1)
       for (auto q = std::lower_bound(act.begin(), act.end(), k); q != act.end(); ++q)
-        emit(k, SK_INP, pack_task(b, *q, k, k0), 2.0 * t3 * (k - k0));
+        emit(k, SK_INP, pack_task(b, *q, k, k0, k - 1 - k0), 2.0 * t3 * (k - k0));
     if (k > 0) admit(k);  // now env <= k
     emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
     const auto first_after_k = std::upper_bound(act.begin(), act.end(), k);
@@ -859,7 +896,7 @@ void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookah
       for (auto qs = first_after_k; qs != act.end(); ++qs) {
         const int s = *qs;
         const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
-        for (auto qr = qs; qr != act.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0), 2.0 * t3 * (k - k0 + 1));
+        for (auto qr = qs; qr != act.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0, k - k0), 2.0 * t3 * (k - k0 + 1));
       }
     }
   }
@@ -875,8 +912,9 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   out.flops = 0.0;
   out.update_tasks = 0;
   if (panel < 1) panel = 1;
+  if (panel > MAX_TASK_NK + 1) panel = MAX_TASK_NK + 1;
   int maxk = 0;
-  for (auto& it : items) maxk = std::max(maxk, it.e1 + it.e2);
+  for (auto& it : items) maxk = std::max(maxk, item_steps(it));
   const int32_t ni = (int32_t)items.size();
   unsigned hw = std::thread::hardware_concurrency();
   int T = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
@@ -906,7 +944,8 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   // offsets: slot-major, thread-minor (= item order within a slot)
   std::vector<std::vector<int64_t>> off(T, std::vector<int64_t>(slots, 0));
   int64_t total = 0;
-  static const int kind_of[SK_N] = {L_NEGATE, L_INPANEL, L_DIAG, L_PANEL, L_TRAIL, L_TRAIL};
+  auto kind_of = [](int l) { return l == SK_NEG ? L_NEGATE : l == SK_INP ? L_INPANEL : l == SK_DIA ? L_DIAG
+                                 : l == SK_PAN ? L_PANEL : L_TRAIL; };
   for (size_t sl = 0; sl < slots; ++sl) {
     int64_t n = 0;
     double f = 0.0;
@@ -917,7 +956,7 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
     }
     if (n > 0) {
       const int k = (int)(sl / SK_N), l = (int)(sl % SK_N);
-      FactorLaunch L{kind_of[l], k, total, n, f, 0, false};
+      FactorLaunch L{kind_of(l), k, total, n, f, 0, false};
       if (lookahead) {
         if (l == SK_RST) { L.stream = 1; L.wait = true; }   // after the panel and the next-panel update
         if (l == SK_NXT || l == SK_NEG) L.wait = true;     // after the previous bulk update

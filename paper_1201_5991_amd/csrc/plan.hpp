@@ -140,6 +140,7 @@ struct FactorItemDesc {
   const int32_t* sptr = nullptr;
   const int32_t* srow = nullptr;
   const int32_t* gtile = nullptr;
+  const int32_t* gheight = nullptr;     // height of every group in the dissection tree
   int32_t ngroups = 0;
 };
 
@@ -161,7 +162,11 @@ struct FactorSchedule {
 
 // panel: tile columns per panel.  lookahead: split each trailing update into
 // the next panel's columns (stream 0) and the rest (stream 1), so that the
-// next panel's factorization overlaps the bulk of the update.
+// next panel's factorization overlaps the bulk of the update (items with a
+// tile structure keep one stream).  Launch k is a step index: the tile column
+// for items scheduled by envelope; for items with a tile structure the groups
+// of one dissection height advance together (step = first step of the height
+// + column within the group).
 void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out,
                            bool lookahead = false);
 

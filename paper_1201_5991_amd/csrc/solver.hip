@@ -679,6 +679,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         D.K.items[b].sptr = S.sptr.data();
         D.K.items[b].srow = S.srow.data();
         D.K.items[b].gtile = S.gtile.data();
+        D.K.items[b].gheight = S.gheight.data();
         D.K.items[b].ngroups = (int32_t)S.gtile.size() - 1;
       }
     }
@@ -1002,8 +1003,26 @@ mlbddc_status Handle::validate_level(int li, int part) {
       if (J.items[i].e1 + J.items[i].e2 > J.nt[i]) return bad(L + "elimination beyond the matrix");
       if ((int)J.env[i].size() != J.nt[i]) return bad(L + "envelope size");
       if (J.nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
+      // tile structure: a column's rows below the diagonal lie in its own group or in higher groups
+      const FactorItemDesc& it = J.items[i];
+      if (it.sptr) {
+        if (it.e2 != 0 || !it.gtile || !it.gheight || it.ngroups < 1 || it.gtile[0] != 0 || it.gtile[it.ngroups] != it.e1)
+          return bad(L + "tile structure groups");
+        std::vector<int32_t> grp(it.e1, 0);
+        for (int g = 0; g < it.ngroups; ++g) {
+          if (it.gtile[g + 1] < it.gtile[g]) return bad(L + "tile structure groups");
+          for (int k = it.gtile[g]; k < it.gtile[g + 1]; ++k) grp[k] = g;
+        }
+        for (int k = 0; k < it.e1; ++k)
+          for (int32_t q = it.sptr[k]; q < it.sptr[k + 1]; ++q) {
+            const int r = it.srow[q];
+            if (r <= k || r >= J.nt[i]) return bad(L + "tile structure rows");
+            if (r < it.e1 && grp[r] != grp[k] && it.gheight[grp[r]] <= it.gheight[grp[k]])
+              return bad(L + "dissection groups couple out of order");
+          }
+      }
     }
-    if (ni >= (1u << 24)) return bad(L + "too many matrices for the task encoding");
+    if ((int64_t)ni >= MAX_TASK_ITEMS) return bad(L + "too many matrices for the task encoding");
     // every task against its launch kind and its matrix (launches split over threads)
     auto check = [&](size_t l0, size_t l1) -> const char* {
       for (size_t l = l0; l < l1; ++l) {
@@ -1012,15 +1031,15 @@ mlbddc_status Handle::validate_level(int li, int part) {
         for (int64_t q = F.first; q < F.first + F.count; ++q) {
           uint64_t t = J.sched.tasks[q];
           size_t it = (size_t)task_item(t);
-          int r = task_r(t), c = task_s(t), kf = task_kf(t);
+          int r = task_r(t), c = task_s(t), kf = task_kf(t), kl = kf + task_nk(t);
           if (it >= ni) return "task item";
           int nt = J.nt[it], ee = J.items[it].e1 + J.items[it].e2;
           if (r >= nt || c > r) return "task tile";
           switch (F.kind) {
-            case L_DIAG: if (r != F.k || c != F.k || F.k >= ee) return "diag task"; break;
-            case L_PANEL: if (c != F.k || r <= F.k || F.k >= ee) return "panel task"; break;
-            case L_INPANEL: if (c != F.k || kf >= F.k) return "in-panel task"; break;
-            case L_TRAIL: if (c <= F.k || kf > F.k) return "trailing task"; break;
+            case L_DIAG: if (r != c || c >= ee) return "diag task"; break;
+            case L_PANEL: if (r <= c || c >= ee) return "panel task"; break;
+            case L_INPANEL: if (kl != c - 1 || kf > kl) return "in-panel task"; break;
+            case L_TRAIL: if (c <= kl || kl >= ee) return "trailing task"; break;
             case L_NEGATE: if (c < J.items[it].e1) return "negate task"; break;
             default: return "task kind";
           }
