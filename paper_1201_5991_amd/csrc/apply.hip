@@ -165,6 +165,95 @@ __global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* 
   }
 }
 
+// ------------------------------------------------------------ tile lists
+// One wavefront per listed tile.  Lane l = 16 cq + sub loads rows
+// 4 sub .. 4 sub + 3 of the columns 4 m + cq (m = 0..15) as 16-byte vectors,
+// so one instruction reads four whole columns; the sums are finished across
+// lanes by butterflies (a lane keeps half of its partial sums, adds the
+// partner's matching half and passes on the other), which leaves the entry
+// 4 sub + cq of T x (trans 0) or of T^T x (trans 1) in lane l.
+__device__ inline double tile_quad_dot(const double* __restrict__ T, int trans, const double* x, int lane) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int sub = lane & 15, cq = lane >> 4;
+  double v[16][4];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const d2* q = reinterpret_cast<const d2*>(T + (4 * m + cq) * TS + 4 * sub);
+    const d2 a = q[0], b = q[1];
+    v[m][0] = a[0];
+    v[m][1] = a[1];
+    v[m][2] = b[0];
+    v[m][3] = b[1];
+  }
+  if (!trans) {
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const double xb = x[4 * m + cq];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r[i] += v[m][i] * xb;
+    }
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double send = b5 ? r[k] : r[k + 2], keep = b5 ? r[k + 2] : r[k];
+      r[k] = keep + __shfl_xor(send, 32);
+    }
+    const double send = b4 ? r[0] : r[1], keep = b4 ? r[1] : r[0];
+    return keep + __shfl_xor(send, 16);
+  }
+  double xr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) xr[i] = x[4 * sub + i];
+  double c[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) c[m] = (v[m][0] * xr[0] + v[m][1] * xr[1]) + (v[m][2] * xr[2] + v[m][3] * xr[3]);
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1) {
+    const bool bit = (sub & h) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double send = bit ? c[k] : c[k + h], keep = bit ? c[k + h] : c[k];
+      c[k] = keep + __shfl_xor(send, h);
+    }
+  }
+  return c[0];
+}
+
+constexpr int TL_WAVES = 4;
+
+__global__ void __launch_bounds__(TL_WAVES * 64) k_tl_products(int trans, const TileRef* __restrict__ tiles, int64_t n,
+                                                              const double* __restrict__ A, const double* __restrict__ x,
+                                                              double* __restrict__ P) {
+  __shared__ double sx[TL_WAVES][TS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * TL_WAVES + w;
+  if (e >= n) return;
+  const TileRef R = tiles[e];
+  sx[w][lane] = x[R.x + lane];
+  __builtin_amdgcn_wave_barrier();
+  const double val = tile_quad_dot(A + R.a, trans, sx[w], lane);
+  P[e * TS + 4 * (lane & 15) + (lane >> 4)] = val;
+}
+
+__global__ void __launch_bounds__(256) k_tl_reduce(const OutRef* __restrict__ outs, int64_t n, const double* __restrict__ P,
+                                                   double* y, double alpha, int acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= n) return;
+  const OutRef O = outs[o];
+  double s0 = 0.0, s1 = 0.0;
+  int p = O.p0;
+  for (; p + 1 < O.p1; p += 2) {
+    s0 += P[(int64_t)p * TS + lane];
+    s1 += P[(int64_t)(p + 1) * TS + lane];
+  }
+  if (p < O.p1) s0 += P[(int64_t)p * TS + lane];
+  double v = alpha * (s0 + s1);
+  if (acc) v += y[O.y + lane];
+  y[O.y + lane] = v;
+}
+
 // ------------------------------------------------------------------ trsv
 // Blocked triangular solve with the interior factor over one group of tile
 // rows per workgroup of eight wavefronts (the nonzero tiles of a row or a
@@ -424,6 +513,15 @@ template <typename TI, typename TO>
 void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_scatter<TI, TO>), dim3(grid_for(n)), dim3(256), 0, st, n, idx, in, out);
+}
+
+void launch_tile_list_mv(hipStream_t st, bool trans, const TileRef* tiles, int64_t ntiles, const OutRef* outs, int64_t nouts,
+                         const double* A, const double* x, double* P, double* y, double alpha, bool acc) {
+  if (nouts <= 0) return;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_tl_products, dim3((unsigned)((ntiles + TL_WAVES - 1) / TL_WAVES)), dim3(TL_WAVES * 64), 0, st,
+                       trans ? 1 : 0, tiles, ntiles, A, x, P);
+  hipLaunchKernelGGL(k_tl_reduce, dim3((unsigned)((nouts + 3) / 4)), dim3(256), 0, st, outs, nouts, P, y, alpha, acc ? 1 : 0);
 }
 
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,

@@ -90,6 +90,17 @@ void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int6
 template <typename TI, typename TO>
 void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out);
 
+// Tile-list products with FP64 tiles: entry e multiplies the 64x64 tile at
+// element offset tiles[e].a (transposed if trans) by the 64-block of x at
+// tiles[e].x into the scratch vector P[64 e ..]; then output o sums its entries
+// outs[o].p0 .. outs[o].p1 - 1 in order:  y[y .. y + 63] = alpha * sum (+ y if acc).
+// Used where a block's nonzero tiles are a sparse subset (the L_GI products
+// and the off-group parts of the triangular solves).
+struct TileRef { int64_t a, x; };
+struct OutRef { int64_t y; int32_t p0, p1; };
+void launch_tile_list_mv(hipStream_t st, bool trans, const TileRef* tiles, int64_t ntiles, const OutRef* outs, int64_t nouts,
+                         const double* A, const double* x, double* P, double* y, double alpha, bool acc);
+
 // Blocked triangular solves with the interior factor of tile-packed FP64 K
 // matrices and the stored inverse diagonal tiles.  One workgroup per item: a
 // group of tile rows k0..k1-1 of one matrix; the items of one launch must not

@@ -121,7 +121,7 @@ struct LevelDev {
   double* wI = nullptr; // flat interior FP64 (level 1 condensation)
   void* partial = nullptr;
   // tile mat-vec sets
-  MvSet mvS, mvG, mvPsiN, mvPsiT, mvPre, mvPreT, mvPostN, mvLgi, mvLgiT;
+  MvSet mvS, mvG, mvPsiN, mvPsiT, mvPre, mvPreT, mvPostN;
   // triangular solves: items sorted by dissection height (trsv_lvl[h] = first
   // item of height h, last entry = item count) and the tile lists
   std::vector<TrsvDesc> trsv_h;
@@ -129,6 +129,18 @@ struct LevelDev {
   std::vector<int32_t> tr_rptr, tr_rcol, tr_cptr, tr_crow;
   TrsvDesc* d_trsv = nullptr;
   int32_t *d_tr_rptr = nullptr, *d_tr_rcol = nullptr, *d_tr_cptr = nullptr, *d_tr_crow = nullptr;
+  // tile-list products over nonzero tiles of the level-1 factor: L_GI and
+  // L_GI^T (condensation, recovery) and, per dissection height, the coupling of
+  // a height's groups to lower groups (forward) or higher groups (backward)
+  struct TileList {
+    std::vector<TileRef> t;
+    std::vector<OutRef> o;
+    TileRef* dt = nullptr;
+    OutRef* dout = nullptr;
+  };
+  TileList lgiN, lgiT;
+  std::vector<TileList> trF, trB;
+  double* tl_partial = nullptr;
   // coarse matrices of this level (inputs of the next level's assembly)
   double* kc_compact = nullptr;
   std::vector<int64_t> kc_off;
@@ -376,11 +388,12 @@ void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bo
                              acc, (TA*)partial, s.max_out);
 }
 
-// Lists of the nonzero interior tiles of every level-1 factor (from the
-// tile structure, else every tile of the envelope) and one triangular-solve
-// item per interior group, ordered by the group's height in the dissection
-// tree: the groups of one height depend only on lower groups (forward) or
-// higher groups (backward).
+// Lists of the nonzero tiles of every level-1 factor (from the tile
+// structure, else every tile of the envelope): one triangular-solve item per
+// interior group with the group's own tiles, ordered by the group's height in
+// the dissection tree (the groups of one height depend only on lower groups
+// in the forward solve and on higher groups in the backward one); the tiles
+// coupling a group to other groups and the L_GI tiles go to tile lists.
 mlbddc_status Handle::build_trsv(LevelDev& D) {
   const LevelPlan& P = *D.P;
   D.trsv_h.clear();
@@ -388,26 +401,64 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
   D.tr_rcol.clear();
   D.tr_cptr.clear();
   D.tr_crow.clear();
+  D.lgiN = LevelDev::TileList{};
+  D.lgiT = LevelDev::TileList{};
+  D.trF.clear();
+  D.trB.clear();
   std::vector<std::vector<TrsvDesc>> by_h;
-  std::vector<int32_t> rcnt;
+  std::vector<std::vector<int32_t>> cols;  // per tile column k: rows r > k of L (interior and interface)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> grow;  // per interface row: (column, -) pairs
+  std::vector<int32_t> grp, g0v, g1v, hgt, rcnt;
   for (int b = 0; b < P.n_sub; ++b) {
     const SubPlan& S = P.subs[b];
-    const int tI = (int)(S.nIp / TS);
+    const int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS), nt = D.K.nt[b];
+    const int64_t aoff = D.K.off[b], io = D.iofs[b], go = D.gofs[b];
+    auto tile = [&](int r, int c) { return aoff + tile_index(r, c, nt) * TE; };
+    cols.assign(tI, {});
+    for (int k = 0; k < tI; ++k) {
+      if (!S.sptr.empty()) {
+        for (int32_t q = S.sptr[k]; q < S.sptr[k + 1]; ++q) cols[k].push_back(S.srow[q]);
+      } else {
+        for (int r = k + 1; r < tI + tG; ++r)
+          if (S.envK[r] <= k) cols[k].push_back(r);
+      }
+    }
+    // groups
+    grp.assign(tI, 0);
+    g0v.clear();
+    g1v.clear();
+    hgt.clear();
+    if (!S.gtile.empty()) {
+      for (size_t g = 0; g + 1 < S.gtile.size(); ++g) {
+        g0v.push_back(S.gtile[g]);
+        g1v.push_back(S.gtile[g + 1]);
+        hgt.push_back(S.gheight[g]);
+        for (int k = S.gtile[g]; k < S.gtile[g + 1]; ++k) grp[k] = (int32_t)g;
+      }
+    } else {
+      g0v.push_back(0);
+      g1v.push_back(tI);
+      hgt.push_back(0);
+    }
+    const int H = *std::max_element(hgt.begin(), hgt.end()) + 1;
+    if ((int)D.trF.size() < H) {
+      D.trF.resize(H);
+      D.trB.resize(H);
+    }
+    // order check: a tile below the diagonal couples a column to its own group or a higher one
+    for (int k = 0; k < tI; ++k)
+      for (int32_t r : cols[k])
+        if (r < tI && grp[r] != grp[k] && hgt[grp[r]] <= hgt[grp[k]])
+          return fail(MLBDDC_E_ARG, "internal layout check failed: dissection groups couple out of order");
+    // in-group lists for the triangular solves (columns, then their transpose)
     const int32_t p_col = (int32_t)D.tr_cptr.size(), p_row = (int32_t)D.tr_rptr.size();
-    // columns: rows r > k inside the interior
     const size_t c0 = D.tr_crow.size();
     for (int k = 0; k < tI; ++k) {
       D.tr_cptr.push_back((int32_t)D.tr_crow.size());
-      if (!S.sptr.empty()) {
-        for (int32_t q = S.sptr[k]; q < S.sptr[k + 1]; ++q)
-          if (S.srow[q] < tI) D.tr_crow.push_back(S.srow[q]);
-      } else {
-        for (int r = k + 1; r < tI; ++r)
-          if (S.envK[r] <= k) D.tr_crow.push_back(r);
-      }
+      for (int32_t r : cols[k])
+        if (r < tI && grp[r] == grp[k]) D.tr_crow.push_back(r);
     }
     D.tr_cptr.push_back((int32_t)D.tr_crow.size());
-    // rows: the transpose (columns ascending)
     rcnt.assign(tI + 1, 0);
     for (size_t q = c0; q < D.tr_crow.size(); ++q) rcnt[D.tr_crow[q] + 1]++;
     for (int r = 0; r < tI; ++r) rcnt[r + 1] += rcnt[r];
@@ -416,29 +467,50 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
     for (int r = 0; r <= tI; ++r) D.tr_rptr.push_back(r0 + rcnt[r]);
     for (int k = 0; k < tI; ++k)
       for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) D.tr_rcol[r0 + rcnt[D.tr_crow[q]]++] = k;
-    // the items of one height must not depend on one another: a tile (r, k)
-    // below the diagonal couples k to a lower group of the tree or its own
-    if (!S.gtile.empty()) {
-      std::vector<int32_t> grp(tI, 0);
-      for (size_t g = 0; g + 1 < S.gtile.size(); ++g)
-        for (int k = S.gtile[g]; k < S.gtile[g + 1]; ++k) grp[k] = (int32_t)g;
-      for (int k = 0; k < tI; ++k)
-        for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) {
-          const int32_t gr = grp[D.tr_crow[q]], gk = grp[k];
-          if (gr != gk && S.gheight[gr] <= S.gheight[gk])
-            return fail(MLBDDC_E_ARG, "internal layout check failed: dissection groups couple out of order");
-        }
+    for (size_t g = 0; g < g0v.size(); ++g) {
+      if (g1v[g] <= g0v[g]) continue;
+      if ((int)by_h.size() <= hgt[g]) by_h.resize(hgt[g] + 1);
+      by_h[hgt[g]].push_back(TrsvDesc{aoff, nt, g0v[g], g1v[g], p_row, p_col, 0, D.K.inv_off[b], io});
     }
-    // items
-    auto add = [&](int k0, int k1, int h) {
-      if (k1 <= k0) return;
-      if ((int)by_h.size() <= h) by_h.resize(h + 1);
-      by_h[h].push_back(TrsvDesc{D.K.off[b], D.K.nt[b], k0, k1, p_row, p_col, 0, D.K.inv_off[b], D.iofs[b]});
-    };
-    if (!S.gtile.empty()) {
-      for (size_t g = 0; g + 1 < S.gtile.size(); ++g) add(S.gtile[g], S.gtile[g + 1], S.gheight[g]);
-    } else {
-      add(0, tI, 0);
+    // coupling lists: forward, row k of a group takes the tiles (k, s) of lower
+    // groups; backward, column k takes the tiles (r, k) of higher groups
+    {
+      std::vector<std::vector<int32_t>> rowlow(tI);
+      for (int s = 0; s < tI; ++s)
+        for (int32_t r : cols[s])
+          if (r < tI && grp[r] != grp[s]) rowlow[r].push_back(s);
+      for (int k = 0; k < tI; ++k) {
+        LevelDev::TileList& F = D.trF[hgt[grp[k]]];
+        if (!rowlow[k].empty()) {
+          const int32_t p0 = (int32_t)F.t.size();
+          for (int32_t sc : rowlow[k]) F.t.push_back(TileRef{tile(k, sc), io + (int64_t)sc * TS});
+          F.o.push_back(OutRef{io + (int64_t)k * TS, p0, (int32_t)F.t.size()});
+        }
+        LevelDev::TileList& Bk = D.trB[hgt[grp[k]]];
+        const int32_t q0 = (int32_t)Bk.t.size();
+        for (int32_t r : cols[k])
+          if (r < tI && grp[r] != grp[k]) Bk.t.push_back(TileRef{tile(r, k), io + (int64_t)r * TS});
+        if ((int32_t)Bk.t.size() > q0) Bk.o.push_back(OutRef{io + (int64_t)k * TS, q0, (int32_t)Bk.t.size()});
+      }
+    }
+    // L_GI: column k takes its interface rows (transposed product into w_I);
+    // interface row r takes its columns (product into the interface block)
+    {
+      std::vector<std::vector<int32_t>> gcols(tG);
+      for (int k = 0; k < tI; ++k) {
+        const int32_t q0 = (int32_t)D.lgiT.t.size();
+        for (int32_t r : cols[k])
+          if (r >= tI) {
+            D.lgiT.t.push_back(TileRef{tile(r, k), go + (int64_t)(r - tI) * TS});
+            gcols[r - tI].push_back(k);
+          }
+        if ((int32_t)D.lgiT.t.size() > q0) D.lgiT.o.push_back(OutRef{io + (int64_t)k * TS, q0, (int32_t)D.lgiT.t.size()});
+      }
+      for (int r = 0; r < tG; ++r) {  // every interface block is written (sum of nothing = 0)
+        const int32_t q0 = (int32_t)D.lgiN.t.size();
+        for (int32_t k : gcols[r]) D.lgiN.t.push_back(TileRef{tile(tI + r, k), io + (int64_t)k * TS});
+        D.lgiN.o.push_back(OutRef{go + (int64_t)r * TS, q0, (int32_t)D.lgiN.t.size()});
+      }
     }
   }
   D.trsv_lvl.assign(1, 0);
@@ -446,18 +518,38 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
     D.trsv_h.insert(D.trsv_h.end(), v.begin(), v.end());
     D.trsv_lvl.push_back((int32_t)D.trsv_h.size());
   }
+  if (D.trF.size() < by_h.size()) {
+    D.trF.resize(by_h.size());
+    D.trB.resize(by_h.size());
+  }
   mlbddc_status st;
   if ((st = upload(&D.d_trsv, D.trsv_h))) return st;
   if ((st = upload(&D.d_tr_rptr, D.tr_rptr))) return st;
   if ((st = upload(&D.d_tr_rcol, D.tr_rcol))) return st;
   if ((st = upload(&D.d_tr_cptr, D.tr_cptr))) return st;
-  return upload(&D.d_tr_crow, D.tr_crow);
+  if ((st = upload(&D.d_tr_crow, D.tr_crow))) return st;
+  int64_t pmax = 1;
+  auto up = [&](LevelDev::TileList& T) -> mlbddc_status {
+    pmax = std::max<int64_t>(pmax, (int64_t)T.t.size());
+    mlbddc_status s2;
+    if ((s2 = upload(&T.dt, T.t))) return s2;
+    return upload(&T.dout, T.o);
+  };
+  if ((st = up(D.lgiN)) || (st = up(D.lgiT))) return st;
+  for (auto& T : D.trF)
+    if ((st = up(T))) return st;
+  for (auto& T : D.trB)
+    if ((st = up(T))) return st;
+  return dalloc(&D.tl_partial, pmax * TS);
 }
 
 void Handle::run_trsv(LevelDev& D, bool transposed) {
   const int nh = (int)D.trsv_lvl.size() - 1;
   for (int i = 0; i < nh; ++i) {
     const int h = transposed ? nh - 1 - i : i;
+    LevelDev::TileList& C = transposed ? D.trB[h] : D.trF[h];
+    launch_tile_list_mv(stream, transposed, C.dt, (int64_t)C.t.size(), C.dout, (int64_t)C.o.size(), (const double*)D.K.buf,
+                        D.wI, D.tl_partial, D.wI, -1.0, true);
     launch_trsv(stream, transposed, D.d_trsv + D.trsv_lvl[h], D.trsv_lvl[h + 1] - D.trsv_lvl[h], (const double*)D.K.buf,
                 (const double*)D.K.inv, D.d_tr_rptr, D.d_tr_rcol, D.d_tr_cptr, D.d_tr_crow, D.wI);
   }
@@ -807,14 +899,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     enqueue_async(li, true);
     // K-job tile mat-vecs
     {
-      std::vector<MvDesc> s, pre, lgi;
+      std::vector<MvDesc> s, pre;
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
         int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
         if (li == 0) {
           s.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, tI, tG, D.gofs[b], D.gofs[b], 0, nullptr});
-          if (tI > 0 && tG > 0)
-            lgi.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, 0, tI, D.iofs[b], D.gofs[b], 0, nullptr});
         } else if (tI > 0) {
           int tId = tI + tG;
           pre.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tId, tI, D.iofs[b], D.iofs[b], 0, nullptr});
@@ -822,12 +912,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
       if (li == 0) {
         if ((st = build_mv(D.mvS, MV_SYM, s))) return st;
-        // L_GI products: condensation (N: y_G = L_GI w_I) and recovery (T: y_I = L_GI^T u_G)
-        std::vector<MvDesc> lt = lgi;
-        for (auto& d : lt) { d.x_off = 0; }
-        for (size_t i = 0; i < lgi.size(); ++i) { lt[i].x_off = lgi[i].y_off; lt[i].y_off = lgi[i].x_off; }
-        if ((st = build_mv(D.mvLgi, MV_N, lgi))) return st;
-        if ((st = build_mv(D.mvLgiT, MV_T, lt))) return st;
+        // triangular solves and the L_GI products of condensation and recovery
         if ((st = build_trsv(D))) return st;
       } else {
         if ((st = build_mv(D.mvPre, MV_SYM, pre))) return st;
@@ -949,7 +1034,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
     // partial-sum scratch: the largest of this level's products
     int64_t pmax = 1;
-    for (MvSet* s : {&D.mvS, &D.mvG, &D.mvPsiN, &D.mvPsiT, &D.mvPre, &D.mvPreT, &D.mvPostN, &D.mvLgi, &D.mvLgiT})
+    for (MvSet* s : {&D.mvS, &D.mvG, &D.mvPsiN, &D.mvPsiT, &D.mvPre, &D.mvPreT, &D.mvPostN})
       pmax = std::max(pmax, s->partial_elems);
     if ((st = dalloc((double**)&D.partial, pmax))) return st;
     mark("  constraints, coarse, M mat-vecs");
@@ -1110,8 +1195,18 @@ mlbddc_status Handle::validate_level(int li, int part) {
   };
   if (li == 0) {
     if (!mv_ok(D.mvS, D.K, D.nG_flat, D.nG_flat)) return bad(L + "S mat-vec");
-    if (!mv_ok(D.mvLgi, D.K, D.nI_flat, D.nG_flat)) return bad(L + "L_GI mat-vec");
-    if (!mv_ok(D.mvLgiT, D.K, D.nG_flat, D.nI_flat)) return bad(L + "L_GI^T mat-vec");
+    // tile lists: tiles inside the K job, x and y blocks inside their vectors, entries in range
+    auto tl_ok = [&](const LevelDev::TileList& T, int64_t xlen, int64_t ylen) {
+      for (const TileRef& t : T.t)
+        if (t.a < 0 || t.a + TE > D.K.elems || t.x < 0 || t.x + TS > xlen) return false;
+      for (const OutRef& o : T.o)
+        if (o.y < 0 || o.y + TS > ylen || o.p0 < 0 || o.p1 < o.p0 || o.p1 > (int64_t)T.t.size()) return false;
+      return true;
+    };
+    if (!tl_ok(D.lgiN, D.nI_flat, D.nG_flat) || !tl_ok(D.lgiT, D.nG_flat, D.nI_flat)) return bad(L + "L_GI tile list");
+    for (size_t h = 0; h < D.trF.size(); ++h)
+      if (!tl_ok(D.trF[h], D.nI_flat, D.nI_flat) || !tl_ok(D.trB[h], D.nI_flat, D.nI_flat)) return bad(L + "coupling tile list");
+    if (D.trF.size() + 1 < D.trsv_lvl.size()) return bad(L + "coupling tile list heights");
     for (const TrsvDesc& t : D.trsv_h) {
       if (t.k0 < 0 || t.k1 <= t.k0 || t.k1 > t.a_nt || t.v_off + (int64_t)t.k1 * TS > D.nI_flat ||
           t.inv_off + (int64_t)t.k1 * TE > D.K.inv_elems || t.p_row < 0 || t.p_col < 0 ||
@@ -1366,8 +1461,8 @@ mlbddc_status Handle::condense(const double* f, double* g) {
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   launch_gather<double, double>(stream, D.nI_flat, D.d_iidx, nullptr, f, D.wI);
   run_trsv(D, false);
-  launch_fill(stream, D.nG_flat, 0.0, D.tG);
-  run_mv<double, double, double>(D.mvLgi, D.K, D.wI, D.tG, -1.0, false, D.partial);
+  launch_tile_list_mv(stream, false, D.lgiN.dt, (int64_t)D.lgiN.t.size(), D.lgiN.dout, (int64_t)D.lgiN.o.size(),
+                      (const double*)D.K.buf, D.wI, D.tl_partial, D.tG, -1.0, false);
   launch_gather<double, double>(stream, nif, D.d_iface_dofs, nullptr, f, g);
   launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.tG, g, 1.0);
   HIPCHK(hipGetLastError());
@@ -1378,7 +1473,8 @@ mlbddc_status Handle::recover(const double* uhat, double* u) {
   LevelDev& D = lev[0];
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, uhat, D.gd);
-  run_mv<double, double, double>(D.mvLgiT, D.K, D.gd, D.wI, -1.0, true, D.partial);
+  launch_tile_list_mv(stream, true, D.lgiT.dt, (int64_t)D.lgiT.t.size(), D.lgiT.dout, (int64_t)D.lgiT.o.size(),
+                      (const double*)D.K.buf, D.gd, D.tl_partial, D.wI, -1.0, true);
   run_trsv(D, true);
   launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, D.wI, u);
   launch_scatter_idx(stream, nif, D.d_iface_dofs, uhat, u);
