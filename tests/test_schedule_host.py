@@ -1,0 +1,57 @@
+"""Host factorization schedule (CPU): nested-dissection interiors, the tile
+structure and the schedule in which groups of one dissection height advance
+together.  A small C++ program built from the library's planner runs the task
+list of one subdomain in launch order on a random SPD matrix with the
+subdomain's element pattern and compares with a dense partial Cholesky of the
+interior columns (it also checks that no launch writes a tile twice)."""
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1201_5991_amd.solver import Problem
+from workloads import box_workload
+from workloads.gen import uniform_cuts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1201_5991_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    cxx = shutil.which("g++") or shutil.which("clang++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    d = tmp_path_factory.mktemp("sched")
+    exe = str(d / "schedule_check")
+    cmd = [cxx, "-O2", "-std=c++17", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+           os.path.join(ROOT, "tests", "schedule_check.cpp"), os.path.join(CSRC, "plan.cpp"), "-o", exe, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    # 3x3x3 subdomains of 9^3 elastic hexahedra: 8^3 interior nodes of the centre
+    # subdomain (1536 DOFs) are cut into two parts and a separator
+    n = 27
+    w = box_workload("sched", "elasticity", (n,) * 3, [uniform_cuts(n, 3)] * 3, groups=(), young=None, seed=0)
+    p = Problem(w)
+    p.elem_nodes.tofile(d / "elem_nodes.bin")
+    p.dirichlet.tofile(d / "dirichlet.bin")
+    p.elem_to_sub.tofile(d / "elem_to_sub.bin")
+    for i, par in enumerate(p.parents):
+        np.asarray(par, dtype=np.int32).tofile(d / f"parent{i}.bin")
+    (d / "meta.txt").write_text(f"{p.dim} {p.ndof} {p.n_nodes} {p.n_elems} {p.nodes_per_elem} {p.n_levels} "
+                                f"{len(p.parents)} {p.constraints}\n")
+    return exe, str(d)
+
+
+@pytest.mark.parametrize("sub,panel", [(13, 2), (0, 4), (4, 3)])
+def test_schedule_reproduces_dense_cholesky(checker, sub, panel):
+    exe, d = checker
+    r = subprocess.run([exe, d, str(sub), str(panel)], capture_output=True, text=True, timeout=300)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    # the centre subdomain is cut by the dissection (several groups)
+    if sub == 13:
+        assert int(r.stdout.split(" groups ")[1].split()[0]) >= 3
