@@ -49,10 +49,15 @@ template <> struct Mfma<float> {
 // optionally transposed, converting from TS_ to T.
 template <typename T, typename TSRC>
 __device__ inline void stage_tile(T* __restrict__ s, const TSRC* __restrict__ g, bool trans) {
-  for (int idx = threadIdx.x; idx < TE; idx += blockDim.x) {
-    int i = idx & (TS - 1), j = idx >> 6;
-    T v = (T)g[idx];
-    if (trans) s[i * LDT + j] = v; else s[j * LDT + i] = v;
+  // 256 threads: every load is issued before the first LDS store
+  constexpr int PER = TE / 256;
+  TSRC v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) v[q] = g[threadIdx.x + 256 * q];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + 256 * q, i = idx & (TS - 1), j = idx >> 6;
+    if (trans) s[i * LDT + j] = (T)v[q]; else s[j * LDT + i] = (T)v[q];
   }
 }
 
@@ -230,6 +235,7 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
                                               int32_t* err, T* A, T* Inv) {
   __shared__ T sA[TS * LDT];
+  __shared__ T colbuf[16];
   typedef typename Mfma<T>::acc_t acc_t;
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
@@ -244,44 +250,59 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
     const int j0 = 16 * jb;
     T* D = &sA[j0 * LDT + j0];
     if (w == 0) {
-      // lane i of every row of 16 lanes keeps row i of the block (d) and row
-      // i of V, the inverse of the block's factor (v).  Step j finishes
-      // column j of L and eliminates it from the trailing block, then
-      // finishes row j of V (scale by 1/L(j, j)) and eliminates it from the
-      // rows of V below, which needs only column j of L.
-      const int i = lane & 15;
-      T d[16], v[16];
+      // Lane l = 16 q + i keeps row i of the block in the columns m = 4 t + q
+      // (d[t]) and row i of V, the inverse of the block's factor, in the same
+      // columns (v[t]).  Step j: the lanes owning column j put it in LDS; every
+      // lane reads the pivot, its own row's entry and the entries of its
+      // columns, finishes column j of L and eliminates it from its trailing
+      // columns; then row j of V is scaled and eliminated from the rows of V
+      // below (row j of V lives in lane j of each row of 16 lanes, broadcast
+      // with DPP).
+      const int i = lane & 15, q = lane >> 4;
+      T d[4], v[4];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        d[m] = D[m * LDT + i];
-        v[m] = m == i ? (T)1 : (T)0;
+      for (int t = 0; t < 4; ++t) {
+        d[t] = D[(4 * t + q) * LDT + i];
+        v[t] = 4 * t + q == i ? (T)1 : (T)0;
       }
       static_for<0, 16>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        T piv = row_bcast<j>(d[j]);
+        constexpr int j = decltype(J)::value, qj = j & 3, tj = j >> 2;
+        if (q == qj) colbuf[i] = d[tj];
+        __builtin_amdgcn_wave_barrier();
+        T piv = colbuf[j];
+        const T ai = colbuf[i];
+        T am[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) am[t] = 4 * t + 3 > j ? colbuf[(4 * t + q) & 15] : (T)0;
+        __builtin_amdgcn_wave_barrier();
         const bool ok = piv > (T)0;
         badcol = (!ok && badcol < 0) ? j0 + j : badcol;
         piv = ok ? piv : (T)NAN;
         const T inv = rsqrt_pivot(piv), sq = piv * inv;
-        d[j] = i > j ? d[j] * inv : (i == j ? sq : (T)0);
-        static_for<j + 1, 16>([&](auto M) {
-          constexpr int m = decltype(M)::value;
-          d[m] -= d[j] * row_bcast<m>(d[j]);
-        });
-        const T lij = i > j ? d[j] : (T)0;
-        static_for<0, j + 1>([&](auto C) {
-          constexpr int c = decltype(C)::value;
-          if (i == j) v[c] *= inv;
-          v[c] -= lij * row_bcast<j>(v[c]);
-        });
-      });
-      if (lane < 16) {
+        const T lij = i > j ? ai * inv : (i == j ? sq : (T)0);
+        if (q == qj) d[tj] = lij;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          gA[(j0 + m) * TS + j0 + i] = m <= i ? d[m] : (T)0;
-          if (m < i) D[m * LDT + i] = d[m];
-          if (m <= i) D[i * LDT + m] = v[m];  // V(i, m) at block position (m, i)
-        }
+        for (int t = 0; t < 4; ++t)
+          if (4 * t + 3 > j) {
+            const int m = 4 * t + q;
+            if (m > j) d[t] -= lij * (am[t] * inv);
+          }
+        const T lv = i > j ? lij : (T)0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (4 * t <= j) {
+            const int c = 4 * t + q;
+            if (i == j) v[t] *= inv;
+            const T vj = row_bcast<j>(v[t]);
+            if (c <= j) v[t] -= lv * vj;
+          }
+      });
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int m = 4 * t + q;
+        gA[(j0 + m) * TS + j0 + i] = m <= i ? d[t] : (T)0;
+        if (m < i) D[m * LDT + i] = d[t];
+        if (m <= i) D[i * LDT + m] = v[t];  // V(i, m) at block position (m, i)
       }
     }
     __syncthreads();
@@ -329,8 +350,9 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
   }
   if (tid == 0 && badcol >= 0 && atomicCAS(&err[0], 0, item + 1) == 0) err[1] = k * TS + badcol;
   T* gI = Inv + inv_off[item] + (int64_t)k * TE;
-  for (int idx = tid; idx < TE; idx += blockDim.x) {
-    const int r = idx & (TS - 1), c = idx >> 6;
+#pragma unroll
+  for (int q = 0; q < TE / 256; ++q) {
+    const int idx = tid + 256 * q, r = idx & (TS - 1), c = idx >> 6;
     if ((r >> 4) != (c >> 4)) gA[idx] = r > c ? sA[c * LDT + r] : (T)0;
     gI[idx] = r >= c ? sA[r * LDT + c] : (T)0;
   }
