@@ -8,11 +8,112 @@
 #include <unordered_map>
 #include <numeric>
 #include <thread>
+#include <mutex>
+#include <condition_variable>
+#include <unistd.h>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
 
 namespace mlbddc {
+
+// ------------------------------------------------------------ worker pool
+// Spawning and joining 16 threads costs about half a millisecond, as much as
+// several of the planner's parallel loops themselves, so the loops run on
+// threads that are started once and then wait for work.  One loop at a time
+// uses the pool; a loop started meanwhile (another handle's set-up on another
+// thread, or a loop nested in a body) spawns threads of its own.  After a
+// fork the child starts a new pool (the parent's workers do not exist there).
+namespace {
+
+thread_local bool in_parallel_body = false;  // set while a thread runs a body
+
+class WorkerPool {
+ public:
+  static constexpr int MAXT = 16;
+  explicit WorkerPool(pid_t pid) : pid_(pid) {}
+  pid_t pid() const { return pid_; }
+
+  // false when the pool is busy (the caller then spawns its own threads)
+  bool run(int T, const std::function<void(int)>& body) {
+    if (in_parallel_body) return false;
+    std::unique_lock<std::mutex> own(run_mx_, std::try_to_lock);
+    if (!own.owns_lock()) return false;
+    {
+      std::lock_guard<std::mutex> g(mx_);
+      while ((int)workers_.size() < T - 1) {
+        const int w = (int)workers_.size() + 1;
+        workers_.emplace_back([this, w] { loop(w); });
+        workers_.back().detach();
+      }
+      body_ = &body;
+      active_ = T;
+      pending_ = T - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    in_parallel_body = true;
+    body(0);
+    in_parallel_body = false;
+    std::unique_lock<std::mutex> g(mx_);
+    done_cv_.wait(g, [this] { return pending_ == 0; });
+    body_ = nullptr;
+    return true;
+  }
+
+ private:
+  void loop(int w) {
+    uint64_t seen = 0;
+    {
+      std::lock_guard<std::mutex> g(mx_);
+      seen = gen_ - 1;  // a worker created for the current loop joins it
+    }
+    for (;;) {
+      const std::function<void(int)>* body;
+      {
+        std::unique_lock<std::mutex> g(mx_);
+        cv_.wait(g, [&] { return gen_ != seen; });
+        seen = gen_;
+        if (w >= active_) continue;
+        body = body_;
+      }
+      in_parallel_body = true;
+      (*body)(w);
+      in_parallel_body = false;
+      std::lock_guard<std::mutex> g(mx_);
+      if (--pending_ == 0) done_cv_.notify_one();
+    }
+  }
+
+  pid_t pid_;
+  std::mutex run_mx_, mx_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> workers_;
+  const std::function<void(int)>* body_ = nullptr;
+  int active_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+};
+
+WorkerPool* pool_for_this_process() {
+  static std::mutex mx;
+  static WorkerPool* pool = nullptr;  // never destroyed: its workers wait until the process ends
+  std::lock_guard<std::mutex> g(mx);
+  const pid_t pid = getpid();
+  if (!pool || pool->pid() != pid) pool = new WorkerPool(pid);
+  return pool;
+}
+
+}  // namespace
+
+void parallel_run(int T, const std::function<void(int)>& body) {
+  T = std::max(1, std::min(T, (int)WorkerPool::MAXT));
+  if (T == 1) { body(0); return; }
+  if (pool_for_this_process()->run(T, body)) return;
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back([&body, t] { body(t); });
+  body(0);
+  for (auto& x : th) x.join();
+}
 
 namespace {
 
@@ -41,12 +142,7 @@ template <typename F>
 void parallel_ranges(int64_t n, F&& work) {
   const int T = plan_threads(n);
   if (T <= 1) { work(0, (int64_t)0, n); return; }
-  std::vector<std::thread> th;
-  for (int t = 0; t < T; ++t) {
-    int64_t b0 = n * t / T, b1 = n * (t + 1) / T;
-    th.emplace_back([&, t, b0, b1] { work(t, b0, b1); });
-  }
-  for (auto& x : th) x.join();
+  parallel_run(T, [&](int t) { work(t, n * t / T, n * (t + 1) / T); });
 }
 
 // ------------------------------------------------------ nested dissection
@@ -926,12 +1022,7 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
     b0 = (int32_t)((int64_t)ni * t / T);
     b1 = (int32_t)((int64_t)ni * (t + 1) / T);
   };
-  auto run = [&](auto&& body) {
-    if (T == 1) { body(0); return; }
-    std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t) th.emplace_back([&, t] { body(t); });
-    for (auto& x : th) x.join();
-  };
+  auto run = [&](auto&& body) { parallel_run(T, body); };
   run([&](int t) {
     int32_t b0, b1;
     range(t, b0, b1);

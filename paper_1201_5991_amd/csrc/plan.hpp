@@ -19,6 +19,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "common.hpp"
@@ -169,5 +170,11 @@ struct FactorSchedule {
 // + column within the group).
 void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out,
                            bool lookahead = false);
+
+// Runs body(t) for t = 0..T-1 concurrently and returns when every call has
+// returned; the caller runs t = 0, persistent worker threads the others (a
+// call made while another thread is inside parallel_run, or from inside a
+// body, gets threads of its own).  T is clamped to 1..16.
+void parallel_run(int T, const std::function<void(int)>& body);
 
 }  // namespace mlbddc

@@ -1133,15 +1133,11 @@ mlbddc_status Handle::validate_level(int li, int part) {
       return nullptr;
     };
     const size_t nl = J.sched.launches.size();
-    const size_t T = std::min<size_t>(8, std::max<size_t>(1, J.sched.tasks.size() / 100000));
-    std::vector<std::future<const char*>> parts;
-    for (size_t t = 1; t < T; ++t) parts.push_back(std::async(std::launch::async, check, nl * t / T, nl * (t + 1) / T));
-    const char* why = check(0, nl / T);
-    for (auto& f : parts) {
-      const char* w = f.get();
-      if (!why) why = w;
-    }
-    if (why) return bad(L + why);
+    const int T = (int)std::min<size_t>(8, std::max<size_t>(1, J.sched.tasks.size() / 100000));
+    std::vector<const char*> whys(T, nullptr);
+    parallel_run(T, [&](int t) { whys[t] = check(nl * t / T, nl * (t + 1) / T); });
+    for (const char* w : whys)
+      if (w) return bad(L + w);
     return MLBDDC_OK;
   };
   auto seg_ok = [&](const std::vector<DiagSeg>& v) {
