@@ -1014,7 +1014,7 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   const int32_t ni = (int32_t)items.size();
   unsigned hw = std::thread::hardware_concurrency();
   int T = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
-  T = std::max(1, std::min<int>(T, ni / 8));
+  T = std::max(1, std::min<int>(T, ni / 4));
   const size_t slots = (size_t)maxk * SK_N;
   std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(slots, 0));
   std::vector<std::vector<double>> fl(T, std::vector<double>(slots, 0.0));

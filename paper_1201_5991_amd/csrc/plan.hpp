@@ -20,6 +20,8 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -145,6 +147,27 @@ struct FactorItemDesc {
   int32_t ngroups = 0;
 };
 
+// Allocator whose value construction leaves scalars uninitialized: a vector
+// that is filled completely right after resize() skips the zeroing pass.
+template <typename T>
+struct NoInitAllocator : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAllocator<U>;
+  };
+  NoInitAllocator() = default;
+  template <typename U>
+  NoInitAllocator(const NoInitAllocator<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+
 struct FactorLaunch {
   int kind;
   int k;                                // global tile column of this step
@@ -155,7 +178,7 @@ struct FactorLaunch {
 };
 
 struct FactorSchedule {
-  std::vector<uint64_t> tasks;
+  std::vector<uint64_t, NoInitAllocator<uint64_t>> tasks;  // every element is written by the builder
   std::vector<FactorLaunch> launches;
   double flops = 0.0;                   // dense flops of the tasks (for rooflines)
   int64_t update_tasks = 0;

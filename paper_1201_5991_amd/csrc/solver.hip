@@ -292,16 +292,26 @@ struct Handle {
     }
     return MLBDDC_OK;
   }
-  template <typename T>
-  mlbddc_status upload(T** p, const std::vector<T>& v) {
+  template <typename T, typename A>
+  mlbddc_status upload(T** p, const std::vector<T, A>& v) {
     mlbddc_status st = dalloc(p, (int64_t)v.size());
     if (st) return st;
     if (!v.empty()) {
       if ((st = ensure_ustream())) return st;
       char* h = nullptr;
-      if ((st = stage(sizeof(T) * v.size(), &h))) return st;
-      std::memcpy(h, v.data(), sizeof(T) * v.size());
-      HIPCHK(hipMemcpyAsync(*p, h, sizeof(T) * v.size(), hipMemcpyHostToDevice, ustream));
+      const size_t bytes = sizeof(T) * v.size();
+      if ((st = stage(bytes, &h))) return st;
+      // large arrays (task lists of several MB) are staged by several threads
+      const int nth = (int)std::min<size_t>(8, bytes >> 19);
+      const char* src = reinterpret_cast<const char*>(v.data());
+      if (nth > 1)
+        parallel_run(nth, [&](int t) {
+          const size_t b0 = bytes * t / nth, b1 = bytes * (t + 1) / nth;
+          std::memcpy(h + b0, src + b0, b1 - b0);
+        });
+      else
+        std::memcpy(h, src, bytes);
+      HIPCHK(hipMemcpyAsync(*p, h, bytes, hipMemcpyHostToDevice, ustream));
     }
     return MLBDDC_OK;
   }
@@ -1133,7 +1143,7 @@ mlbddc_status Handle::validate_level(int li, int part) {
       return nullptr;
     };
     const size_t nl = J.sched.launches.size();
-    const int T = (int)std::min<size_t>(8, std::max<size_t>(1, J.sched.tasks.size() / 100000));
+    const int T = (int)std::min<size_t>(16, std::max<size_t>(1, J.sched.tasks.size() / 30000));
     std::vector<const char*> whys(T, nullptr);
     parallel_run(T, [&](int t) { whys[t] = check(nl * t / T, nl * (t + 1) / T); });
     for (const char* w : whys)
@@ -1149,27 +1159,37 @@ mlbddc_status Handle::validate_level(int li, int part) {
   mlbddc_status st;
   if (part == 0) {  // what assembly, weights and the K job use
     if ((st = job_ok(D.K))) return st;
-    for (int64_t e = 0; e + 1 < (int64_t)P.el_local_ptr.size(); ++e) {
-      int b = P.el_sub[e];
-      int64_t nK = (int64_t)D.K.nt[b] * TS;
-      for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
-        if (P.el_local[j] < -1 || (int64_t)P.el_local[j] + P.ndof > nK) return bad(L + "element map");
-      if (li > 0) {
-        const LevelPlan& PP = *lev[li - 1].P;
-        int64_t nloc = (int64_t)(P.el_local_ptr[e + 1] - P.el_local_ptr[e]) * P.ndof;
-        const SubPlan& S = PP.subs[e];
-        if (nloc != S.nc || lev[li - 1].kc_off[e] + nloc * nloc > (int64_t)lev[li - 1].kc_off.back() + (int64_t)PP.subs.back().nc * PP.subs.back().nc)
-          return bad(L + "coarse element matrix");
+    // element maps and subdomain maps, split over threads
+    const int64_t ne = (int64_t)P.el_local_ptr.size() - 1, ns = (int64_t)P.subs.size();
+    const int T = (int)std::min<int64_t>(16, std::max<int64_t>(1, ne / 4096));
+    std::vector<const char*> whys(T, nullptr);
+    parallel_run(T, [&](int t) {
+      for (int64_t e = ne * t / T; e < ne * (t + 1) / T; ++e) {
+        int b = P.el_sub[e];
+        int64_t nK = (int64_t)D.K.nt[b] * TS;
+        for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
+          if (P.el_local[j] < -1 || (int64_t)P.el_local[j] + P.ndof > nK) { whys[t] = "element map"; return; }
+        if (li > 0) {
+          const LevelPlan& PP = *lev[li - 1].P;
+          int64_t nloc = (int64_t)(P.el_local_ptr[e + 1] - P.el_local_ptr[e]) * P.ndof;
+          const SubPlan& S = PP.subs[e];
+          if (nloc != S.nc || lev[li - 1].kc_off[e] + nloc * nloc > (int64_t)lev[li - 1].kc_off.back() + (int64_t)PP.subs.back().nc * PP.subs.back().nc) {
+            whys[t] = "coarse element matrix";
+            return;
+          }
+        }
       }
-    }
+      for (int64_t b = ns * t / T; b < ns * (t + 1) / T; ++b) {
+        if ((int64_t)P.subs[b].dofI.size() != P.subs[b].nIp) { whys[t] = "interior map size"; return; }
+        for (int64_t d : P.subs[b].dofI)
+          if (d < -1 || d >= P.n_dofs) { whys[t] = "interior map"; return; }
+        for (int32_t g : P.subs[b].iface)
+          if (g < 0 || g >= (int64_t)P.iface_dofs.size()) { whys[t] = "interface map"; return; }
+      }
+    });
+    for (const char* w : whys)
+      if (w) return bad(L + w);
     if (!seg_ok(D.ksegs_h)) return bad(L + "diagonal segment");
-    for (size_t b = 0; b < P.subs.size(); ++b) {
-      if ((int64_t)P.subs[b].dofI.size() != P.subs[b].nIp) return bad(L + "interior map size");
-      for (int64_t d : P.subs[b].dofI)
-        if (d < -1 || d >= P.n_dofs) return bad(L + "interior map");
-      for (int32_t g : P.subs[b].iface)
-        if (g < 0 || g >= (int64_t)P.iface_dofs.size()) return bad(L + "interface map");
-    }
     for (int64_t d : P.iface_dofs)
       if (d < 0 || d >= P.n_dofs) return bad(L + "interface DOF");
     return MLBDDC_OK;
