@@ -208,7 +208,7 @@ typedef struct {
   int64_t tiles[MLBDDC_PROF_N];   /* tile tasks processed */
   double job_time_s[2];           /* wall time of the factorization jobs: [0] subdomain
                                      matrices (all levels), [1] constrained local problems */
-  int32_t panel[2];               /* panel widths used by the last set-up (K, M jobs) */
+  int32_t panel[2];               /* panel widths of the largest K and M jobs of the last set-up */
 } mlbddc_profile;
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable);
 mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out);

@@ -9,6 +9,7 @@
 #include <numeric>
 #include <thread>
 #include <mutex>
+#include <atomic>
 #include <condition_variable>
 #include <unistd.h>
 #include <chrono>
@@ -715,7 +716,18 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
     for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_mask[n] = 0; }
   }
   };
-  parallel_ranges(ns, work);
+  // subdomains handed out one at a time, largest first (the cost grows with
+  // the node count; interior subdomains are cut by the dissection)
+  {
+    std::vector<int32_t> order(ns);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t c) { return sub_nodes[a].size() > sub_nodes[c].size(); });
+    std::atomic<int32_t> next{0};
+    parallel_run(plan_threads(ns), [&](int t) {
+      for (int32_t i = next++; i < ns; i = next++) work(t, order[i], order[i] + 1);
+    });
+  }
   mark("local layouts (parallel)");
   for (int32_t b = 0; b < ns; ++b) {
     if (sub_fail[b] == 1)

@@ -208,6 +208,7 @@ struct Handle {
   // profiling
   bool prof = false;
   mlbddc_profile pdata{};
+  int panel_nt[2] = {0, 0};  // largest matrix (tiles per side) of each job kind in this set-up
   std::vector<hipEvent_t> events;
 
   mlbddc_status herr(const char* what, hipError_t e) {
@@ -612,7 +613,10 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
-  pdata.panel[job] = J.panel;
+  if (ntmax >= panel_nt[job]) {  // report the panel width of the largest job of the set-up
+    panel_nt[job] = ntmax;
+    pdata.panel[job] = J.panel;
+  }
   build_factor_schedule(J.items, J.panel, J.sched, lookahead);
   if ((st = upload(&J.d_off, J.off))) return st;
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
@@ -695,6 +699,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   HIPCHK(hipStreamSynchronize(stream));
   if (mlbddc_status sr = stage_reset()) return sr;
   free_all(true);
+  panel_nt[0] = panel_nt[1] = 0;
   const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
   double tm = now();
   auto mark = [&](const char* what) {
