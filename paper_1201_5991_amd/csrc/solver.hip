@@ -354,6 +354,7 @@ struct Handle {
   bool lookahead = false;
   std::vector<std::array<int, 4>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel)
   int pick_panel(int job, bool fp32, int ntmax) const;
+  mlbddc_status reserve_job(Job& J, bool fp32);
   mlbddc_status prepare_job(Job& J, bool fp32, int job = 0);
   mlbddc_status factor(Job& J, int level, bool precond);
   mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
@@ -583,7 +584,10 @@ int Handle::pick_panel(int job, bool fp32, int ntmax) const {
   return best > 0 ? best : 4;
 }
 
-mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
+// Matrix layout and storage of a job (J.nt and the items' e1, e2 set): the
+// matrices are zeroed on the upload stream right away, while the host keeps
+// preparing (the upload fence orders this before the assembly).
+mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
   J.fp32 = fp32;
   const size_t esz = fp32 ? 4 : 8;
   J.off.resize(J.nt.size());
@@ -594,7 +598,6 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
     tot += packed_tiles(J.nt[i]) * TE;
     J.inv_off[i] = itot;
     itot += (int64_t)(J.items[i].e1 + J.items[i].e2) * TE;
-    J.items[i].env = J.env[i].data();
   }
   J.elems = tot;
   J.inv_elems = itot;
@@ -606,10 +609,15 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   if (st) return st;
   J.buf = b;
   J.inv = iv;
-  // zero the matrices on the upload stream now, while the host keeps preparing
-  // (the upload fence orders it before the assembly)
   if ((st = ensure_ustream())) return st;
   HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
+  mlbddc_status st;
+  if (!J.buf && (st = reserve_job(J, fp32))) return st;
+  for (size_t i = 0; i < J.nt.size(); ++i) J.items[i].env = J.env[i].data();
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
@@ -792,6 +800,21 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
     if ((st = prepare_job(D.K, D.kfp32))) return st;
     flops_K += D.K.sched.flops;
+    // storage of the constrained problems now, so that zeroing it does not
+    // run beside the factorization of K
+    if (!P.top) {
+      D.M.nt.resize(ns);
+      D.M.items.resize(ns);
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        const int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
+        D.M.nt[b] = 2 * (tG + tC);
+        D.M.items[b].nt = D.M.nt[b];
+        D.M.items[b].e1 = tG;
+        D.M.items[b].e2 = tC;
+      }
+      if ((st = reserve_job(D.M, D.mfp32))) return st;
+    }
     mark("  K job layout + schedule");
 
     // diagonal segments of the K matrices: padding and identity block
