@@ -207,6 +207,7 @@ struct Handle {
   double flops_K = 0, flops_M = 0;
   // profiling
   bool prof = false;
+  bool verbose = false;  // MLBDDC_VERBOSE set: set-up phase times on stderr
   mlbddc_profile pdata{};
   int panel_nt[2] = {0, 0};  // largest matrix (tiles per side) of each job kind in this set-up
   std::vector<hipEvent_t> events;
@@ -616,7 +617,13 @@ mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
 
 mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   mlbddc_status st;
+  double tm = now();
+  auto mark = [&](const char* what) {
+    if (verbose) std::fprintf(stderr, "[mlbddc setup]     %-24s %8.2f ms\n", what, (now() - tm) * 1e3);
+    tm = now();
+  };
   if (!J.buf && (st = reserve_job(J, fp32))) return st;
+  mark("storage");
   for (size_t i = 0; i < J.nt.size(); ++i) J.items[i].env = J.env[i].data();
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
@@ -626,11 +633,13 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
     pdata.panel[job] = J.panel;
   }
   build_factor_schedule(J.items, J.panel, J.sched, lookahead);
+  mark("schedule");
   if ((st = upload(&J.d_off, J.off))) return st;
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
   if ((st = upload(&J.d_nt, J.nt))) return st;
   if ((st = upload(&J.d_tasks, J.sched.tasks))) return st;
   if ((st = dalloc(&J.d_err, 2))) return st;
+  mark("uploads");
   return MLBDDC_OK;
 }
 
@@ -708,12 +717,13 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if (mlbddc_status sr = stage_reset()) return sr;
   free_all(true);
   panel_nt[0] = panel_nt[1] = 0;
-  const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
-  double tm = now();
+  verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
+  double tm = t0;
   auto mark = [&](const char* what) {
     if (verbose) std::fprintf(stderr, "[mlbddc setup] %-28s %8.2f ms\n", what, (now() - tm) * 1e3);
     tm = now();
   };
+  mark("wait, release previous");
   // Queuing a factorization can block the host once the launch queue is
   // full, so each level's numeric work is queued by a worker thread while
   // this thread prepares the next part.  At most one part is being queued at
@@ -762,13 +772,6 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     if ((st = upload(&d_Kref, kref))) return st;
     std::vector<double> sc(mesh->elem_scale, mesh->elem_scale + n_elems);
     if ((st = upload(&d_scale, sc))) return st;
-    std::vector<int32_t> edof((size_t)n_elems * nloc1);
-    for (int64_t el = 0; el < n_elems; ++el)
-      for (int a = 0; a < in.nodes_per_elem; ++a) {
-        int64_t fnode = plan.node_to_free[mesh->elem_nodes[el * in.nodes_per_elem + a]];
-        for (int c = 0; c < nd; ++c) edof[el * nloc1 + a * nd + c] = fnode < 0 ? -1 : (int32_t)(fnode * nd + c);
-      }
-    if ((st = upload(&d_edof, edof))) return st;
   }
 
   for (int li = 0; li < nlev; ++li) {
@@ -1082,6 +1085,23 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     if ((st = upload_fence())) return st;
     enqueue_async(li, false);
   }
+
+  // element DOF map (only the element energies use it: built after the
+  // factorizations are queued, while the device works)
+  {
+    std::vector<int32_t> edof((size_t)n_elems * nloc1);
+    const int npe = in.nodes_per_elem;
+    const int T = (int)std::min<int64_t>(16, std::max<int64_t>(1, n_elems / 8192));
+    parallel_run(T, [&](int t) {
+      for (int64_t el = n_elems * t / T; el < n_elems * (t + 1) / T; ++el)
+        for (int a = 0; a < npe; ++a) {
+          int64_t fnode = plan.node_to_free[mesh->elem_nodes[el * npe + a]];
+          for (int c = 0; c < nd; ++c) edof[el * nloc1 + a * nd + c] = fnode < 0 ? -1 : (int32_t)(fnode * nd + c);
+        }
+    });
+    if ((st = upload(&d_edof, edof))) return st;
+  }
+  mark("element DOF map");
 
   // PCG vectors
   const int64_t nif = (int64_t)plan.levels[0].iface_dofs.size();
