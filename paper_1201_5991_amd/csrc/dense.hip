@@ -130,6 +130,13 @@ __global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ el
   }
 }
 
+__global__ void __launch_bounds__(256) k_zero_runs(const ZeroRun* __restrict__ runs, char* base) {
+  const ZeroRun z = runs[blockIdx.x];
+  uint4* p = reinterpret_cast<uint4*>(base + z.off);
+  const int64_t n = z.bytes / 16;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <typename T>
 __global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A) {
   const DiagSeg s = segs[blockIdx.y];
@@ -566,6 +573,11 @@ void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int3
   if (n <= 0) return;
   hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)n), dim3(256), 0, st, elems, el_local_ptr, el_local, nd, el_sub, sub_off,
                      sub_nt, Kref, scale, ekc_off, ekc, A);
+}
+
+void launch_zero_runs(hipStream_t st, const ZeroRun* runs, int64_t nrun, void* base) {
+  if (nrun <= 0) return;
+  hipLaunchKernelGGL(k_zero_runs, dim3((unsigned)nrun), dim3(256), 0, st, runs, (char*)base);
 }
 
 template <typename T>

@@ -21,6 +21,11 @@ void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int3
                      const int32_t* el_local, int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
                      const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A);
 
+// Zero byte ranges (offsets and lengths multiples of 16) of one buffer, one
+// workgroup per range.
+struct ZeroRun { int64_t off, bytes; };
+void launch_zero_runs(hipStream_t st, const ZeroRun* runs, int64_t nrun, void* base);
+
 // Set entries A[row0+i][col0+i] = val for every segment (tile-packed matrices).
 struct DiagSeg { int64_t off; int32_t nt; int32_t row0, col0, count; double val; };
 template <typename T>

@@ -106,6 +106,27 @@ WorkerPool* pool_for_this_process() {
 
 }  // namespace
 
+void read_before_write_tiles(const FactorItemDesc& it, const std::function<void(int, int, int)>& emit) {
+  const int nt = it.nt;
+  std::vector<char> rows;
+  for (int g = 0; g < it.ngroups; ++g) {
+    rows.assign(nt, 0);
+    for (int k = it.gtile[g]; k < it.gtile[g + 1]; ++k) {
+      rows[k] = 1;
+      for (int32_t q = it.sptr[k]; q < it.sptr[k + 1]; ++q) rows[it.srow[q]] = 1;
+    }
+    for (int k = it.gtile[g]; k < it.gtile[g + 1]; ++k)
+      for (int r = k; r < nt;) {
+        if (!rows[r]) { ++r; continue; }
+        int r1 = r;
+        while (r1 < nt && rows[r1]) ++r1;
+        emit(r, k, r1 - r);
+        r = r1;
+      }
+  }
+  for (int k = it.e1; k < nt; ++k) emit(k, k, nt - k);
+}
+
 void parallel_run(int T, const std::function<void(int)>& body) {
   T = std::max(1, std::min(T, (int)WorkerPool::MAXT));
   if (T == 1) { body(0); return; }

@@ -194,6 +194,16 @@ struct FactorSchedule {
 void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, FactorSchedule& out,
                            bool lookahead = false);
 
+// Tiles of a tile-structured matrix (it.sptr set) that the factorization,
+// the assembly and the solves read before writing, as runs of consecutive
+// rows r0 .. r0 + count - 1 of column k; no kernel reads any other tile.  The
+// update tasks of a panel read tile (r, kk) for every column kk of the panel
+// and every row r in the structure of one of them; panels lie within one
+// dissection group, so the tiles (r, k) with k in a group and r in the union
+// of the group's column structures and its own rows cover them; the trailing
+// (interface) block is dense.
+void read_before_write_tiles(const FactorItemDesc& it, const std::function<void(int r0, int k, int count)>& emit);
+
 // Runs body(t) for t = 0..T-1 concurrently and returns when every call has
 // returned; the caller runs t = 0, persistent worker threads the others (a
 // call made while another thread is inside parallel_run, or from inside a

@@ -611,7 +611,30 @@ mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
   J.buf = b;
   J.inv = iv;
   if ((st = ensure_ustream())) return st;
-  HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
+  bool structured = false;
+  for (const FactorItemDesc& it : J.items) structured = structured || it.sptr;
+  if (!structured) {
+    HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
+    return MLBDDC_OK;
+  }
+  // tile-structured matrices: only the tiles some kernel reads before writing
+  std::vector<ZeroRun> runs;
+  auto add = [&](int64_t off_elems, int64_t ntiles) {  // at most 8 tiles per workgroup
+    for (int64_t q = 0; q < ntiles; q += 8)
+      runs.push_back(ZeroRun{off_elems * (int64_t)esz + q * TE * (int64_t)esz, std::min<int64_t>(8, ntiles - q) * TE * (int64_t)esz});
+  };
+  for (size_t i = 0; i < J.nt.size(); ++i) {
+    const int nt = J.nt[i];
+    if (!J.items[i].sptr) {
+      add(J.off[i], packed_tiles(nt));
+      continue;
+    }
+    read_before_write_tiles(J.items[i], [&](int r0, int k, int count) { add(J.off[i] + tile_index(r0, k, nt) * TE, count); });
+  }
+  ZeroRun* d_runs = nullptr;
+  if ((st = upload(&d_runs, runs))) return st;
+  launch_zero_runs(ustream, d_runs, (int64_t)runs.size(), J.buf);
+  HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
 

@@ -4,7 +4,9 @@
 // matrix with the subdomain's element pattern; compares the eliminated
 // columns and the updated trailing block with a dense right-looking Cholesky
 // of the interior columns, and checks that no two tasks of one launch write
-// the same tile.
+// the same tile.  Tiles outside the set the library zeroes before the
+// assembly (read_before_write_tiles) start as NaN: a task that read one would
+// spread NaN into the compared tiles.
 //
 // usage: schedule_check <dir with meta.txt and *.bin> <subdomain> <panel>
 // prints one line; exit status 0 when the comparison passes.
@@ -117,10 +119,35 @@ int main(int argc, char** argv) {
     }
   }
 
+  // tiles the library zeroes before assembling (all of them without a tile structure)
+  std::vector<char> zset((size_t)nt * nt, 0);
+  if (!S.sptr.empty())
+    read_before_write_tiles(items[0], [&](int r0, int k, int count) {
+      for (int r = r0; r < r0 + count; ++r) zset[(size_t)k * nt + r] = 1;
+    });
+  else
+    for (int k = 0; k < nt; ++k)
+      for (int r = k; r < nt; ++r) zset[(size_t)k * nt + r] = 1;
+  auto tile_nonzero = [&](const std::vector<double>& M, int r, int k) {
+    for (int j = 0; j < TS; ++j)
+      for (int i = 0; i < TS; ++i)
+        if (M[(size_t)(k * TS + j) * N + r * TS + i] != 0.0) return true;
+    return false;
+  };
+  bool cover = true;  // every assembled or factor tile lies in the zeroed set
+  for (int k = 0; k < nt; ++k)
+    for (int r = k; r < nt; ++r)
+      if (!zset[(size_t)k * nt + r] && (tile_nonzero(A, r, k) || tile_nonzero(R, r, k))) cover = false;
+
   // the schedule's tasks on tiles of X (column-major N x N; tile (r, s) at
   // rows 64 r.., columns 64 s..), inverse diagonal tiles in W
   std::vector<double> X = A, W((size_t)tI * TE, 0.0), tmp(TE);
   auto el = [&](int r, int s, int i, int j) -> double& { return X[(size_t)(s * TS + j) * N + r * TS + i]; };
+  for (int k = 0; k < nt; ++k)
+    for (int r = k; r < nt; ++r)
+      if (!zset[(size_t)k * nt + r])
+        for (int j = 0; j < TS; ++j)
+          for (int i = 0; i < TS; ++i) el(r, k, i, j) = std::nan("");
   bool conflict = false;
   for (const FactorLaunch& F : fs.launches) {
     std::set<std::pair<int, int>> written;
@@ -168,15 +195,21 @@ int main(int argc, char** argv) {
     }
   }
   double md = 0.0, mr = 0.0;
+  bool finite = true;
   for (int j = 0; j < N; ++j)
     for (int i = j; i < N; ++i) {
+      if (!zset[(size_t)(j / TS) * nt + i / TS]) continue;
       const double a = X[(size_t)j * N + i], c = R[(size_t)j * N + i];
+      if (!std::isfinite(a)) finite = false;
       md = std::max(md, std::fabs(a - c));
       mr = std::max(mr, std::fabs(c));
     }
-  const bool ok = !conflict && md <= 1e-10 * mr;
-  std::printf("subdomain %d tiles %d interior %d groups %d launches %zu tasks %zu conflict %d max|diff| %.3e max|ref| %.3e %s\n",
-              want, nt, tI, S.gtile.empty() ? 1 : (int)S.gtile.size() - 1, fs.launches.size(), fs.tasks.size(),
-              (int)conflict, md, mr, ok ? "ok" : "FAIL");
+  const bool ok = !conflict && cover && finite && md <= 1e-10 * mr;
+  long nz = 0;
+  for (char z : zset) nz += z;
+  std::printf("subdomain %d tiles %d interior %d groups %d launches %zu tasks %zu zeroed tiles %ld of %d conflict %d "
+              "cover %d finite %d max|diff| %.3e max|ref| %.3e %s\n",
+              want, nt, tI, S.gtile.empty() ? 1 : (int)S.gtile.size() - 1, fs.launches.size(), fs.tasks.size(), nz,
+              nt * (nt + 1) / 2, (int)conflict, (int)cover, (int)finite, md, mr, ok ? "ok" : "FAIL");
   return ok ? 0 : 1;
 }
