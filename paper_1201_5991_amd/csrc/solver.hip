@@ -304,7 +304,7 @@ struct Handle {
       const size_t bytes = sizeof(T) * v.size();
       if ((st = stage(bytes, &h))) return st;
       // large arrays (task lists of several MB) are staged by several threads
-      const int nth = (int)std::min<size_t>(8, bytes >> 19);
+      const int nth = (int)std::min<size_t>(8, bytes >> 20);
       const char* src = reinterpret_cast<const char*>(v.data());
       if (nth > 1)
         parallel_run(nth, [&](int t) {
@@ -856,6 +856,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
     for (auto& s : D.ksegs_h) D.kseg_max = std::max(D.kseg_max, s.count);
     if ((st = upload(&D.d_ksegs, D.ksegs_h))) return st;
+    // the layout checks of what assembly, weights and the K job use run on
+    // another thread while this one builds the assembly and flat layouts
+    // (they read only the plan, the K job and the segments above)
+    std::future<mlbddc_status> checked = std::async(std::launch::async, [this, li] { return validate_level(li, 0); });
 
     // assembly data
     {
@@ -956,7 +960,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
 
     mark("  flat layouts + vectors");
     // the device assembles and factors this level's K job while the host goes on
-    if ((st = validate_level(li, 0))) return st;
+    if ((st = checked.get())) return st;
     mark("  validate (K job)");
     if ((st = join())) return st;
     if ((st = upload_fence())) return st;
