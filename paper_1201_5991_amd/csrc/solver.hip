@@ -619,18 +619,23 @@ mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
   }
   // tile-structured matrices: only the tiles some kernel reads before writing
   std::vector<ZeroRun> runs;
-  auto add = [&](int64_t off_elems, int64_t ntiles) {  // at most 8 tiles per workgroup
-    for (int64_t q = 0; q < ntiles; q += 8)
-      runs.push_back(ZeroRun{off_elems * (int64_t)esz + q * TE * (int64_t)esz, std::min<int64_t>(8, ntiles - q) * TE * (int64_t)esz});
-  };
-  for (size_t i = 0; i < J.nt.size(); ++i) {
-    const int nt = J.nt[i];
-    if (!J.items[i].sptr) {
-      add(J.off[i], packed_tiles(nt));
-      continue;
+  const int ni = (int)J.nt.size();
+  std::vector<std::vector<ZeroRun>> per(ni);  // per matrix, built on several threads
+  parallel_run(std::min(16, std::max(1, ni / 4)), [&](int t) {
+    const int T = std::min(16, std::max(1, ni / 4));
+    for (int i = ni * t / T; i < ni * (t + 1) / T; ++i) {
+      const int nt = J.nt[i];
+      auto add = [&](int64_t off_elems, int64_t ntiles) {  // at most 8 tiles per workgroup
+        for (int64_t q = 0; q < ntiles; q += 8)
+          per[i].push_back(ZeroRun{off_elems * (int64_t)esz + q * TE * (int64_t)esz,
+                                   std::min<int64_t>(8, ntiles - q) * TE * (int64_t)esz});
+      };
+      if (!J.items[i].sptr) add(J.off[i], packed_tiles(nt));
+      else
+        read_before_write_tiles(J.items[i], [&](int r0, int k, int count) { add(J.off[i] + tile_index(r0, k, nt) * TE, count); });
     }
-    read_before_write_tiles(J.items[i], [&](int r0, int k, int count) { add(J.off[i] + tile_index(r0, k, nt) * TE, count); });
-  }
+  });
+  for (auto& v : per) runs.insert(runs.end(), v.begin(), v.end());
   ZeroRun* d_runs = nullptr;
   if ((st = upload(&d_runs, runs))) return st;
   launch_zero_runs(ustream, d_runs, (int64_t)runs.size(), J.buf);
