@@ -132,6 +132,72 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int mode, const MvDesc* __res
   }
 }
 
+// Small products (the coarse levels): one workgroup per output tile walks
+// the tiles that feed it, plain ones in its tile row and, for symmetric
+// blocks, transposed ones in its tile column below the diagonal, and writes
+// the result directly (FP64 sums; no partial tiles, one launch instead of two).
+template <typename TA, typename TX, typename TY>
+__global__ void __launch_bounds__(256) k_mv_rows(int mode, const MvDesc* __restrict__ d, const TA* __restrict__ A,
+                                                 const TX* __restrict__ x, TY* y, double alpha, int accumulate) {
+  const MvDesc D = d[blockIdx.y];
+  const int o = blockIdx.x;
+  const int nout = mode == MV_T ? D.nc : D.nr;
+  if (o >= nout) return;
+  const int t = threadIdx.x, a0 = 4 * (t & 15), g = t >> 4;
+  __shared__ double red[16][TS];
+  __shared__ double vcol[TS];
+  double up[4] = {0.0, 0.0, 0.0, 0.0}, vp[4] = {0.0, 0.0, 0.0, 0.0};
+  // plain tile: up(rows a0..a0+3) += A(:, b) x[b]; transposed: vp(col b) += A(a0.., b) . x[a0..]
+  auto tile = [&](int R, int S, const TX* xv, bool transposed) {
+    if (D.env && S < D.env[R]) return;
+    const TA* a = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
+    double xa[4];
+    if (transposed)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xa[i] = (double)xv[a0 + i];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int b = g + 16 * m;
+      const TA* col = a + b * TS + a0;
+      if (transposed) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vp[m] += (double)col[i] * xa[i];
+      } else {
+        const double xb = (double)xv[b];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) up[i] += (double)col[i] * xb;
+      }
+    }
+  };
+  const TX* xb = x + D.x_off;
+  if (mode == MV_N) {
+    for (int j = 0; j < D.nc; ++j) tile(D.r0 + o, D.c0 + j, xb + (int64_t)j * TS, false);
+  } else if (mode == MV_T) {
+    for (int j = 0; j < D.nr; ++j) tile(D.r0 + j, D.c0 + o, xb + (int64_t)j * TS, true);
+  } else {
+    for (int j = 0; j <= o; ++j) tile(D.r0 + o, D.r0 + j, xb + (int64_t)j * TS, false);
+    for (int j = o + 1; j < D.nr; ++j) tile(D.r0 + j, D.r0 + o, xb + (int64_t)j * TS, true);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[g][a0 + i] = up[i];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+    for (int off = 8; off > 0; off >>= 1) vp[m] += __shfl_xor(vp[m], off, 16);
+  if ((t & 15) == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) vcol[g + 16 * m] = vp[m];
+  __syncthreads();
+  if (t < TS) {
+    double acc = vcol[t];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += red[q][t];
+    TY* yy = y + D.y_off + (int64_t)o * TS + t;
+    double v = alpha * acc;
+    if (accumulate) v += (double)*yy;
+    *yy = (TY)v;
+  }
+}
+
 // --------------------------------------------------------- gather / scatter
 template <typename TI, typename TO>
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ idx, const double* __restrict__ w, const TI* __restrict__ in,
@@ -490,6 +556,11 @@ template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles, const int64_t* tile_prefix,
                     const TA* A, const TX* x, TY* y, double alpha, bool accumulate, TA* partials, int32_t max_out_tiles) {
   if (nitems <= 0 || total_tiles <= 0) return;
+  if (total_tiles <= SMALL_MV_TILES) {  // coarse levels: one launch, no partial tiles
+    hipLaunchKernelGGL((k_mv_rows<TA, TX, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d, A,
+                       x, y, alpha, accumulate ? 1 : 0);
+    return;
+  }
   hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
                      partials);
   hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d,

@@ -79,6 +79,10 @@ struct MvDesc {
   int64_t p_off;                 // partial-sum scratch offset (nr*nc*64 entries)
   const int32_t* env;            // optional first nonzero tile column per row of A (global tile index) or null
 };
+// Products with at most SMALL_MV_TILES tiles in all run as one launch with a
+// workgroup per output tile; larger ones as a workgroup per tile plus a
+// reduction of the partial tiles.
+constexpr int64_t SMALL_MV_TILES = 64;
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles,
                     const int64_t* tile_prefix, const TA* A, const TX* x, TY* y, double alpha, bool accumulate,
