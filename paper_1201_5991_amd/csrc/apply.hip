@@ -223,6 +223,31 @@ __global__ void k_seg_reduce(int64_t n, const int64_t* __restrict__ ptr, const i
   }
 }
 
+// out[g] = base[bidx[g]] + sum_{j in ptr[g]..ptr[g+1]} in[list[j]]  (FP64)
+__global__ void k_gather_seg(int64_t n, const int32_t* __restrict__ bidx, const double* __restrict__ base,
+                             const int64_t* __restrict__ ptr, const int64_t* __restrict__ list, const double* __restrict__ in,
+                             double* __restrict__ out) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    double acc = base[bidx[g]];
+    for (int64_t j = ptr[g]; j < ptr[g + 1]; ++j) acc += in[list[j]];
+    out[g] = acc;
+  }
+}
+
+// out[i1[i]] = in1[i] (i1 >= 0) for i < n1, then out[i2[i]] = in2[i] for i < n2 (disjoint targets)
+template <typename TI>
+__global__ void k_scatter2(int64_t n1, const int32_t* __restrict__ i1, const TI* __restrict__ in1, int64_t n2,
+                           const int32_t* __restrict__ i2, const double* __restrict__ in2, double* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n1 + n2; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n1) {
+      const int32_t j = i1[i];
+      if (j >= 0) out[j] = (double)in1[i];
+    } else {
+      out[i2[i - n1]] = in2[i - n1];
+    }
+  }
+}
+
 template <typename TI, typename TO>
 __global__ void k_scatter(int64_t n, const int32_t* __restrict__ idx, const TI* __restrict__ in, TO* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -664,6 +689,19 @@ template void launch_seg_reduce<double>(hipStream_t, int64_t, const int64_t*, co
                                         double*, double);
 template void launch_seg_reduce<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
                                        double*, double);
+void launch_gather_seg(hipStream_t st, int64_t n, const int32_t* bidx, const double* base, const int64_t* ptr,
+                       const int64_t* list, const double* in, double* out) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_seg, dim3(grid_for(n)), dim3(256), 0, st, n, bidx, base, ptr, list, in, out);
+}
+template <typename TI>
+void launch_scatter2(hipStream_t st, int64_t n1, const int32_t* i1, const TI* in1, int64_t n2, const int32_t* i2,
+                     const double* in2, double* out) {
+  if (n1 + n2 > 0) hipLaunchKernelGGL(k_scatter2<TI>, dim3(grid_for(n1 + n2)), dim3(256), 0, st, n1, i1, in1, n2, i2, in2, out);
+}
+template void launch_scatter2<double>(hipStream_t, int64_t, const int32_t*, const double*, int64_t, const int32_t*,
+                                      const double*, double*);
+template void launch_scatter2<float>(hipStream_t, int64_t, const int32_t*, const float*, int64_t, const int32_t*,
+                                     const double*, double*);
 template void launch_scatter<double, double>(hipStream_t, int64_t, const int32_t*, const double*, double*);
 template void launch_scatter<float, float>(hipStream_t, int64_t, const int32_t*, const float*, float*);
 template void launch_scatter<double, float>(hipStream_t, int64_t, const int32_t*, const double*, float*);

@@ -95,6 +95,15 @@ void launch_gather(hipStream_t st, int64_t n, const int32_t* idx, const double* 
 template <typename TI>
 void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
                        double* out, double beta);
+// out[g] = base[bidx[g]] + sum_{j in ptr[g]..ptr[g+1]} in[list[j]]  (FP64): a gather and a
+// segmented sum in one launch.
+void launch_gather_seg(hipStream_t st, int64_t n, const int32_t* bidx, const double* base, const int64_t* ptr,
+                       const int64_t* list, const double* in, double* out);
+// out[i1[i]] = in1[i] (i1 >= 0), i < n1, and out[i2[i]] = in2[i], i < n2: two scatters to
+// disjoint targets in one launch.
+template <typename TI>
+void launch_scatter2(hipStream_t st, int64_t n1, const int32_t* i1, const TI* in1, int64_t n2, const int32_t* i2,
+                     const double* in2, double* out);
 // out[idx[i]] = in[i] for idx >= 0 (a permutation scatter)
 template <typename TI, typename TO>
 void launch_scatter(hipStream_t st, int64_t n, const int32_t* idx, const TI* in, TO* out);

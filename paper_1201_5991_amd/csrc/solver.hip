@@ -1525,20 +1525,18 @@ mlbddc_status Handle::apply_full(int li, const double* r, double* z) {
   const int64_t nif = (int64_t)P.iface_dofs.size();
   if (f32) run_mv<float, float, double>(D.mvPreT, D.K, (const float*)D.rI, D.tG, 1.0, false, D.partial);
   else run_mv<double, double, double>(D.mvPreT, D.K, (const double*)D.rI, D.tG, 1.0, false, D.partial);
-  launch_gather<double, double>(stream, nif, D.d_iface_dofs, nullptr, r, D.rhat);
-  launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.tG, D.rhat, 1.0);
+  launch_gather_seg(stream, nif, D.d_iface_dofs, r, D.d_gptr, D.d_glist, D.tG, D.rhat);
   if ((st = apply_interface(li, D.rhat, D.zhat))) return st;
   // z_I = u_I - K_II^{-1} K_IG z_G
   if (f32) {
     launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, nullptr, D.zhat, (float*)D.zG);
     run_mv<float, float, float>(D.mvPostN, D.K, (const float*)D.zG, (float*)D.uI, 1.0, true, D.partial);
-    launch_scatter<float, double>(stream, D.nI_flat, D.d_iidx, (const float*)D.uI, z);
+    launch_scatter2<float>(stream, D.nI_flat, D.d_iidx, (const float*)D.uI, nif, D.d_iface_dofs, D.zhat, z);
   } else {
     launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.zhat, (double*)D.zG);
     run_mv<double, double, double>(D.mvPostN, D.K, (const double*)D.zG, (double*)D.uI, 1.0, true, D.partial);
-    launch_scatter<double, double>(stream, D.nI_flat, D.d_iidx, (const double*)D.uI, z);
+    launch_scatter2<double>(stream, D.nI_flat, D.d_iidx, (const double*)D.uI, nif, D.d_iface_dofs, D.zhat, z);
   }
-  launch_scatter_idx(stream, nif, D.d_iface_dofs, D.zhat, z);
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
