@@ -171,7 +171,7 @@ void parallel_ranges(int64_t n, F&& work) {
 // Interior DOFs below which a subdomain keeps one group in node order, and
 // the largest part left undivided (in DOFs).
 constexpr int64_t ND_MIN_DOFS = 16 * TS;
-constexpr int64_t ND_LEAF_DOFS = 20 * TS;
+constexpr int64_t ND_LEAF_DOFS = 12 * TS;
 
 // Nested-dissection order of a subdomain's interior nodes 0..n-1 (adjacency
 // CSR ptr / adj).  The separators are level sets of breadth-first distances
