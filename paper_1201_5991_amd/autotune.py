@@ -18,7 +18,7 @@ import math
 import os
 import sys
 
-CANDIDATES = (1, 2, 4, 8)
+CANDIDATES = (1, 2, 3, 4, 6, 8)
 
 
 def _bucket(n: int) -> int:
