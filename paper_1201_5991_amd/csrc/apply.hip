@@ -490,36 +490,70 @@ __global__ void __launch_bounds__(256) k_dot_final(int nb, const double* __restr
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// The iteration counter lives on the device (so that an iteration can be
-// replayed from a captured graph): alpha_j goes to hist[2j]; beta_j, computed
-// at the start of iteration j+1, to hist[2j+1], after which the counter moves on.
-__global__ void k_pcg_alpha(double* s, double* hist, const int* it) {
-  if (s[S_DONE] != 0.0) return;
-  s[S_ALPHA] = s[S_RZ] / s[S_PQ];
-  if (hist) hist[2 * (*it)] = s[S_ALPHA];
-}
-__global__ void k_pcg_check(double* s, double rtol2) {
-  const double pq = s[S_PQ];
-  const bool stop = !(pq > 0.0) || !(pq < INFINITY) || s[S_RR] < rtol2 * s[S_GG];
-  if (s[S_DONE] != 0.0 || stop) s[S_DONE] = 1.0;
-}
-__global__ void k_pcg_beta(double* s, double* hist, int* it) {
-  if (s[S_DONE] != 0.0) return;
-  s[S_BETA] = s[S_RZNEW] / s[S_RZ];
-  s[S_RZ] = s[S_RZNEW];
-  if (hist) hist[2 * (*it) + 1] = s[S_BETA];
-  *it += 1;
-}
 __global__ void k_set_int(int* p, int v) { *p = v; }
-__global__ void k_pcg_update_xr(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                                const double* __restrict__ q, const double* __restrict__ s) {
+
+// Sum of the block partials (fixed order) and the scalar step after it.  The
+// iteration counter lives on the device (so that an iteration can be
+// replayed from a captured graph): alpha_j goes to hist[2j], beta_j to
+// hist[2j+1], after which the counter moves on.
+__global__ void __launch_bounds__(256) k_dot_step(int nb, const double* __restrict__ partial, double* s, int slot, int step,
+                                                  double* hist, int* it, double rtol2) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += partial[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double tot = red[0];
+  s[slot] = tot;
+  if (step == DOT_CHECK) {
+    const double pq = s[S_PQ];
+    const bool stop = !(pq > 0.0) || !(pq < INFINITY) || tot < rtol2 * s[S_GG];
+    if (s[S_DONE] != 0.0 || stop) s[S_DONE] = 1.0;
+    return;
+  }
   if (s[S_DONE] != 0.0) return;
-  const double a = s[S_ALPHA];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += a * p[i];
-    r[i] -= a * q[i];
+  if (step == DOT_ALPHA) {
+    s[S_ALPHA] = s[S_RZ] / tot;
+    if (hist) hist[2 * (*it)] = s[S_ALPHA];
+  } else if (step == DOT_BETA) {
+    s[S_BETA] = tot / s[S_RZ];
+    s[S_RZ] = tot;
+    if (hist) hist[2 * (*it) + 1] = s[S_BETA];
+    *it += 1;
   }
 }
+
+// x += alpha p, r -= alpha q (unless done), and per-block partial sums of r.r.
+__global__ void __launch_bounds__(256) k_pcg_update_xr_partial(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                               const double* __restrict__ p, const double* __restrict__ q,
+                                                               const double* __restrict__ s, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const bool done = s[S_DONE] != 0.0;
+  const double a = s[S_ALPHA];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double ri = r[i];
+    if (!done) {
+      x[i] += a * p[i];
+      ri -= a * q[i];
+      r[i] = ri;
+    }
+    v += ri * ri;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 __global__ void k_pcg_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ s) {
   if (s[S_DONE] != 0.0) return;
   const double b = s[S_BETA];
@@ -632,17 +666,24 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, nblocks, partial, out);
 }
 
-void launch_pcg_alpha(hipStream_t st, double* s, double* hist, const int* it) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, st, s, hist, it);
+static unsigned dot_blocks(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(DOT_BLOCKS, (n + 255) / 256));
 }
-void launch_pcg_check(hipStream_t st, double* s, double rtol2) { hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1), 0, st, s, rtol2); }
-void launch_pcg_beta(hipStream_t st, double* s, double* hist, int* it) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, st, s, hist, it);
+void launch_dot_step(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* s, int slot,
+                     int step, double* hist, int* it, double rtol2) {
+  const unsigned nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_dot_step, dim3(1), dim3(256), 0, st, (int)nb, partial, s, slot, step, hist, it, rtol2);
 }
+void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
+                                double* partial, double* s, double rtol2) {
+  const unsigned nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_pcg_update_xr_partial, dim3(nb), dim3(256), 0, st, n, x, r, p, q, s, partial);
+  hipLaunchKernelGGL(k_dot_step, dim3(1), dim3(256), 0, st, (int)nb, partial, s, (int)S_RR, (int)DOT_CHECK, nullptr, nullptr,
+                     rtol2);
+}
+
 void launch_set_int(hipStream_t st, int* p, int v) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v); }
-void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q, const double* s) {
-  hipLaunchKernelGGL(k_pcg_update_xr, dim3(grid_for(n)), dim3(256), 0, st, n, x, r, p, q, s);
-}
 void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s) {
   hipLaunchKernelGGL(k_pcg_update_p, dim3(grid_for(n)), dim3(256), 0, st, n, p, z, s);
 }

@@ -139,14 +139,19 @@ constexpr int DOT_BLOCKS = 1024;
 // S_DONE: set (sticky) once the iteration converged or broke down; the
 // PCG update kernels then leave x, r, p and the history untouched.
 enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_DONE = 7, S_NSCAL = 8 };
-void launch_pcg_alpha(hipStream_t st, double* s, double* hist, const int* it);  // alpha = rz / pq
-void launch_pcg_update_xr(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
-                          const double* s);                                    // x += a p, r -= a q
-void launch_pcg_beta(hipStream_t st, double* s, double* hist, int* it);         // beta = rznew / rz, rz = rznew, ++it
 void launch_set_int(hipStream_t st, int* p, int v);
-// s[S_DONE] = 1 if p^T S p <= 0 or not finite, or r^T r < rtol2 * g^T g (stays 1 once set).
-void launch_pcg_check(hipStream_t st, double* s, double rtol2);
 void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s);  // p = z + beta p
+// A dot product whose single-block finish also does the scalar step that
+// follows it: DOT_ALPHA alpha = rz / pq (slot S_PQ); DOT_CHECK the stopping
+// test, s[S_DONE] = 1 (sticky) when p.q <= 0 or not finite or r.r < rtol2 g.g
+// (slot S_RR); DOT_BETA beta = rznew / rz, rz = rznew, ++it (slot S_RZNEW).
+enum DotStep { DOT_ALPHA = 1, DOT_CHECK = 2, DOT_BETA = 3 };
+void launch_dot_step(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* s, int slot,
+                     int step, double* hist, int* it, double rtol2);
+// x += alpha p, r -= alpha q (unless done) and the partial sums of r.r in one
+// launch, then the finish of r.r with the stopping test.
+void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
+                                double* partial, double* s, double rtol2);
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
 
 // Element energies out_e = E_e a_e^T K0 b_e (level-1 mesh).

@@ -1616,25 +1616,21 @@ static void lanczos(const std::vector<double>& al, const std::vector<double>& be
 }
 
 // One PCG iteration after the first (first == false) or the first one:
-//   [beta = rz_new / rz, p = z + beta p]   (not in the first iteration)
-//   q = S^ p;  alpha = rz / (p.q);  x += alpha p;  r -= alpha q;  rr = r.r
-//   z = M r;  rz_new = r.z
-// The host checks rr (and p.q) after the iteration.
+//   [p = z + beta p]   (not in the first iteration)
+//   q = S^ p;  p.q and alpha = rz / p.q
+//   x += alpha p;  r -= alpha q with r.r, then the stopping test
+//   z = M r;  rz_new = r.z, then beta = rz_new / rz for the next iteration
+// Each dot product ends in one single-block launch that also does the scalar
+// step after it.  The host reads rr (and p.q) after the iteration.
 mlbddc_status Handle::pcg_body(bool first) {
   mlbddc_status st;
   const int64_t n = (int64_t)lev[0].P->iface_dofs.size();
-  if (!first) {
-    launch_pcg_beta(stream, d_s, d_hist, d_it);
-    launch_pcg_update_p(stream, n, d_p, d_z, d_s);
-  }
+  if (!first) launch_pcg_update_p(stream, n, d_p, d_z, d_s);
   if ((st = schur(d_p, d_q))) return st;
-  launch_dot(stream, n, d_p, d_q, d_dotp, DOT_BLOCKS, d_s + S_PQ);
-  launch_pcg_alpha(stream, d_s, d_hist, d_it);
-  launch_pcg_update_xr(stream, n, d_x, d_r, d_p, d_q, d_s);
-  launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
-  launch_pcg_check(stream, d_s, opt.rtol * opt.rtol);
+  launch_dot_step(stream, n, d_p, d_q, d_dotp, d_s, S_PQ, DOT_ALPHA, d_hist, d_it, 0.0);
+  launch_pcg_update_xr_check(stream, n, d_x, d_r, d_p, d_q, d_dotp, d_s, opt.rtol * opt.rtol);
   if ((st = apply_interface(0, d_r, d_z))) return st;
-  launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZNEW);
+  launch_dot_step(stream, n, d_r, d_z, d_dotp, d_s, S_RZNEW, DOT_BETA, d_hist, d_it, 0.0);
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
