@@ -528,6 +528,33 @@ __global__ void __launch_bounds__(256) k_dot_step(int nb, const double* __restri
   }
 }
 
+// out[g] = sum_{j in ptr[g]..ptr[g+1]} (w ? w[list[j]] : 1) in[list[j]], and
+// per-block partial sums of out[g] dotv[g].
+template <typename TI>
+__global__ void __launch_bounds__(256) k_seg_reduce_dot(int64_t n, const int64_t* __restrict__ ptr,
+                                                        const int64_t* __restrict__ list, const double* __restrict__ w,
+                                                        const TI* __restrict__ in, double* __restrict__ out,
+                                                        const double* __restrict__ dotv, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int64_t j = ptr[g]; j < ptr[g + 1]; ++j) {
+      const int64_t q = list[j];
+      acc += (w ? w[q] : 1.0) * (double)in[q];
+    }
+    out[g] = acc;
+    v += acc * dotv[g];
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // x += alpha p, r -= alpha q (unless done), and per-block partial sums of r.r.
 __global__ void __launch_bounds__(256) k_pcg_update_xr_partial(int64_t n, double* __restrict__ x, double* __restrict__ r,
                                                                const double* __restrict__ p, const double* __restrict__ q,
@@ -669,12 +696,19 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
 static unsigned dot_blocks(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(DOT_BLOCKS, (n + 255) / 256));
 }
-void launch_dot_step(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* s, int slot,
-                     int step, double* hist, int* it, double rtol2) {
+template <typename TI>
+void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
+                           double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,
+                           int* it, double rtol2) {
   const unsigned nb = dot_blocks(n);
-  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_seg_reduce_dot<TI>, dim3(nb), dim3(256), 0, st, n, ptr, list, w, in, out, dotv, partial);
   hipLaunchKernelGGL(k_dot_step, dim3(1), dim3(256), 0, st, (int)nb, partial, s, slot, step, hist, it, rtol2);
 }
+template void launch_seg_reduce_dot<double>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const double*,
+                                            double*, const double*, double*, double*, int, int, double*, int*, double);
+template void launch_seg_reduce_dot<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
+                                           double*, const double*, double*, double*, int, int, double*, int*, double);
+
 void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
                                 double* partial, double* s, double rtol2) {
   const unsigned nb = dot_blocks(n);

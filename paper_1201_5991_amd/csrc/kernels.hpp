@@ -141,13 +141,17 @@ constexpr int DOT_BLOCKS = 1024;
 enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_DONE = 7, S_NSCAL = 8 };
 void launch_set_int(hipStream_t st, int* p, int v);
 void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s);  // p = z + beta p
-// A dot product whose single-block finish also does the scalar step that
-// follows it: DOT_ALPHA alpha = rz / pq (slot S_PQ); DOT_CHECK the stopping
+// Steps that the single-block finish of a PCG dot product does after it:
+// DOT_ALPHA alpha = rz / pq (slot S_PQ); DOT_CHECK the stopping
 // test, s[S_DONE] = 1 (sticky) when p.q <= 0 or not finite or r.r < rtol2 g.g
 // (slot S_RR); DOT_BETA beta = rznew / rz, rz = rznew, ++it (slot S_RZNEW).
 enum DotStep { DOT_ALPHA = 1, DOT_CHECK = 2, DOT_BETA = 3 };
-void launch_dot_step(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, double* s, int slot,
-                     int step, double* hist, int* it, double rtol2);
+// A segmented sum (as launch_seg_reduce with beta 0) whose blocks also form
+// the partial sums of out.dotv, then the dot product's finish and step.
+template <typename TI>
+void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
+                           double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,
+                           int* it, double rtol2);
 // x += alpha p, r -= alpha q (unless done) and the partial sums of r.r in one
 // launch, then the finish of r.r with the stopping test.
 void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,

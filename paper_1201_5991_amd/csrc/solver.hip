@@ -363,9 +363,14 @@ struct Handle {
   void run_trsv(LevelDev& D, bool transposed);
   template <typename TA, typename TX, typename TY>
   void run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial);
-  mlbddc_status apply_interface(int li, const double* rhat, double* zhat);
+  // A PCG dot product finished by the last kernel of a product (see DotFinish).
+  struct DotFinish {
+    int slot, step;
+    double rtol2;
+  };
+  mlbddc_status apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds = nullptr);
   mlbddc_status apply_full(int li, const double* r, double* z);
-  mlbddc_status schur(const double* x, double* y);
+  mlbddc_status schur(const double* x, double* y, const DotFinish* ds = nullptr);
   mlbddc_status condense(const double* f, double* g);
   mlbddc_status recover(const double* uhat, double* u);
   mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
@@ -1470,7 +1475,7 @@ mlbddc_status Handle::numeric() {
 }
 
 // --------------------------------------------------------------------- apply
-mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat) {
+mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds) {
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   mlbddc_status st;
@@ -1488,13 +1493,21 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat) 
     launch_gather<double, float>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (float*)D.zcl);
     run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial);
     run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
-    launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0);
+    if (ds)  // with rhat.zhat and its scalar step
+      launch_seg_reduce_dot<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat,
+                                   rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2);
+    else
+      launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0);
   } else {
     launch_gather<double, double>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (double*)D.zcl);
     run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial);
     run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
-    launch_seg_reduce<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl, zhat,
-                              0.0);
+    if (ds)
+      launch_seg_reduce_dot<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl,
+                                    zhat, rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2);
+    else
+      launch_seg_reduce<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl, zhat,
+                                0.0);
   }
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
@@ -1541,11 +1554,16 @@ mlbddc_status Handle::apply_full(int li, const double* r, double* z) {
   return MLBDDC_OK;
 }
 
-mlbddc_status Handle::schur(const double* x, double* y) {
+mlbddc_status Handle::schur(const double* x, double* y, const DotFinish* ds) {
   LevelDev& D = lev[0];
   launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, x, D.gd);
   run_mv<double, double, double>(D.mvS, D.K, D.gd, D.gd2, 1.0, false, D.partial);
-  launch_seg_reduce<double>(stream, (int64_t)D.P->iface_dofs.size(), D.d_gptr, D.d_glist, nullptr, D.gd2, y, 0.0);
+  const int64_t nif = (int64_t)D.P->iface_dofs.size();
+  if (ds)  // with x.y and its scalar step
+    launch_seg_reduce_dot<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd2, y, x, d_dotp, d_s, ds->slot, ds->step,
+                                  d_hist, d_it, ds->rtol2);
+  else
+    launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd2, y, 0.0);
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
@@ -1621,16 +1639,16 @@ static void lanczos(const std::vector<double>& al, const std::vector<double>& be
 //   x += alpha p;  r -= alpha q with r.r, then the stopping test
 //   z = M r;  rz_new = r.z, then beta = rz_new / rz for the next iteration
 // Each dot product ends in one single-block launch that also does the scalar
-// step after it.  The host reads rr (and p.q) after the iteration.
+// step after it; p.q and r.z take their partial sums in the segmented sums
+// that finish q and z.  The host reads rr (and p.q) after the iteration.
 mlbddc_status Handle::pcg_body(bool first) {
   mlbddc_status st;
   const int64_t n = (int64_t)lev[0].P->iface_dofs.size();
   if (!first) launch_pcg_update_p(stream, n, d_p, d_z, d_s);
-  if ((st = schur(d_p, d_q))) return st;
-  launch_dot_step(stream, n, d_p, d_q, d_dotp, d_s, S_PQ, DOT_ALPHA, d_hist, d_it, 0.0);
+  const DotFinish pq{S_PQ, DOT_ALPHA, 0.0}, rz{S_RZNEW, DOT_BETA, 0.0};
+  if ((st = schur(d_p, d_q, &pq))) return st;
   launch_pcg_update_xr_check(stream, n, d_x, d_r, d_p, d_q, d_dotp, d_s, opt.rtol * opt.rtol);
-  if ((st = apply_interface(0, d_r, d_z))) return st;
-  launch_dot_step(stream, n, d_r, d_z, d_dotp, d_s, S_RZNEW, DOT_BETA, d_hist, d_it, 0.0);
+  if ((st = apply_interface(0, d_r, d_z, &rz))) return st;
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
