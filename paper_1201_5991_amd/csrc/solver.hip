@@ -363,7 +363,8 @@ struct Handle {
   void run_trsv(LevelDev& D, bool transposed);
   template <typename TA, typename TX, typename TY>
   void run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial);
-  // A PCG dot product finished by the last kernel of a product (see DotFinish).
+  // A PCG dot product formed by the last kernel of a product: its scalar slot,
+  // the step after it (DotStep) and the squared tolerance of the stopping test.
   struct DotFinish {
     int slot, step;
     double rtol2;
