@@ -193,6 +193,8 @@ struct Handle {
   double* d_hist = nullptr;        // alpha/beta history
   double* d_dotp = nullptr;
   double* h_s = nullptr;           // pinned mirror of the scalars, then two per-iteration snapshots
+  int32_t* h_err = nullptr;        // pinned error words of the factorization jobs
+  size_t h_err_cap = 0;
   hipEvent_t ev_snap[2] = {nullptr, nullptr};
   int32_t* d_it = nullptr;         // device iteration counter
   // HIP graph of one PCG iteration (captured on an internal stream)
@@ -1444,13 +1446,25 @@ mlbddc_status Handle::enqueue_rest(int li, bool zero) {
 // Wait for the queued numeric set-up and report the first factorization
 // that met a non-positive pivot (levels in order, K job before M job).
 mlbddc_status Handle::finish_numeric() {
-  HIPCHK(hipStreamSynchronize(stream));
+  // every job's error words copied behind the last job, then one wait
+  const size_t nw = 4 * lev.size();
+  if (h_err_cap < nw) {
+    if (h_err) (void)hipHostFree(h_err);
+    h_err = nullptr;
+    HIPCHK(hipHostMalloc((void**)&h_err, sizeof(int32_t) * nw, hipHostMallocDefault));
+    h_err_cap = nw;
+  }
   for (size_t li = 0; li < lev.size(); ++li)
     for (int j = 0; j < 2; ++j) {
       const Job& J = j == 0 ? lev[li].K : lev[li].M;
-      if (!J.d_err) continue;
-      int32_t e[2] = {0, 0};
-      HIPCHK(hipMemcpy(e, J.d_err, sizeof(e), hipMemcpyDeviceToHost));
+      int32_t* e = h_err + 4 * li + 2 * j;
+      e[0] = e[1] = 0;
+      if (J.d_err) HIPCHK(hipMemcpyAsync(e, J.d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    }
+  HIPCHK(hipStreamSynchronize(stream));
+  for (size_t li = 0; li < lev.size(); ++li)
+    for (int j = 0; j < 2; ++j) {
+      const int32_t* e = h_err + 4 * li + 2 * j;
       if (e[0] != 0) {
         const int level = lev[li].P->level, sub = e[0] - 1;
         if (j == 1) return fail(MLBDDC_E_SINGULAR_CONSTRAINTS, "constrained local problem is singular", level, sub, e[1]);
@@ -2002,6 +2016,7 @@ mlbddc_status mlbddc_destroy(mlbddc_t h) {
     (void)hipStreamDestroy(h->h.ustream);
   }
   if (h->h.h_s) (void)hipHostFree(h->h.h_s);
+  if (h->h.h_err) (void)hipHostFree(h->h.h_err);
   for (hipEvent_t e : h->h.ev_snap)
     if (e) (void)hipEventDestroy(e);
   for (auto& c : h->h.staging) (void)hipHostFree(c.first);
