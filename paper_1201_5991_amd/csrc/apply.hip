@@ -688,14 +688,16 @@ void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nit
                      crow, v);
 }
 
-void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(nblocks), dim3(256), 0, st, n, a, b, partial);
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, nblocks, partial, out);
-}
-
 static unsigned dot_blocks(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(DOT_BLOCKS, (n + 255) / 256));
 }
+
+void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out) {
+  const unsigned nb = std::min<unsigned>((unsigned)std::max(nblocks, 1), dot_blocks(n));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, st, n, a, b, partial);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (int)nb, partial, out);
+}
+
 template <typename TI>
 void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
                            double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,

@@ -133,7 +133,7 @@ void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nit
 // ------------------------------------------------------------------- PCG
 // Deterministic dot product: partial sums per block then a single-block finish.
 void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, double* partial, int32_t nblocks, double* out);
-constexpr int DOT_BLOCKS = 1024;
+constexpr int DOT_BLOCKS = 4096;  // at most one partial per 256 entries, as many blocks as the other vector kernels
 
 // Scalars used by the PCG kernels (device array).
 // S_DONE: set (sticky) once the iteration converged or broke down; the
