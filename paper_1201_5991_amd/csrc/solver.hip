@@ -1722,9 +1722,9 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
     launch_fill(stream, 1, 0.0, d_s + S_DONE);
     for (hipEvent_t& e : ev_snap)
       if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    // Iteration k+1 is queued before the host reads iteration k's scalars
-    // (snapshot k&1), so the device never waits for the host; once the
-    // device flags convergence or breakdown the queued iteration changes
+    // Iteration k+1 is normally queued before the host reads iteration k's
+    // scalars (snapshot k&1), so the device does not wait for the host; once
+    // the device flags convergence or breakdown a queued iteration changes
     // nothing (its products recompute the same scalars).
     auto issue = [&](int k) -> mlbddc_status {
       mlbddc_status sb;
@@ -1752,18 +1752,38 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
       return MLBDDC_OK;
     };
     if ((st = issue(0))) return st;
+    int issued = 1;
+    std::vector<double> rels;  // relative residuals read so far
     while (true) {
-      if (it + 1 < opt.max_iter && (st = issue(it + 1))) return st;
+      // Queue the next iteration before reading the one in flight, unless the
+      // residual trend (geometric, over the last three iterations) says that
+      // the one in flight probably meets the tolerance: a queued iteration
+      // would then be wasted work, and waiting for the host costs less.
+      bool ahead = issued == it + 1 && issued < opt.max_iter;
+      const size_t m = rels.size();
+      if (ahead && m >= 2) {
+        const double ratio = m >= 4 ? std::cbrt(rels[m - 1] / rels[m - 4]) : rels[m - 1] / rels[m - 2];
+        if (rels[m - 1] * ratio < opt.rtol) ahead = false;
+      }
+      if (ahead) {
+        if ((st = issue(issued))) return st;
+        ++issued;
+      }
       HIPCHK(hipEventSynchronize(ev_snap[it & 1]));
       const double* hs = h_s + S_NSCAL * (1 + (it & 1));
       ++it;
       rel = std::sqrt(hs[S_RR]) / gnorm;
+      rels.push_back(rel);
       if (hs[S_DONE] != 0.0) {
         if (!(hs[S_PQ] > 0.0) || !std::isfinite(hs[S_PQ])) breakdown = true;
         else conv = true;
         break;
       }
       if (it >= opt.max_iter) break;
+      if (issued == it) {  // held back and not converged: queue the next one now
+        if ((st = issue(issued))) return st;
+        ++issued;
+      }
     }
   }
   if ((st = recover(d_x, u))) return st;
