@@ -138,7 +138,8 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int mode, const MvDesc* __res
 // the result directly (FP64 sums; no partial tiles, one launch instead of two).
 template <typename TA, typename TX, typename TY>
 __global__ void __launch_bounds__(256) k_mv_rows(int mode, const MvDesc* __restrict__ d, const TA* __restrict__ A,
-                                                 const TX* __restrict__ x, TY* y, double alpha, int accumulate) {
+                                                 const TX* __restrict__ x, TY* y, double alpha, int accumulate, int mode2,
+                                                 const MvDesc* __restrict__ d2, const TX* __restrict__ x2) {
   const MvDesc D = d[blockIdx.y];
   const int o = blockIdx.x;
   const int nout = mode == MV_T ? D.nc : D.nr;
@@ -148,9 +149,9 @@ __global__ void __launch_bounds__(256) k_mv_rows(int mode, const MvDesc* __restr
   __shared__ double vcol[TS];
   double up[4] = {0.0, 0.0, 0.0, 0.0}, vp[4] = {0.0, 0.0, 0.0, 0.0};
   // plain tile: up(rows a0..a0+3) += A(:, b) x[b]; transposed: vp(col b) += A(a0.., b) . x[a0..]
-  auto tile = [&](int R, int S, const TX* xv, bool transposed) {
-    if (D.env && S < D.env[R]) return;
-    const TA* a = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
+  auto tile = [&](const MvDesc& DD, int R, int S, const TX* xv, bool transposed) {
+    if (DD.env && S < DD.env[R]) return;
+    const TA* a = A + DD.a_off + tile_index(R, S, DD.a_nt) * TE;
     double xa[4];
     if (transposed)
 #pragma unroll
@@ -169,15 +170,19 @@ __global__ void __launch_bounds__(256) k_mv_rows(int mode, const MvDesc* __restr
       }
     }
   };
-  const TX* xb = x + D.x_off;
-  if (mode == MV_N) {
-    for (int j = 0; j < D.nc; ++j) tile(D.r0 + o, D.c0 + j, xb + (int64_t)j * TS, false);
-  } else if (mode == MV_T) {
-    for (int j = 0; j < D.nr; ++j) tile(D.r0 + j, D.c0 + o, xb + (int64_t)j * TS, true);
-  } else {
-    for (int j = 0; j <= o; ++j) tile(D.r0 + o, D.r0 + j, xb + (int64_t)j * TS, false);
-    for (int j = o + 1; j < D.nr; ++j) tile(D.r0 + j, D.r0 + o, xb + (int64_t)j * TS, true);
-  }
+  auto walk = [&](const MvDesc& DD, int md, const TX* xx) {
+    const TX* xb = xx + DD.x_off;
+    if (md == MV_N) {
+      for (int j = 0; j < DD.nc; ++j) tile(DD, DD.r0 + o, DD.c0 + j, xb + (int64_t)j * TS, false);
+    } else if (md == MV_T) {
+      for (int j = 0; j < DD.nr; ++j) tile(DD, DD.r0 + j, DD.c0 + o, xb + (int64_t)j * TS, true);
+    } else {
+      for (int j = 0; j <= o; ++j) tile(DD, DD.r0 + o, DD.r0 + j, xb + (int64_t)j * TS, false);
+      for (int j = o + 1; j < DD.nr; ++j) tile(DD, DD.r0 + j, DD.r0 + o, xb + (int64_t)j * TS, true);
+    }
+  };
+  walk(D, mode, x);
+  if (d2) walk(d2[blockIdx.y], mode2, x2);  // a second product into the same output tiles
 #pragma unroll
   for (int i = 0; i < 4; ++i) red[g][a0 + i] = up[i];
 #pragma unroll
@@ -556,9 +561,12 @@ __global__ void __launch_bounds__(256) k_seg_reduce_dot(int64_t n, const int64_t
 }
 
 // x += alpha p, r -= alpha q (unless done), and per-block partial sums of r.r.
+template <typename TC>
 __global__ void __launch_bounds__(256) k_pcg_update_xr_partial(int64_t n, double* __restrict__ x, double* __restrict__ r,
                                                                const double* __restrict__ p, const double* __restrict__ q,
-                                                               const double* __restrict__ s, double* __restrict__ partial) {
+                                                               const double* __restrict__ s, double* __restrict__ partial,
+                                                               const int64_t* __restrict__ ptr, const int64_t* __restrict__ list,
+                                                               const double* __restrict__ w, TC* __restrict__ copies) {
   __shared__ double red[256];
   const bool done = s[S_DONE] != 0.0;
   const double a = s[S_ALPHA];
@@ -571,6 +579,11 @@ __global__ void __launch_bounds__(256) k_pcg_update_xr_partial(int64_t n, double
       r[i] = ri;
     }
     v += ri * ri;
+    if (copies)  // weighted subdomain copies of the new residual
+      for (int64_t j = ptr[i]; j < ptr[i + 1]; ++j) {
+        const int64_t c = list[j];
+        copies[c] = (TC)(w[c] * ri);
+      }
   }
   red[threadIdx.x] = v;
   __syncthreads();
@@ -581,11 +594,22 @@ __global__ void __launch_bounds__(256) k_pcg_update_xr_partial(int64_t n, double
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void k_pcg_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ s) {
-  if (s[S_DONE] != 0.0) return;
+// p = z + beta p (unless done); with copies, also copies[list[j]] = p[g] for
+// j in ptr[g]..ptr[g+1] (the subdomain copies of every interface entry).
+__global__ void k_pcg_update_p(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ s,
+                               const int64_t* __restrict__ ptr, const int64_t* __restrict__ list, double* __restrict__ copies) {
+  const bool done = s[S_DONE] != 0.0;
+  if (done && !copies) return;
   const double b = s[S_BETA];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = z[i] + b * p[i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = p[i];
+    if (!done) {
+      v = z[i] + b * v;
+      p[i] = v;
+    }
+    if (copies)
+      for (int64_t j = ptr[i]; j < ptr[i + 1]; ++j) copies[list[j]] = v;
+  }
 }
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -644,13 +668,21 @@ void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, i
   if (nitems <= 0 || total_tiles <= 0) return;
   if (total_tiles <= SMALL_MV_TILES) {  // coarse levels: one launch, no partial tiles
     hipLaunchKernelGGL((k_mv_rows<TA, TX, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d, A,
-                       x, y, alpha, accumulate ? 1 : 0);
+                       x, y, alpha, accumulate ? 1 : 0, 0, (const MvDesc*)nullptr, (const TX*)nullptr);
     return;
   }
   hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
                      partials);
   hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d,
                      partials, y, alpha, accumulate ? 1 : 0);
+}
+
+template <typename TA, typename TX, typename TY>
+void launch_tile_mv_sum(hipStream_t st, int mode, const MvDesc* d, int mode2, const MvDesc* d2, int32_t nitems,
+                        int32_t max_out_tiles, const TA* A, const TX* x, const TX* x2, TY* y, double alpha, bool accumulate) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL((k_mv_rows<TA, TX, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d, A, x,
+                     y, alpha, accumulate ? 1 : 0, mode2, d2, x2);
 }
 
 template <typename TI, typename TO>
@@ -711,17 +743,25 @@ template void launch_seg_reduce_dot<double>(hipStream_t, int64_t, const int64_t*
 template void launch_seg_reduce_dot<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
                                            double*, const double*, double*, double*, int, int, double*, int*, double);
 
+template <typename TC>
 void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
-                                double* partial, double* s, double rtol2) {
+                                double* partial, double* s, double rtol2, const int64_t* ptr, const int64_t* list,
+                                const double* w, TC* copies) {
   const unsigned nb = dot_blocks(n);
-  hipLaunchKernelGGL(k_pcg_update_xr_partial, dim3(nb), dim3(256), 0, st, n, x, r, p, q, s, partial);
+  hipLaunchKernelGGL(k_pcg_update_xr_partial<TC>, dim3(nb), dim3(256), 0, st, n, x, r, p, q, s, partial, ptr, list, w, copies);
   hipLaunchKernelGGL(k_dot_step, dim3(1), dim3(256), 0, st, (int)nb, partial, s, (int)S_RR, (int)DOT_CHECK, nullptr, nullptr,
                      rtol2);
 }
+template void launch_pcg_update_xr_check<double>(hipStream_t, int64_t, double*, double*, const double*, const double*,
+                                                 double*, double*, double, const int64_t*, const int64_t*, const double*,
+                                                 double*);
+template void launch_pcg_update_xr_check<float>(hipStream_t, int64_t, double*, double*, const double*, const double*, double*,
+                                                double*, double, const int64_t*, const int64_t*, const double*, float*);
 
 void launch_set_int(hipStream_t st, int* p, int v) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v); }
-void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s) {
-  hipLaunchKernelGGL(k_pcg_update_p, dim3(grid_for(n)), dim3(256), 0, st, n, p, z, s);
+void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s, const int64_t* ptr,
+                         const int64_t* list, double* copies) {
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(grid_for(n)), dim3(256), 0, st, n, p, z, s, ptr, list, copies);
 }
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y) {
   if (n <= 0) return;
@@ -751,6 +791,8 @@ void launch_scatter_idx(hipStream_t st, int64_t n, const int32_t* idx, const dou
 }
 
 #define INST_MV(TA, TX, TY)                                                                                             \
+  template void launch_tile_mv_sum<TA, TX, TY>(hipStream_t, int, const MvDesc*, int, const MvDesc*, int32_t, int32_t, \
+                                               const TA*, const TX*, const TX*, TY*, double, bool);                   \
   template void launch_tile_mv<TA, TX, TY>(hipStream_t, int, const MvDesc*, int32_t, int64_t, const int64_t*, const TA*, \
                                            const TX*, TY*, double, bool, TA*, int32_t);
 INST_MV(double, double, double)

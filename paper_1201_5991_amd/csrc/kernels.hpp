@@ -83,6 +83,12 @@ struct MvDesc {
 // workgroup per output tile; larger ones as a workgroup per tile plus a
 // reduction of the partial tiles.
 constexpr int64_t SMALL_MV_TILES = 64;
+// y = alpha (A1 x + A2 x2) (+ y) for two small product sets whose items
+// write the same output tiles (item i of both: equal output count and y_off),
+// in one launch.
+template <typename TA, typename TX, typename TY>
+void launch_tile_mv_sum(hipStream_t st, int mode, const MvDesc* d, int mode2, const MvDesc* d2, int32_t nitems,
+                        int32_t max_out_tiles, const TA* A, const TX* x, const TX* x2, TY* y, double alpha, bool accumulate);
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles,
                     const int64_t* tile_prefix, const TA* A, const TX* x, TY* y, double alpha, bool accumulate,
@@ -140,7 +146,10 @@ constexpr int DOT_BLOCKS = 4096;  // at most one partial per 256 entries, as man
 // PCG update kernels then leave x, r, p and the history untouched.
 enum PcgScalar { S_RZ = 0, S_PQ = 1, S_ALPHA = 2, S_RR = 3, S_RZNEW = 4, S_BETA = 5, S_GG = 6, S_DONE = 7, S_NSCAL = 8 };
 void launch_set_int(hipStream_t st, int* p, int v);
-void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s);  // p = z + beta p
+// p = z + beta p (unless done); when copies is given, also copies[list[j]] = p[g]
+// for j in ptr[g]..ptr[g+1] (the gather that starts the interface product).
+void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s, const int64_t* ptr = nullptr,
+                         const int64_t* list = nullptr, double* copies = nullptr);
 // Steps that the single-block finish of a PCG dot product does after it:
 // DOT_ALPHA alpha = rz / pq (slot S_PQ); DOT_CHECK the stopping
 // test, s[S_DONE] = 1 (sticky) when p.q <= 0 or not finite or r.r < rtol2 g.g
@@ -153,9 +162,13 @@ void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const 
                            double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,
                            int* it, double rtol2);
 // x += alpha p, r -= alpha q (unless done) and the partial sums of r.r in one
-// launch, then the finish of r.r with the stopping test.
+// launch, then the finish of r.r with the stopping test; when copies is given
+// the launch also writes copies[list[j]] = w[list[j]] r[g] for j in
+// ptr[g]..ptr[g+1] (the weighted restriction that starts the preconditioner).
+template <typename TC>
 void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
-                                double* partial, double* s, double rtol2);
+                                double* partial, double* s, double rtol2, const int64_t* ptr, const int64_t* list,
+                                const double* w, TC* copies);
 void launch_axpby(hipStream_t st, int64_t n, double a, const double* x, double b, double* y);
 
 // Element energies out_e = E_e a_e^T K0 b_e (level-1 mesh).

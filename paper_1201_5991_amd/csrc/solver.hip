@@ -122,6 +122,7 @@ struct LevelDev {
   void* partial = nullptr;
   // tile mat-vec sets
   MvSet mvS, mvG, mvPsiN, mvPsiT, mvPre, mvPreT, mvPostN;
+  bool g_psi_sum = false;  // y = G r + Psi z_C as one launch (both products small, items aligned)
   // triangular solves: items sorted by dissection height (trsv_lvl[h] = first
   // item of height h, last entry = item count) and the tile lists
   std::vector<TrsvDesc> trsv_h;
@@ -371,9 +372,11 @@ struct Handle {
     int slot, step;
     double rtol2;
   };
-  mlbddc_status apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds = nullptr);
+  // r_copied: the weighted copies of rhat are already in place (written by the PCG update)
+  mlbddc_status apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds = nullptr, bool r_copied = false);
   mlbddc_status apply_full(int li, const double* r, double* z);
-  mlbddc_status schur(const double* x, double* y, const DotFinish* ds = nullptr);
+  // x_copied: the subdomain copies of x are already in place (written by the PCG update)
+  mlbddc_status schur(const double* x, double* y, const DotFinish* ds = nullptr, bool x_copied = false);
   mlbddc_status condense(const double* f, double* g);
   mlbddc_status recover(const double* uhat, double* u);
   mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
@@ -1112,6 +1115,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       if ((st = build_mv(D.mvG, MV_SYM, g))) return st;
       if ((st = build_mv(D.mvPsiN, MV_N, pn))) return st;
       if ((st = build_mv(D.mvPsiT, MV_T, pt))) return st;
+      D.g_psi_sum = D.mvG.tiles <= SMALL_MV_TILES && D.mvPsiT.tiles <= SMALL_MV_TILES && D.mvG.h.size() == D.mvPsiT.h.size() &&
+                    D.mvG.max_out == D.mvPsiT.max_out;
+      for (size_t q = 0; D.g_psi_sum && q < D.mvG.h.size(); ++q)
+        D.g_psi_sum = D.mvG.h[q].nr == D.mvPsiT.h[q].nc && D.mvG.h[q].y_off == D.mvPsiT.h[q].y_off;
     }
     // partial-sum scratch: the largest of this level's products
     int64_t pmax = 1;
@@ -1490,13 +1497,17 @@ mlbddc_status Handle::numeric() {
 }
 
 // --------------------------------------------------------------------- apply
-mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds) {
+mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds, bool r_copied) {
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   mlbddc_status st;
   // r_i = D_i R_i r^
-  if (D.mfp32) launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
-  else launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
+  if (r_copied) {
+  } else if (D.mfp32) {
+    launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
+  } else {
+    launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
+  }
   // r_C = sum R_Ci^T Psi_i^T r_i
   if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
   else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, 1.0, false, D.partial);
@@ -1506,8 +1517,14 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
   // y_i = G_i r_i + Psi_i R_Ci z_C
   if (D.mfp32) {
     launch_gather<double, float>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (float*)D.zcl);
-    run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial);
-    run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
+    if (D.g_psi_sum) {
+      launch_tile_mv_sum<float, float, float>(stream, MV_SYM, D.mvG.d, MV_T, D.mvPsiT.d, (int32_t)D.mvG.h.size(), D.mvG.max_out,
+                                              (const float*)D.M.buf, (const float*)D.rl, (const float*)D.zcl, (float*)D.yl, 1.0,
+                                              false);
+    } else {
+      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial);
+      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
+    }
     if (ds)  // with rhat.zhat and its scalar step
       launch_seg_reduce_dot<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat,
                                    rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2);
@@ -1515,8 +1532,14 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
       launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0);
   } else {
     launch_gather<double, double>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (double*)D.zcl);
-    run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial);
-    run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
+    if (D.g_psi_sum) {
+      launch_tile_mv_sum<double, double, double>(stream, MV_SYM, D.mvG.d, MV_T, D.mvPsiT.d, (int32_t)D.mvG.h.size(),
+                                                 D.mvG.max_out, (const double*)D.M.buf, (const double*)D.rl,
+                                                 (const double*)D.zcl, (double*)D.yl, 1.0, false);
+    } else {
+      run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial);
+      run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
+    }
     if (ds)
       launch_seg_reduce_dot<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl,
                                     zhat, rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2);
@@ -1569,9 +1592,9 @@ mlbddc_status Handle::apply_full(int li, const double* r, double* z) {
   return MLBDDC_OK;
 }
 
-mlbddc_status Handle::schur(const double* x, double* y, const DotFinish* ds) {
+mlbddc_status Handle::schur(const double* x, double* y, const DotFinish* ds, bool x_copied) {
   LevelDev& D = lev[0];
-  launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, x, D.gd);
+  if (!x_copied) launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, x, D.gd);
   run_mv<double, double, double>(D.mvS, D.K, D.gd, D.gd2, 1.0, false, D.partial);
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   if (ds)  // with x.y and its scalar step
@@ -1659,11 +1682,19 @@ static void lanczos(const std::vector<double>& al, const std::vector<double>& be
 mlbddc_status Handle::pcg_body(bool first) {
   mlbddc_status st;
   const int64_t n = (int64_t)lev[0].P->iface_dofs.size();
-  if (!first) launch_pcg_update_p(stream, n, d_p, d_z, d_s);
+  LevelDev& D = lev[0];
+  // p and r are written to their subdomain copies by the updates themselves
+  // (the padding entries of the copies keep the zeros of the first gathers)
+  if (!first) launch_pcg_update_p(stream, n, d_p, d_z, d_s, D.d_gptr, D.d_glist, D.gd);
   const DotFinish pq{S_PQ, DOT_ALPHA, 0.0}, rz{S_RZNEW, DOT_BETA, 0.0};
-  if ((st = schur(d_p, d_q, &pq))) return st;
-  launch_pcg_update_xr_check(stream, n, d_x, d_r, d_p, d_q, d_dotp, d_s, opt.rtol * opt.rtol);
-  if ((st = apply_interface(0, d_r, d_z, &rz))) return st;
+  if ((st = schur(d_p, d_q, &pq, !first))) return st;
+  if (D.mfp32)
+    launch_pcg_update_xr_check<float>(stream, n, d_x, d_r, d_p, d_q, d_dotp, d_s, opt.rtol * opt.rtol, D.d_gptr, D.d_glist,
+                                      D.d_w, (float*)D.rl);
+  else
+    launch_pcg_update_xr_check<double>(stream, n, d_x, d_r, d_p, d_q, d_dotp, d_s, opt.rtol * opt.rtol, D.d_gptr, D.d_glist,
+                                       D.d_w, (double*)D.rl);
+  if ((st = apply_interface(0, d_r, d_z, &rz, true))) return st;
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
