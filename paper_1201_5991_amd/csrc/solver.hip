@@ -1502,11 +1502,9 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
   LevelPlan& P = *D.P;
   mlbddc_status st;
   // r_i = D_i R_i r^
-  if (r_copied) {
-  } else if (D.mfp32) {
-    launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
-  } else {
-    launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
+  if (!r_copied) {
+    if (D.mfp32) launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
+    else launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
   }
   // r_C = sum R_Ci^T Psi_i^T r_i
   if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
