@@ -1737,20 +1737,25 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
   launch_dot(stream, n, d_g, d_g, d_dotp, DOT_BLOCKS, d_s + S_GG);
   launch_dot(stream, n, d_r, d_r, d_dotp, DOT_BLOCKS, d_s + S_RR);
   HIPCHK(hipMemcpyAsync(h_s, d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  for (hipEvent_t& e : ev_snap)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev_snap[0], stream));
+  // z0 = M^-1 r0, <r0,z0> and p0 = z0 are queued before the host reads the
+  // initial norms, so the device works while the host waits; they write only
+  // z, p and the RZ scalar, which nothing reads if r0 already meets the
+  // tolerance (a zero r0 gives a zero z0).
+  if ((st = apply_interface(0, d_r, d_z))) return st;
+  launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZ);
+  HIPCHK(hipMemcpyAsync(d_p, d_z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+  launch_set_int(stream, d_it, 0);
+  launch_fill(stream, 1, 0.0, d_s + S_DONE);
+  HIPCHK(hipEventSynchronize(ev_snap[0]));
   const double gnorm = std::sqrt(h_s[S_GG]);
   double rel = gnorm > 0 ? std::sqrt(h_s[S_RR]) / gnorm : 0.0;
   int it = 0;
   bool conv = rel < opt.rtol;
   bool breakdown = false;
   if (!conv) {
-    if ((st = apply_interface(0, d_r, d_z))) return st;
-    launch_dot(stream, n, d_r, d_z, d_dotp, DOT_BLOCKS, d_s + S_RZ);
-    HIPCHK(hipMemcpyAsync(d_p, d_z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
-    launch_set_int(stream, d_it, 0);
-    launch_fill(stream, 1, 0.0, d_s + S_DONE);
-    for (hipEvent_t& e : ev_snap)
-      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // Iteration k+1 is normally queued before the host reads iteration k's
     // scalars (snapshot k&1), so the device does not wait for the host; once
     // the device flags convergence or breakdown a queued iteration changes
