@@ -387,6 +387,7 @@ struct Handle {
   mlbddc_status recover(const double* uhat, double* u);
   mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
   mlbddc_status pcg_body(bool first);
+  mlbddc_status capture_pcg();
   mlbddc_status solve_on_stream(const double* f, double* u, const double* u0, mlbddc_stats* st);
 };
 
@@ -1182,6 +1183,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if ((st = upload_fence())) return st;
   // host preparation done; the device may still be factorizing the last parts
   t_plan = now() - t0;
+  if (opt.use_graph && !lev.empty() && !lev[0].P->top && (st = capture_pcg())) return st;
   st = finish_numeric();
   if (h_edof) {  // copied beside the solve; element energies wait for it
     edof_job.get();
@@ -1741,6 +1743,38 @@ mlbddc_status Handle::pcg_body(bool first) {
 // With graphs the whole solve runs on an internal stream ordered after the
 // caller's stream (the caller's stream may be the null stream, which cannot
 // be captured); the caller's stream waits for it at the end.
+// Capture one PCG iteration (a non-first pcg_body) as a HIP graph on the
+// internal stream; the set-up does it while the device factorizes, so that a
+// solve does not wait for it.
+mlbddc_status Handle::capture_pcg() {
+  if (!cap) {
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  }
+  if (gexec) return MLBDDC_OK;
+  hipStream_t user = stream;
+  stream = cap;
+  hipGraph_t graph = nullptr;
+  hipError_t be = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  mlbddc_status cst = be == hipSuccess ? pcg_body(false) : MLBDDC_OK;
+  hipError_t ce = be == hipSuccess ? hipStreamEndCapture(stream, &graph) : hipSuccess;
+  stream = user;
+  if (be != hipSuccess) return herr("hipStreamBeginCapture", be);
+  if (cst) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return cst;
+  }
+  if (ce != hipSuccess) return herr("hipStreamEndCapture", ce);
+  hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    gexec = nullptr;
+    return herr("hipGraphInstantiate", ie);
+  }
+  return MLBDDC_OK;
+}
+
 mlbddc_status Handle::solve(const double* f, double* u, const double* u0, mlbddc_stats* stt) {
   if (!opt.use_graph) return solve_on_stream(f, u, u0, stt);
   if (!cap) {
@@ -1806,20 +1840,7 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
       if (k == 0 || !opt.use_graph) {
         if ((sb = pcg_body(k == 0))) return sb;
       } else {
-        if (!gexec) {
-          hipGraph_t graph = nullptr;
-          HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-          mlbddc_status cst = pcg_body(false);
-          hipError_t ce = hipStreamEndCapture(stream, &graph);
-          if (cst) return cst;
-          if (ce != hipSuccess) return herr("hipStreamEndCapture", ce);
-          hipError_t ie = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(graph);
-          if (ie != hipSuccess) {
-            gexec = nullptr;
-            return herr("hipGraphInstantiate", ie);
-          }
-        }
+        if (!gexec && (sb = capture_pcg())) return sb;
         HIPCHK(hipGraphLaunch(gexec, stream));
       }
       HIPCHK(hipMemcpyAsync(h_s + S_NSCAL * (1 + (k & 1)), d_s, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, stream));
