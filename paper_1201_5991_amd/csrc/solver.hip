@@ -357,6 +357,8 @@ struct Handle {
   mlbddc_status setup(const mlbddc_mesh* mesh, const mlbddc_partition* part);
   mlbddc_status validate_level(int li, int part);
   mlbddc_status enqueue_K(int li, bool zero);
+  mlbddc_status enqueue_K_assembly(int li, bool zero);
+  mlbddc_status enqueue_K_factor(int li);
   mlbddc_status enqueue_rest(int li, bool zero);
   mlbddc_status finish_numeric();
   mlbddc_status numeric();
@@ -777,11 +779,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   // stream sees the same order as a sequential set-up.
   std::future<mlbddc_status> pending;
   auto join = [&]() -> mlbddc_status { return pending.valid() ? pending.get() : MLBDDC_OK; };
-  auto enqueue_async = [&](int li, bool kjob) {
+  // part 0: K assembly; 1: interface weights and K factorization; 2: the rest
+  auto enqueue_async = [&](int li, int part) {
     const int dev = opt.device;
-    pending = std::async(std::launch::async, [this, li, kjob, dev]() -> mlbddc_status {
+    pending = std::async(std::launch::async, [this, li, part, dev]() -> mlbddc_status {
       if (hipSetDevice(dev) != hipSuccess) return herr("hipSetDevice", hipGetLastError());
-      return kjob ? enqueue_K(li, false) : enqueue_rest(li, false);
+      return part == 0 ? enqueue_K_assembly(li, false) : part == 1 ? enqueue_K_factor(li) : enqueue_rest(li, false);
     });
   };
   PlanInput in;
@@ -924,6 +927,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
 
     mark("  assembly maps");
+    // the device assembles K while the host builds the flat layouts
+    if ((st = checked.get())) return st;
+    mark("  validate (K job)");
+    if ((st = join())) return st;
+    if ((st = upload_fence())) return st;
+    enqueue_async(li, 0);
     // flat layouts
     D.gofs.assign(ns + 1, 0);
     D.iofs.assign(ns + 1, 0);
@@ -999,12 +1008,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     if ((st = dalloc(&D.wI, std::max<int64_t>(D.nI_flat, 1)))) return st;
 
     mark("  flat layouts + vectors");
-    // the device assembles and factors this level's K job while the host goes on
-    if ((st = checked.get())) return st;
-    mark("  validate (K job)");
+    // the device factors this level's K job while the host goes on
     if ((st = join())) return st;
     if ((st = upload_fence())) return st;
-    enqueue_async(li, true);
+    enqueue_async(li, 1);
     // K-job tile mat-vecs
     {
       std::vector<MvDesc> s, pre;
@@ -1160,7 +1167,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     mark("  validate (rest)");
     if ((st = join())) return st;
     if ((st = upload_fence())) return st;
-    enqueue_async(li, false);
+    enqueue_async(li, 2);
     if (li == 0 && h_edof) start_edof();  // the next levels wait for the device
   }
   if (h_edof && !edof_job.valid()) start_edof();
@@ -1402,6 +1409,11 @@ mlbddc_status Handle::validate_level(int li, int part) {
 // library stream only; errors are collected by finish_numeric().
 mlbddc_status Handle::enqueue_K(int li, bool zero) {
   mlbddc_status st;
+  if ((st = enqueue_K_assembly(li, zero))) return st;
+  return enqueue_K_factor(li);
+}
+
+mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   // assemble K
@@ -1423,6 +1435,13 @@ mlbddc_status Handle::enqueue_K(int li, bool zero) {
   else
     launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
   HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
+mlbddc_status Handle::enqueue_K_factor(int li) {
+  mlbddc_status st;
+  LevelDev& D = lev[li];
+  LevelPlan& P = *D.P;
   // weights from the assembled interface diagonal (before factorization)
   if (!P.top) {
     const int64_t nif = (int64_t)P.iface_dofs.size();
