@@ -11,10 +11,12 @@ next-level assembly, top coarse factor), condensation, BDDC-PCG to
 ||r||/||g|| < 1e-8 and interior recovery.  Inputs are resident in device
 memory before the timed region.
 
-The default workload is 3D linear elasticity on a 48^3 hexahedral mesh of
-the unit cube (345,744 DOFs), 4x4x4 subdomains of 12^3 elements, corners +
-edge + face averages, three levels (2x2x2 level-2 groups), E = 1, nu = 0.3,
-body force (0, 0, -1), face x = 0 clamped.
+The default workload is the largest single-GPU configuration: 3D linear
+elasticity on a 96^3 hexahedral mesh of the unit cube (2,709,792 DOFs),
+12x12x12 = 1728 subdomains of 8^3 elements, corners + edge + face
+averages, three levels (4x4x4 level-2 groups -> 27 level-2 subdomains,
+top coarse problem of 294 DOFs), per-element E = 10^(3U), U ~ U(0,1)
+(seed 0), nu = 0.3, body force (0, 0, -1), face x = 0 clamped.
 
 Prints one JSON line (see the field notes in the design doc).
 """
@@ -64,32 +66,92 @@ def algorithmic_apply_bytes(s, precision: str) -> dict:
     return {"apply": total, "schur": schur}
 
 
-def kernel_source_hash() -> str:
-    """Hash of the tile-update kernel's source (the PMC traffic figure in
-    profiles/ is only valid for the kernel it was measured on)."""
+# Source sections whose PMC traffic figures are valid only for the code they were measured on.
+KERNEL_SOURCES = {
+    "k_tile_mm": ("dense.hip", "// Register staging of NE consecutive elements",
+                  "template <typename T>\n__global__ void __launch_bounds__(256) k_negate("),
+    "k_mv_tiles": ("apply.hip", "// ---------------------------------------------------------------- tile mv",
+                   "// Sum of the partial tiles of one output tile"),
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
     import hashlib
-    src = open(os.path.join(ROOT, "paper_1201_5991_amd", "csrc", "dense.hip")).read()
-    a = src.index("// Register staging of NE consecutive elements")
-    b = src.index("template <typename T>\n__global__ void __launch_bounds__(256) k_negate(")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    fname, a, b = KERNEL_SOURCES[kernel.split("<")[0]]
+    src = open(os.path.join(ROOT, "paper_1201_5991_amd", "csrc", fname)).read()
+    return hashlib.sha256(src[src.index(a):src.index(b)].encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, flops_per_launch: float):
-    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
-    (also when the summary was taken on another workload, another kernel
-    source or another factorization schedule: launches of another size)."""
-    path = os.path.join(ROOT, "profiles", "k_tile_mm_traffic.json")
+def measured_traffic(kernel: str, workload: str, per_launch: float):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (profiles/pmc_traffic.json), or None when the summary was taken on
+    another workload, another kernel source, or launches of another size
+    (`per_launch`: the algorithmic flops or bytes of one launch)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     k = d.get("kernels", {}).get(kernel)
-    if not k or d.get("source_hash") != kernel_source_hash() or d.get("workload_name") != workload:
+    if not k or d.get("workload_name") != workload or k.get("source_hash") != kernel_source_hash(kernel):
         return None
-    f = k.get("flops_per_launch")
-    if not f or abs(f - flops_per_launch) > 0.01 * flops_per_launch:
+    ref = k.get("algorithmic_per_launch")
+    if not ref or abs(ref - per_launch) > 0.01 * per_launch:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+MV_KERNEL = {("schur_mv", "mixed"): "k_mv_tiles<double, double>", ("schur_mv", "fp64"): "k_mv_tiles<double, double>",
+             ("precond_mv", "mixed"): "k_mv_tiles<float, float>", ("precond_mv", "fp64"): "k_mv_tiles<double, double>"}
+
+
+def rooflines(R: dict, mode: str, workload: str):
+    """Roofline of the dominant kernel class of one step (largest device time
+    per step: a set-up class once, a product class once per PCG iteration),
+    and of the dominant set-up kernel."""
+    prof = {k: v for k, v in R["profile"].items() if k != "jobs"}
+    its = R["iterations"]
+    per_step = {}
+    for k, v in prof.items():
+        if not v["launches"]:
+            continue
+        per_step[k] = v["time_s"] / v["launches"] * its if k.endswith("_mv") else v["time_s"]
+    setup_cls = [k for k in per_step if not k.endswith("_mv")]
+
+    def mfma(k):
+        v = prof[k]
+        prec = "fp32" if k.endswith("fp32") else "fp64"
+        achieved = v["flops"] / v["time_s"] * 1e-12 if v["time_s"] > 0 else 0.0
+        kern = f"k_tile_mm<{'float' if prec == 'fp32' else 'double'}, false>" if k.startswith("update") else k
+        r = {"kernel": kern, "bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
+             "frac": achieved / PEAK[prec], "traffic": None,
+             "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+             "launches": v["launches"], "avg_launch_ms": v["time_s"] / max(v["launches"], 1) * 1e3,
+             "flops_per_launch": v["flops"] / max(v["launches"], 1),
+             # lower bound on a launch's HBM bytes: each updated 64x64 tile read and written once
+             "c_tile_bytes_per_launch": v["tiles"] / max(v["launches"], 1) * 2 * 64 * 64 * (4 if prec == "fp32" else 8)}
+        if k.startswith("update"):
+            r["traffic"] = measured_traffic(kern, workload, r["flops_per_launch"])
+        return r
+
+    def hbm(k):
+        v = prof[k]
+        n = max(v["launches"], 1)
+        avg = v["time_s"] / n
+        per = v["bytes"] / n
+        achieved = per / avg * 1e-9 if avg > 0 else 0.0
+        kern = MV_KERNEL[(k, mode)]
+        return {"kernel": kern, "product": "S^ = sum R_i^T S_i R_i (FP64)" if k == "schur_mv" else "level-1 G_i r_i",
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": measured_traffic(kern, workload, per),
+                "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes_per_launch": per, "launches": v["launches"], "avg_launch_ms": avg * 1e3,
+                "device_ms_per_step": avg * its * 1e3}
+
+    dom = max(per_step, key=per_step.get)
+    roof = hbm(dom) if dom.endswith("_mv") else mfma(dom)
+    roof_setup = mfma(max(setup_cls, key=per_step.get)) if setup_cls else None
+    return roof, roof_setup
 
 
 def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0, graph: bool = True,
@@ -114,22 +176,16 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
     torch.cuda.synchronize()
     tts = (time.perf_counter() - t0) / steps
     _log(f"[{precision}] tts {tts:.4f} s, its {st['iterations']}, rel_res {st['rel_res']:.2e}")
-    # true interface residual of the last solution
-    g = s.condense(f)
-    iface = torch.as_tensor(s.problem.node_to_free, device="cuda")  # noqa: F841 (kept for clarity)
-    # profiled set-up pass (events around every factorization launch on the library's stream)
-    s.set_profiling(True)
-    s.setup(prob)
-    prof = s.profile()
-    s.set_profiling(False)
-    u, st2 = s.solve(f)
-    # applies/s on a fixed seeded vector
+    # applies/s on a fixed seeded vector (the whole apply: restriction, local
+    # solves, coarse levels, averaging), and the S^ product alone
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     r = torch.randn(s.n_iface, dtype=torch.float64, device="cuda", generator=gen)
     z = torch.empty_like(r)
+    x = torch.empty_like(r)
     for _ in range(10):
         s.apply_into(r, z)
+        s.apply_schur_into(r, x)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -138,14 +194,24 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
     e1.record()
     torch.cuda.synchronize()
     t_apply = e0.elapsed_time(e1) * 1e-3 / applies
-    x = torch.empty_like(r)
     e0.record()
     for _ in range(applies):
-        s._chk(s.lib.mlbddc_apply_schur(s.h, r.data_ptr(), x.data_ptr()))
+        s.apply_schur_into(r, x)
     e1.record()
     torch.cuda.synchronize()
     t_schur = e0.elapsed_time(e1) * 1e-3 / applies
     nbytes = algorithmic_apply_bytes(s, precision)
+    # profiled pass: HIP events inside the library around every factorization
+    # launch of one set-up and around the S^ / G tile-product kernels of
+    # eager applies, each on the stream the launch runs on
+    s.set_profiling(True)
+    s.setup(prob)
+    for _ in range(applies):
+        s.apply_schur_into(r, x)
+        s.apply_into(r, z)
+    torch.cuda.synchronize()
+    prof = s.profile()
+    s.set_profiling(False)
     res = {
         "tts_s": tts,
         "tts_first_call_s": t_cold,
@@ -163,15 +229,37 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
         "schur_alg_GBps": nbytes["schur"] / t_schur * 1e-9,
         "profile": prof,
     }
-    del s
+    s.destroy()
     return res
 
 
-def cpu_baseline(seconds_hint: float = 20.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
-    full oracle pipeline (set-up, condensation, PCG to 1e-8, recovery) on
-    8 of the 64 subdomains (a 24^3 mesh with 2x2x2 subdomains of the same
-    12^3 size, two levels), scaled by 64 / 8 to the full workload's seconds."""
+def _oracle_record(workload: str):
+    """The committed full-size oracle run of `workload` (written by
+    tests/golden/make_golden.py, which calls only the oracle), or None."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "tests", "golden", "*.json"))):
+        try:
+            d = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if d.get("workload") == workload and "oracle_time_s" in d and isinstance(d["oracle_time_s"], dict):
+            return {"file": os.path.relpath(path, ROOT), "time_s": d["oracle_time_s"], "iterations": d["pcg"]["iterations"],
+                    "host": d.get("host")}
+    return None
+
+
+def cpu_baseline(w, levels: int, gpu_iterations: int):
+    """The FP64 oracle, as it stands, on a bounded sample of the benchmark
+    workload, scaled to the whole workload's time-to-solution.
+
+    Sample: the corner block of 3x3x3 of the workload's subdomains (the same
+    subdomain size and the same element moduli, the clamped face included),
+    run through the oracle's full pipeline (set-up, condensation, PCG to
+    1e-8, recovery) at two levels.  The oracle's work is a loop over
+    subdomains, so its set-up, condensation and recovery scale with the
+    subdomain count, and its PCG with the subdomain count times the
+    iteration count; the full workload's iteration count is the oracle's own
+    when its full-size run is committed, else the GPU's."""
     import numpy as np
     from oracle import fem
     from oracle.bddc import MultilevelBDDC
@@ -180,28 +268,47 @@ def cpu_baseline(seconds_hint: float = 20.0):
     from workloads.gen import uniform_cuts
     try:
         from threadpoolctl import threadpool_info
+        import numpy  # noqa: F401  (BLAS loaded before the query)
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
-    w = box_workload("sample", "elasticity", (24,) * 3, [uniform_cuts(24, 2)] * 3)
+    nsub_axis = [len(c) - 1 for c in w.cuts]
+    el = [int(np.diff(c)[0]) for c in w.cuts]
+    k = 3
+    n = [k * e for e in el]
+    young = w.young.reshape(w.n_el[::-1])[: n[2], : n[1], : n[0]].ravel()
+    ws = box_workload("sample", "elasticity", tuple(n), [uniform_cuts(n[d], k) for d in range(3)], young=young)
+    nsub_full = int(np.prod(nsub_axis))
+    scale = nsub_full / k ** 3
     t0 = time.perf_counter()
-    b = MultilevelBDDC(w, n_levels=2)
-    _, f = fem.assemble_global(w)
-    g = b.condense(f)
+    b = MultilevelBDDC(ws, n_levels=2)
+    t_setup = time.perf_counter() - t0
+    _, fs = fem.assemble_global(ws)
+    t1 = time.perf_counter()
+    g = b.condense(fs)
+    t_cond = time.perf_counter() - t1
+    t2 = time.perf_counter()
     res = pcg(b.schur_apply, g, b.apply, tol=1e-8)
-    b.recover(f, res.x)
-    t = time.perf_counter() - t0
-    r = np.random.default_rng(0).standard_normal(b.level1.n_iface)
-    ta = time.perf_counter()
-    b.apply(r)
-    ta = time.perf_counter() - ta
-    scale = 64 / 8
-    return {"value": t * scale, "unit": "s (time-to-solution, estimated for 64 subdomains)", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"full FP64 oracle solve on 8 of the 64 subdomains (24^3 mesh, 2x2x2 boxes of 12^3, 2 levels, "
-                      f"{res.iterations} PCG its) took {t:.2f} s; scaled x{scale:g}. One oracle apply on the sample "
-                      f"took {ta * 1e3:.1f} ms (~{1.0 / (ta * scale):.2f} applies/s scaled)",
-            "applies_per_s": 1.0 / (ta * scale)}
+    t_pcg = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    b.recover(fs, res.x)
+    t_rec = time.perf_counter() - t3
+    rec = _oracle_record(w.name)
+    its_full = rec["iterations"] if rec else gpu_iterations
+    per_it = t_pcg / max(res.iterations, 1)
+    value = scale * (t_setup + t_cond + t_rec + per_it * its_full)
+    out = {"value": value, "unit": "s (time-to-solution of the whole workload, scaled from the sample)",
+           "cores": int(cores), "kind": "oracle",
+           "sample": (f"FP64 oracle (SciPy SuperLU per subdomain, NumPy) on the corner 3x3x3 block of the workload's "
+                      f"subdomains ({n[0]}x{n[1]}x{n[2]} elements, the same 8^3-element subdomains and moduli), 2 levels: "
+                      f"set-up {t_setup:.2f} s, condensation {t_cond:.2f} s, {res.iterations} PCG iterations "
+                      f"{t_pcg:.2f} s, recovery {t_rec:.2f} s; scaled x{scale:g} subdomains and to {its_full} "
+                      f"iterations ({'the oracle' if rec else 'the GPU'}'s count on the full workload)"),
+           "sample_s": t_setup + t_cond + t_pcg + t_rec}
+    if rec:
+        out["full_run"] = {"note": "the oracle's measured run on the whole workload, committed with the parity fixtures",
+                           **rec}
+    return out
 
 
 def main():
@@ -209,7 +316,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--applies", type=int, default=100)
     ap.add_argument("--modes", default="fp64,mixed")
@@ -243,21 +350,7 @@ def main():
                           args.lookahead)
     main_mode = "mixed" if "mixed" in out else modes[0]
     R = out[main_mode]
-    # dominant kernel of the timed path: the largest device-time class of the set-up profile
-    prof = {k: v for k, v in R["profile"].items() if k != "jobs"}
-    dom = max(prof, key=lambda k: prof[k]["time_s"])
-    dprof = prof[dom]
-    prec = "fp32" if dom.endswith("fp32") else "fp64"
-    achieved = dprof["flops"] / dprof["time_s"] * 1e-12 if dprof["time_s"] > 0 else 0.0
-    roof = {"kernel": f"k_tile_mm<{'float' if prec == 'fp32' else 'double'}, false>" if dom.startswith("update") else dom,
-            "bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK[prec], "traffic": None,
-            "traffic_unit": "bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "launches": dprof["launches"], "avg_launch_ms": dprof["time_s"] / max(dprof["launches"], 1) * 1e3,
-            "flops_per_launch": dprof["flops"] / max(dprof["launches"], 1),
-            # lower bound on a launch's HBM bytes: each updated 64x64 tile read and written once
-            "c_tile_bytes_per_launch": dprof["tiles"] / max(dprof["launches"], 1) * 2 * 64 * 64 * (4 if prec == "fp32" else 8)}
-    roof["traffic"] = measured_traffic(roof["kernel"], w.name, roof["flops_per_launch"])
+    roof, roof_setup = rooflines(R, main_mode, w.name)
     line = {
         "metric": METRIC,
         "value": R["tts_s"],
@@ -277,11 +370,13 @@ def main():
                    "pcg_graph": not args.no_graph, "lookahead": args.lookahead},
         "applies_per_s": R["applies_per_s"],
         "roofline": roof,
+        "roofline_setup": roof_setup,
     }
     for m in modes:
         d = dict(out[m])
         jobs = d["profile"].get("jobs", {})
         d["profile"] = {k: {"time_ms": v["time_s"] * 1e3, "tflops": (v["flops"] / v["time_s"] * 1e-12 if v["time_s"] else 0.0),
+                            "GBps": (v["bytes"] / v["time_s"] * 1e-9 if v["time_s"] else 0.0),
                             "launches": v["launches"]} for k, v in d["profile"].items() if k != "jobs"}
         d["profile"]["jobs"] = jobs
         line[m] = d
@@ -299,7 +394,7 @@ def main():
         line["copy_calibration_bytes"] = 2 * a.numel() * 8
     if not args.no_cpu_baseline:
         _log("[cpu baseline] oracle sample ...")
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(w, int(prob.n_levels), int(out[main_mode]["iterations"]))
     print(json.dumps(line), flush=True)
 
 

@@ -25,6 +25,7 @@
 #ifndef MLBDDC_H
 #define MLBDDC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -122,9 +123,32 @@ const char* mlbddc_status_string(mlbddc_status code);
 /* Default options (FP64, rtol 1e-8, max_iter 1000, stiffness weights, no graph). */
 void mlbddc_default_options(mlbddc_options* opt);
 
+/* Device memory provider.  alloc(bytes, ctx) returns device memory of at
+ * least `bytes` bytes on options->device, aligned to 256 bytes, or NULL when
+ * it has none (the library then releases its cached blocks once and retries,
+ * else fails with E_NOMEM); free(ptr, ctx) takes back a block that alloc
+ * returned.  Both are called from the thread that calls setup, update and
+ * destroy, only while that call runs.  A block is handed back only when no
+ * queued library work uses it any more: before free, the library has
+ * synchronized every stream it used the block on, so an allocator that
+ * reuses blocks on the caller's stream needs no further ordering.  With a
+ * caching allocator (e.g. a framework's), the library owns no device memory
+ * of its own. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} mlbddc_allocator;
+
 /* Create a handle on options->device, ordering all work on `stream`
- * (a hipStream_t passed as void*).  *h receives the handle. */
-mlbddc_status mlbddc_create(mlbddc_t* h, const mlbddc_options* opt, void* stream);
+ * (a hipStream_t passed as void*).  *h receives the handle.  `alloc`
+ * (copied; may be NULL = hipMalloc / hipFree) provides every device block
+ * the handle uses (the operators of every level, work vectors, index maps);
+ * pinned host staging buffers are allocated by the library itself.
+ * Errors: E_ARG (bad options, an allocator without alloc or free),
+ * E_NO_DEVICE, E_HIP.  This follows the paper's statement of the problem
+ * (section 2): one handle holds one decomposition of one mesh. */
+mlbddc_status mlbddc_create(mlbddc_t* h, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream);
 
 /* Set-up (Algorithm 1): plan the levels from the mesh and partition on the
  * host (interface classification into faces, edges and vertices; corner
@@ -149,6 +173,10 @@ int64_t mlbddc_num_dofs(mlbddc_t h);
 int64_t mlbddc_interface_size(mlbddc_t h);
 int64_t mlbddc_coarse_size(mlbddc_t h, int32_t level);
 int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level);
+
+/* The level-1 interface after setup: out[k] = free-DOF index of interface
+ * entry k (increasing), host [interface_size].  E_STATE before setup. */
+mlbddc_status mlbddc_interface_dofs(mlbddc_t h, int64_t* out);
 
 /* Local sizes of the level-`level` subdomains after setup: out[3*i + 0..2] =
  * {interior DOFs, interface DOFs, constraints} of subdomain i (host
@@ -185,20 +213,27 @@ mlbddc_status mlbddc_element_energy(mlbddc_t h, const double* a_dev, const doubl
  * to host memory; for tests. */
 mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* host_out);
 
-/* Kernel-level profiling of the set-up factorizations (for rooflines).
- * When enabled, HIP events are recorded on the handle's stream around every
- * factorization launch; mlbddc_get_profile returns, per kernel class, the
- * accumulated device time, the number of launches and the algorithmic
- * flops of the tiles those launches processed (dense tile counts: a tile
- * update with k inner tile columns is 2*64^3*k flops, a diagonal tile
- * 64^3/3 for the factor plus 64^3/3 for its inverse).  Enabling resets the
- * counters. */
+/* Kernel-level profiling (for rooflines).  When enabled, HIP events are
+ * recorded around every factorization launch of a set-up (on the stream the
+ * launch runs on), and around the tile product kernel of the level-1
+ * interface operator S^ and of the level-1 local operators G_i in every
+ * apply_schur / apply call made outside stream capture (PCG iterations
+ * replayed from a graph are not timed).  mlbddc_get_profile synchronizes
+ * those events and returns, per kernel class, the accumulated device time,
+ * the number of launches, the algorithmic flops of the tiles the
+ * factorization launches processed (dense tile counts: a tile update with k
+ * inner tile columns is 2*64^3*k flops, a diagonal tile 64^3/3 for the
+ * factor plus 64^3/3 for its inverse) and the algorithmic bytes the product
+ * launches streamed (the stored lower triangles, 8 or 4 bytes per entry of
+ * sum_i n_i (n_i + 1) / 2).  Enabling resets the counters. */
 enum {
   MLBDDC_PROF_UPDATE_FP64 = 0,  /* trailing / in-panel tile updates, FP64 MFMA */
   MLBDDC_PROF_UPDATE_FP32 = 1,  /* trailing / in-panel tile updates, FP32 MFMA */
   MLBDDC_PROF_PANEL = 2,        /* panel solves with inverted diagonal tiles */
   MLBDDC_PROF_DIAG = 3,         /* diagonal tile factor + inverse */
   MLBDDC_PROF_NEGATE = 4,       /* sign flips between elimination phases */
+  MLBDDC_PROF_SCHUR_MV = 5,     /* S^ tile products (k_mv_tiles, FP64) */
+  MLBDDC_PROF_PRECOND_MV = 6,   /* level-1 G_i tile products (k_mv_tiles, FP32 or FP64) */
   MLBDDC_PROF_N = 8
 };
 typedef struct {
@@ -209,6 +244,7 @@ typedef struct {
   double job_time_s[2];           /* wall time of the factorization jobs: [0] subdomain
                                      matrices (all levels), [1] constrained local problems */
   int32_t panel[2];               /* panel widths of the largest K and M jobs of the last set-up */
+  double bytes[MLBDDC_PROF_N];    /* algorithmic bytes of the product classes */
 } mlbddc_profile;
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable);
 mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out);
@@ -233,6 +269,13 @@ mlbddc_status mlbddc_element_matrix(int32_t kind, double h, double nu, double* o
 /* Consistent nodal load of a constant source / body force on one element:
  * out[node * ndof + c] = force[c] * volume / nodes. */
 mlbddc_status mlbddc_element_load(int32_t kind, double h, const double* force, double* out);
+
+/* Load vector of the free DOFs: f = sum over the mesh's elements of the
+ * element load `elem_load` (host [nodes_per_elem * ndof_per_node], node-major,
+ * e.g. from mlbddc_element_load), with the DOFs of Dirichlet nodes dropped.
+ * f: host [n_free_dofs], overwritten.  E_ARG when n_free_dofs does not match
+ * the mesh or a node index is out of range. */
+mlbddc_status mlbddc_assemble_load(const mlbddc_mesh* mesh, const double* elem_load, double* f, int64_t n_free_dofs);
 
 /* Plan the decomposition on the host only and report its structure:
  * counts[level-1][0..5] = {subdomains, interface DOFs, coarse DOFs, corners,

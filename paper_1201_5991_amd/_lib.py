@@ -29,16 +29,25 @@ EXPORTED = [
     "mlbddc_num_subdomains", "mlbddc_apply", "mlbddc_apply_schur", "mlbddc_condense", "mlbddc_solve",
     "mlbddc_element_energy", "mlbddc_get_coarse_matrix", "mlbddc_destroy", "mlbddc_last_error",
     "mlbddc_element_matrix", "mlbddc_element_load", "mlbddc_plan_counts", "mlbddc_plan_interface",
-    "mlbddc_set_profiling", "mlbddc_get_profile", "mlbddc_subdomain_sizes",
+    "mlbddc_set_profiling", "mlbddc_get_profile", "mlbddc_subdomain_sizes", "mlbddc_assemble_load",
+    "mlbddc_interface_dofs",
 ]
 PROF_N = 8
-PROF_NAMES = ["update_fp64", "update_fp32", "panel", "diag", "negate"]
+PROF_NAMES = ["update_fp64", "update_fp32", "panel", "diag", "negate", "schur_mv", "precond_mv"]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_iter", C.c_int32), ("weights", C.c_int32),
                 ("use_graph", C.c_int32), ("panel_tiles", C.c_int32), ("device", C.c_int32),
                 ("panel_tiles_precond", C.c_int32), ("tune_table", C.c_char_p), ("lookahead", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class Mesh(C.Structure):
@@ -64,11 +73,12 @@ class Stats(C.Structure):
 
 class Profile(C.Structure):
     _fields_ = [("time_s", C.c_double * 8), ("flops", C.c_double * 8), ("launches", C.c_int64 * 8),
-                ("tiles", C.c_int64 * 8), ("job_time_s", C.c_double * 2), ("panel", C.c_int32 * 2)]
+                ("tiles", C.c_int64 * 8), ("job_time_s", C.c_double * 2), ("panel", C.c_int32 * 2),
+                ("bytes", C.c_double * 8)]
 
     def as_dict(self):
         d = {n: {"time_s": self.time_s[i], "flops": self.flops[i], "launches": self.launches[i],
-                 "tiles": self.tiles[i]} for i, n in enumerate(PROF_NAMES)}
+                 "tiles": self.tiles[i], "bytes": self.bytes[i]} for i, n in enumerate(PROF_NAMES)}
         d["jobs"] = {"K_time_s": self.job_time_s[0], "M_time_s": self.job_time_s[1],
                      "panel_K": self.panel[0], "panel_M": self.panel[1]}
         return d
@@ -105,7 +115,7 @@ def load():
     sig = {
         "mlbddc_status_string": (C.c_char_p, [I32]),
         "mlbddc_default_options": (None, [P(Options)]),
-        "mlbddc_create": (I32, [P(VP), P(Options), VP]),
+        "mlbddc_create": (I32, [P(VP), P(Options), P(Allocator), VP]),
         "mlbddc_setup": (I32, [VP, P(Mesh), P(Partition)]),
         "mlbddc_update_coefficients": (I32, [VP, VP]),
         "mlbddc_num_dofs": (I64, [VP]),
@@ -127,6 +137,8 @@ def load():
         "mlbddc_set_profiling": (I32, [VP, I32]),
         "mlbddc_get_profile": (I32, [VP, P(Profile)]),
         "mlbddc_subdomain_sizes": (I32, [VP, I32, P(I64)]),
+        "mlbddc_assemble_load": (I32, [P(Mesh), P(D), P(D), I64]),
+        "mlbddc_interface_dofs": (I32, [VP, P(I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

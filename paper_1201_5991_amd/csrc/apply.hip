@@ -523,6 +523,10 @@ __global__ void __launch_bounds__(256) k_dot_step(int nb, const double* __restri
   }
   if (s[S_DONE] != 0.0) return;
   if (step == DOT_ALPHA) {
+    if (!(tot > 0.0) || !(tot < INFINITY)) {  // breakdown: no step is taken, x keeps the last iterate
+      s[S_DONE] = 1.0;
+      return;
+    }
     s[S_ALPHA] = s[S_RZ] / tot;
     if (hist) hist[2 * (*it)] = s[S_ALPHA];
   } else if (step == DOT_BETA) {
@@ -664,15 +668,19 @@ inline unsigned grid_for(int64_t n, int block = 256) {
 
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles, const int64_t* tile_prefix,
-                    const TA* A, const TX* x, TY* y, double alpha, bool accumulate, TA* partials, int32_t max_out_tiles) {
+                    const TA* A, const TX* x, TY* y, double alpha, bool accumulate, TA* partials, int32_t max_out_tiles,
+                    hipEvent_t ev0, hipEvent_t ev1) {
   if (nitems <= 0 || total_tiles <= 0) return;
+  if (ev0) (void)hipEventRecord(ev0, st);
   if (total_tiles <= SMALL_MV_TILES) {  // coarse levels: one launch, no partial tiles
     hipLaunchKernelGGL((k_mv_rows<TA, TX, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d, A,
                        x, y, alpha, accumulate ? 1 : 0, 0, (const MvDesc*)nullptr, (const TX*)nullptr);
+    if (ev1) (void)hipEventRecord(ev1, st);
     return;
   }
   hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
                      partials);
+  if (ev1) (void)hipEventRecord(ev1, st);
   hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d,
                      partials, y, alpha, accumulate ? 1 : 0);
 }
@@ -794,7 +802,7 @@ void launch_scatter_idx(hipStream_t st, int64_t n, const int32_t* idx, const dou
   template void launch_tile_mv_sum<TA, TX, TY>(hipStream_t, int, const MvDesc*, int, const MvDesc*, int32_t, int32_t, \
                                                const TA*, const TX*, const TX*, TY*, double, bool);                   \
   template void launch_tile_mv<TA, TX, TY>(hipStream_t, int, const MvDesc*, int32_t, int64_t, const int64_t*, const TA*, \
-                                           const TX*, TY*, double, bool, TA*, int32_t);
+                                           const TX*, TY*, double, bool, TA*, int32_t, hipEvent_t, hipEvent_t);
 INST_MV(double, double, double)
 INST_MV(float, float, float)
 INST_MV(float, float, double)

@@ -9,8 +9,10 @@
 //                     + mu (dN_a/dx_j dN_b/dx_i + delta_ij grad N_a . grad N_b),
 //    with lam = E nu / ((1+nu)(1-2nu)), mu = E / (2(1+nu)), 2x2x2 Gauss.
 // Node order: counter-clockwise in 2D; bottom face then top face in 3D.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.hpp"
 
@@ -92,4 +94,29 @@ extern "C" mlbddc_status mlbddc_element_load(int32_t kind, double h, const doubl
     return MLBDDC_OK;
   }
   return MLBDDC_E_ARG;
+}
+
+// f = sum over elements of the element load vector, scattered to the free
+// DOFs (free nodes in increasing order, components innermost); DOFs of
+// Dirichlet nodes are dropped.
+extern "C" mlbddc_status mlbddc_assemble_load(const mlbddc_mesh* mesh, const double* elem_load, double* f,
+                                              int64_t n_free_dofs) {
+  if (!mesh || !elem_load || !f || !mesh->elem_nodes || !mesh->dirichlet_nodes || mesh->n_nodes <= 0 ||
+      mesh->n_elems < 0 || mesh->nodes_per_elem <= 0 || mesh->ndof_per_node <= 0)
+    return MLBDDC_E_ARG;
+  const int64_t nn = mesh->n_nodes;
+  const int nd = mesh->ndof_per_node, npe = mesh->nodes_per_elem;
+  std::vector<int64_t> free_of(nn);
+  int64_t nf = 0;
+  for (int64_t v = 0; v < nn; ++v) free_of[v] = mesh->dirichlet_nodes[v] ? -1 : nf++;
+  if (nf * nd != n_free_dofs) return MLBDDC_E_ARG;
+  std::fill(f, f + n_free_dofs, 0.0);
+  for (int64_t e = 0; e < mesh->n_elems; ++e)
+    for (int a = 0; a < npe; ++a) {
+      const int64_t v = mesh->elem_nodes[e * npe + a];
+      if (v < 0 || v >= nn) return MLBDDC_E_ARG;
+      if (free_of[v] < 0) continue;
+      for (int c = 0; c < nd; ++c) f[free_of[v] * nd + c] += elem_load[a * nd + c];
+    }
+  return MLBDDC_OK;
 }

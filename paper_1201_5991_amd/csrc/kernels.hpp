@@ -89,10 +89,12 @@ constexpr int64_t SMALL_MV_TILES = 64;
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv_sum(hipStream_t st, int mode, const MvDesc* d, int mode2, const MvDesc* d2, int32_t nitems,
                         int32_t max_out_tiles, const TA* A, const TX* x, const TX* x2, TY* y, double alpha, bool accumulate);
+// ev0 / ev1 (optional): recorded on `st` right before and after the product
+// kernel itself (k_mv_tiles or k_mv_rows), for kernel timing.
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles,
                     const int64_t* tile_prefix, const TA* A, const TX* x, TY* y, double alpha, bool accumulate,
-                    TA* partials, int32_t max_out_tiles);
+                    TA* partials, int32_t max_out_tiles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // out[i] = (w ? w[i] : 1) * in[idx[i]] (0 where idx < 0), converting types.
 template <typename TI, typename TO>
@@ -151,7 +153,8 @@ void launch_set_int(hipStream_t st, int* p, int v);
 void launch_pcg_update_p(hipStream_t st, int64_t n, double* p, const double* z, const double* s, const int64_t* ptr = nullptr,
                          const int64_t* list = nullptr, double* copies = nullptr);
 // Steps that the single-block finish of a PCG dot product does after it:
-// DOT_ALPHA alpha = rz / pq (slot S_PQ); DOT_CHECK the stopping
+// DOT_ALPHA alpha = rz / pq (slot S_PQ), or s[S_DONE] = 1 without a step when
+// p.q <= 0 or not finite (breakdown); DOT_CHECK the stopping
 // test, s[S_DONE] = 1 (sticky) when p.q <= 0 or not finite or r.r < rtol2 g.g
 // (slot S_RR); DOT_BETA beta = rznew / rz, rz = rznew, ++it (slot S_RZNEW).
 enum DotStep { DOT_ALPHA = 1, DOT_CHECK = 2, DOT_BETA = 3 };

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <array>
@@ -233,6 +234,31 @@ struct Handle {
     err.column = col;
     return st;
   }
+  // Device memory comes from the caller's allocator when one was given to
+  // mlbddc_create (e.g. a framework's caching allocator), else from hipMalloc.
+  mlbddc_allocator ext_alloc{};
+  bool has_ext_alloc = false;
+  void* raw_alloc(size_t bytes) {
+    if (has_ext_alloc) {
+      void* q = ext_alloc.alloc(bytes, ext_alloc.ctx);
+      if ((uintptr_t)q & 255) {  // the kernels assume 256-byte alignment
+        ext_alloc.free(q, ext_alloc.ctx);
+        return nullptr;
+      }
+      return q;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return q;
+  }
+  void raw_free(void* q) {
+    if (!q) return;
+    if (has_ext_alloc) ext_alloc.free(q, ext_alloc.ctx);
+    else (void)hipFree(q);
+  }
   template <typename T>
   mlbddc_status dalloc(T** p, int64_t n) {
     *p = nullptr;
@@ -244,23 +270,22 @@ struct Handle {
       q = it->second;
       pool.erase(it);
     } else {
-      hipError_t e = hipMalloc(&q, bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
+      q = raw_alloc(bytes);
+      if (!q) {
         trim_pool();  // retry once without the previous set-up's blocks
-        e = hipMalloc(&q, bytes);
-        if (e != hipSuccess) {
-          (void)hipGetLastError();
-          return fail(MLBDDC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
+        q = raw_alloc(bytes);
+        if (!q) return fail(MLBDDC_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
       }
     }
     allocs.push_back({q, bytes});
     *p = (T*)q;
     return MLBDDC_OK;
   }
+  // Pool blocks are never in use by queued work: set-up moves the previous
+  // set-up's blocks to the pool only after synchronizing the library stream,
+  // and every other library stream joins that stream before its work ends.
   void trim_pool() {
-    for (auto& kv : pool) (void)hipFree(kv.second);
+    for (auto& kv : pool) raw_free(kv.second);
     pool.clear();
   }
   // Host-to-device copies of set-up data: staged in pinned host memory kept
@@ -342,7 +367,7 @@ struct Handle {
     if (keep) {
       for (auto& a : allocs) pool.emplace(a.second, a.first);
     } else {
-      for (auto& a : allocs) (void)hipFree(a.first);
+      for (auto& a : allocs) raw_free(a.first);
       trim_pool();
     }
     allocs.clear();
@@ -371,9 +396,21 @@ struct Handle {
   mlbddc_status build_mv(MvSet& s, int mode, std::vector<MvDesc> descs);
   mlbddc_status build_trsv(LevelDev& D);
   void run_trsv(LevelDev& D, bool transposed);
+  // cls >= 0: time the product kernel as profile class cls (algorithmic bytes `bytes`)
   template <typename TA, typename TX, typename TY>
   void run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial,
-              hipStream_t on = nullptr);
+              hipStream_t on = nullptr, int cls = -1, double bytes = 0.0);
+  // Timing of the level-1 tile products while profiling (outside stream capture).
+  struct MvTiming {
+    int cls;
+    hipEvent_t e0, e1;
+    double bytes;
+  };
+  std::vector<MvTiming> mv_pending;
+  std::vector<hipEvent_t> mv_spare;
+  double alg_bytes_S = 0.0, alg_bytes_G = 0.0;  // lower triangles of the S_i / G_i, bytes
+  void mv_timing(int cls, double bytes, hipStream_t on, hipEvent_t* e0, hipEvent_t* e1);
+  mlbddc_status collect_mv_timing();
   // A PCG dot product formed by the last kernel of a product: its scalar slot,
   // the step after it (DotStep) and the squared tolerance of the stopping test.
   struct DotFinish {
@@ -416,9 +453,56 @@ mlbddc_status Handle::build_mv(MvSet& s, int mode, std::vector<MvDesc> descs) {
 }
 
 template <typename TA, typename TX, typename TY>
-void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial, hipStream_t on) {
-  launch_tile_mv<TA, TX, TY>(on ? on : stream, s.mode, s.d, (int32_t)s.h.size(), s.tiles, s.d_prefix, (const TA*)J.buf, x, y, alpha,
-                             acc, (TA*)partial, s.max_out);
+void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bool acc, void* partial, hipStream_t on,
+                    int cls, double bytes) {
+  hipStream_t st = on ? on : stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (cls >= 0 && prof) mv_timing(cls, bytes, st, &e0, &e1);
+  launch_tile_mv<TA, TX, TY>(st, s.mode, s.d, (int32_t)s.h.size(), s.tiles, s.d_prefix, (const TA*)J.buf, x, y, alpha, acc,
+                             (TA*)partial, s.max_out, e0, e1);
+}
+
+void Handle::mv_timing(int cls, double bytes, hipStream_t on, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(on, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (mv_pending.size() >= 4096) (void)collect_mv_timing();
+  hipEvent_t ev[2];
+  for (hipEvent_t& e : ev) {
+    if (!mv_spare.empty()) {
+      e = mv_spare.back();
+      mv_spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+  }
+  mv_pending.push_back({cls, ev[0], ev[1], bytes});
+  *e0 = ev[0];
+  *e1 = ev[1];
+}
+
+mlbddc_status Handle::collect_mv_timing() {
+  mlbddc_status st = MLBDDC_OK;
+  for (const MvTiming& t : mv_pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.e0, t.e1);
+    if (e != hipSuccess) {
+      if (!st) st = herr("product timing", e);
+    } else {
+      pdata.time_s[t.cls] += 1e-3 * ms;
+      pdata.launches[t.cls] += 1;
+      pdata.bytes[t.cls] += t.bytes;
+    }
+    mv_spare.push_back(t.e0);
+    mv_spare.push_back(t.e1);
+  }
+  mv_pending.clear();
+  return st;
 }
 
 // Lists of the nonzero tiles of every level-1 factor (from the tile
@@ -1173,6 +1257,11 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   if (h_edof && !edof_job.valid()) start_edof();
 
 
+  // algorithmic bytes of the level-1 products (stored lower triangles), for profiling
+  alg_bytes_S = alg_bytes_G = 0.0;
+  for (const SubPlan& S : plan.levels[0].subs) alg_bytes_S += 0.5 * (double)S.nG * (double)(S.nG + 1);
+  alg_bytes_G = alg_bytes_S * (!lev.empty() && lev[0].mfp32 ? 4.0 : 8.0);
+  alg_bytes_S *= 8.0;
   // PCG vectors
   const int64_t nif = (int64_t)plan.levels[0].iface_dofs.size();
   const int64_t ndofs = plan.levels[0].n_dofs;
@@ -1567,8 +1656,12 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
     }
     HIPCHK(hipEventRecord(ev_gfork, stream));
     HIPCHK(hipStreamWaitEvent(gstream, ev_gfork, 0));
-    if (D.mfp32) run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial_g, gstream);
-    else run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial_g, gstream);
+    const int gcls = li == 0 ? MLBDDC_PROF_PRECOND_MV : -1;
+    if (D.mfp32)
+      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial_g, gstream, gcls, alg_bytes_G);
+    else
+      run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial_g, gstream, gcls,
+                                     alg_bytes_G);
     HIPCHK(hipEventRecord(ev_gjoin, gstream));
   }
   launch_seg_reduce<double>(stream, P.n_coarse, D.d_cptr, D.d_clist, nullptr, D.rcl, D.rC, 0.0);
@@ -1583,7 +1676,9 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
                                               false);
     } else {
       if (g_side) HIPCHK(hipStreamWaitEvent(stream, ev_gjoin, 0));
-      else run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial);
+      else
+        run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial, nullptr,
+                                    li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
       run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
     }
     if (ds)  // with rhat.zhat and its scalar step
@@ -1599,7 +1694,9 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
                                                  (const double*)D.zcl, (double*)D.yl, 1.0, false);
     } else {
       if (g_side) HIPCHK(hipStreamWaitEvent(stream, ev_gjoin, 0));
-      else run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial);
+      else
+        run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial, nullptr,
+                                       li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
       run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
     }
     if (ds)
@@ -1657,7 +1754,7 @@ mlbddc_status Handle::apply_full(int li, const double* r, double* z) {
 mlbddc_status Handle::schur(const double* x, double* y, const DotFinish* ds, bool x_copied) {
   LevelDev& D = lev[0];
   if (!x_copied) launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, x, D.gd);
-  run_mv<double, double, double>(D.mvS, D.K, D.gd, D.gd2, 1.0, false, D.partial);
+  run_mv<double, double, double>(D.mvS, D.K, D.gd, D.gd2, 1.0, false, D.partial, nullptr, MLBDDC_PROF_SCHUR_MV, alg_bytes_S);
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
   if (ds)  // with x.y and its scalar step
     launch_seg_reduce_dot<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd2, y, x, d_dotp, d_s, ds->slot, ds->step,
@@ -1847,11 +1944,12 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
   launch_fill(stream, 1, 0.0, d_s + S_DONE);
   HIPCHK(hipEventSynchronize(ev_snap[0]));
   const double gnorm = std::sqrt(h_s[S_GG]);
-  double rel = gnorm > 0 ? std::sqrt(h_s[S_RR]) / gnorm : 0.0;
+  // a non-finite condensed right-hand side (or initial residual) is a breakdown before the first step
+  bool breakdown = !std::isfinite(gnorm) || !std::isfinite(h_s[S_RR]);
+  double rel = breakdown ? NAN : gnorm > 0 ? std::sqrt(h_s[S_RR]) / gnorm : 0.0;
   int it = 0;
-  bool conv = rel < opt.rtol;
-  bool breakdown = false;
-  if (!conv) {
+  bool conv = !breakdown && rel < opt.rtol;
+  if (!conv && !breakdown) {
     // Iteration k+1 is normally queued before the host reads iteration k's
     // scalars (snapshot k&1), so the device does not wait for the host; once
     // the device flags convergence or breakdown a queued iteration changes
@@ -1909,9 +2007,11 @@ mlbddc_status Handle::solve_on_stream(const double* f, double* u, const double* 
   if (it > 0) HIPCHK(hipMemcpyAsync(hist.data(), d_hist, sizeof(double) * 2 * it, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
   if (stt) {
+    // a breakdown iteration records no step: its alpha is not part of the history
+    const int nal = breakdown ? it - 1 : it;
     std::vector<double> al, be;
-    for (int j = 0; j < it; ++j) al.push_back(hist[2 * j]);
-    for (int j = 0; j + 1 < it; ++j) be.push_back(hist[2 * j + 1]);
+    for (int j = 0; j < nal; ++j) al.push_back(hist[2 * j]);
+    for (int j = 0; j + 1 < nal; ++j) be.push_back(hist[2 * j + 1]);
     double lo, hi;
     lanczos(al, be, lo, hi);
     stt->iterations = it;
@@ -1971,9 +2071,14 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->lookahead = 0;
 }
 
-mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stream) {
+mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream) {
   if (!out) return MLBDDC_E_ARG;
   *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    g_create_error.status = MLBDDC_E_ARG;
+    g_create_error.message = "allocator without alloc or free function";
+    return MLBDDC_E_ARG;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -2012,6 +2117,10 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, void* stre
     h->h.opt.tune_table = nullptr;  // the path is not kept
   }
   h->h.stream = (hipStream_t)stream;
+  if (alloc) {
+    h->h.ext_alloc = *alloc;
+    h->h.has_ext_alloc = true;
+  }
   *out = h;
   return MLBDDC_OK;
 }
@@ -2043,6 +2152,14 @@ int64_t mlbddc_coarse_size(mlbddc_t h, int32_t level) {
 int64_t mlbddc_num_subdomains(mlbddc_t h, int32_t level) {
   if (!h || !h->h.planned || level < 1 || level > (int32_t)h->h.plan.levels.size()) return -1;
   return h->h.plan.levels[level - 1].n_sub;
+}
+
+mlbddc_status mlbddc_interface_dofs(mlbddc_t h, int64_t* out) {
+  if (!h || !out) return MLBDDC_E_ARG;
+  if (!h->h.planned) return h->h.fail(MLBDDC_E_STATE, "interface_dofs before setup");
+  const auto& v = h->h.plan.levels[0].iface_dofs;
+  for (size_t i = 0; i < v.size(); ++i) out[i] = v[i];
+  return MLBDDC_OK;
 }
 
 mlbddc_status mlbddc_subdomain_sizes(mlbddc_t h, int32_t level, int64_t* out) {
@@ -2126,6 +2243,7 @@ mlbddc_status mlbddc_get_coarse_matrix(mlbddc_t h, int32_t level, double* out) {
 
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable) {
   if (!h) return MLBDDC_E_ARG;
+  if (mlbddc_status st = h->h.collect_mv_timing()) return st;
   h->h.prof = enable != 0;
   int p0 = h->h.pdata.panel[0], p1 = h->h.pdata.panel[1];
   h->h.pdata = mlbddc_profile{};
@@ -2136,13 +2254,17 @@ mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable) {
 
 mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out) {
   if (!h || !out) return MLBDDC_E_ARG;
+  if (mlbddc_status st = h->h.collect_mv_timing()) return st;
   *out = h->h.pdata;
   return MLBDDC_OK;
 }
 
 mlbddc_status mlbddc_destroy(mlbddc_t h) {
   if (!h) return MLBDDC_OK;
+  // every library stream drains before its blocks go back to the allocator
   (void)hipStreamSynchronize(h->h.stream);
+  for (hipStream_t s : {h->h.cap, h->h.fstream, h->h.gstream, h->h.ustream})
+    if (s) (void)hipStreamSynchronize(s);
   h->h.free_all(false);
   if (h->h.cap) {
     (void)hipStreamSynchronize(h->h.cap);
@@ -2173,6 +2295,8 @@ mlbddc_status mlbddc_destroy(mlbddc_t h) {
   if (h->h.ev_b) (void)hipEventDestroy(h->h.ev_b);
   if (h->h.ev_in) (void)hipEventDestroy(h->h.ev_in);
   if (h->h.ev_out) (void)hipEventDestroy(h->h.ev_out);
+  (void)h->h.collect_mv_timing();
+  for (hipEvent_t e : h->h.mv_spare) (void)hipEventDestroy(e);
   delete h;
   return MLBDDC_OK;
 }

@@ -11,8 +11,10 @@ element sensitivities in a library kernel.
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -48,6 +50,37 @@ def element_load(kind: int, h: float, force: Sequence[float]) -> np.ndarray:
     out = np.zeros(n)
     L.check(L.load().mlbddc_element_load(kind, h, _ptr(f, C.c_double), _ptr(out, C.c_double)))
     return out
+
+
+def _torch_allocator(device: torch.device, stream) -> "L.Allocator":
+    """The library's device allocator: torch's caching allocator on the
+    handle's stream (torch owns every device block the library uses)."""
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:  # out of memory: the library reports E_NOMEM
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = L.Allocator(L.ALLOC_FN(alloc), L.FREE_FN(free), None)
+    a._keep = (alloc, free)
+    return a
+
+
+# Handles still alive at interpreter exit are destroyed while torch is still usable.
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live():
+    for s in list(_LIVE):
+        try:
+            s.destroy()
+        except Exception:
+            pass
 
 
 class Problem:
@@ -86,18 +119,13 @@ class Problem:
         p = L.Partition(self.n_levels, _ptr(self.elem_to_sub, C.c_int32), parr, self.constraints)
         return m, p, parr
 
-    def element_dofs(self) -> np.ndarray:
-        fn = self.node_to_free[self.elem_nodes]
-        d = fn[:, :, None] * self.ndof + np.arange(self.ndof)[None, None, :]
-        d[fn < 0] = -1
-        return d.reshape(self.n_elems, -1)
-
     def load_vector(self) -> np.ndarray:
-        """Consistent load of the constant source / body force on the free DOFs."""
+        """Consistent load of the constant source / body force on the free DOFs
+        (assembled by the library's host routine)."""
         fe = element_load(self.kind, self.h, self.body_force)
-        ed = self.element_dofs()
         f = np.zeros(self.n_dofs)
-        np.add.at(f, ed[ed >= 0], np.broadcast_to(fe, ed.shape)[ed >= 0])
+        m, p, keep = self.structs()
+        L.check(L.load().mlbddc_assemble_load(C.byref(m), _ptr(fe, C.c_double), _ptr(f, C.c_double), self.n_dofs))
         return f
 
     def counts(self):
@@ -135,16 +163,22 @@ class Solver:
         self.opt = opt
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
+        self._alloc = _torch_allocator(self.device, self.stream)
         h = C.c_void_p()
-        L.check(lib.mlbddc_create(C.byref(h), C.byref(opt), C.c_void_p(self.stream.cuda_stream)))
+        L.check(lib.mlbddc_create(C.byref(h), C.byref(opt), C.byref(self._alloc), C.c_void_p(self.stream.cuda_stream)))
         self.h = h
+        _LIVE.add(self)
         self.problem: Optional[Problem] = None
+
+    def destroy(self):
+        """Release the handle; its device blocks go back to torch's caching allocator."""
+        if getattr(self, "h", None):
+            self.lib.mlbddc_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
-            if getattr(self, "h", None):
-                self.lib.mlbddc_destroy(self.h)
-                self.h = None
+            self.destroy()
         except Exception:
             pass
 
@@ -186,6 +220,9 @@ class Solver:
     def apply_into(self, r: torch.Tensor, z: torch.Tensor):
         self._chk(self.lib.mlbddc_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
 
+    def apply_schur_into(self, x: torch.Tensor, y: torch.Tensor):
+        self._chk(self.lib.mlbddc_apply_schur(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+
     def apply_schur(self, x) -> torch.Tensor:
         x = self._vec(x, self.n_iface)
         y = torch.empty_like(x)
@@ -206,7 +243,9 @@ class Solver:
         status = self.lib.mlbddc_solve(self.h, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), u0p, C.byref(st))
         if raise_on_error:
             self._chk(status)
-        return u, st.as_dict()
+        d = st.as_dict()
+        d["status"] = L.STATUS.get(status, str(status))
+        return u, d
 
     def element_energy(self, a, b) -> torch.Tensor:
         a = self._vec(a, self.n_dofs)
@@ -214,6 +253,12 @@ class Solver:
         out = torch.empty(self.problem.n_elems, dtype=torch.float64, device=self.device)
         self._chk(self.lib.mlbddc_element_energy(self.h, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
                                                  C.c_void_p(out.data_ptr())))
+        return out
+
+    def interface_dofs(self) -> np.ndarray:
+        """Free-DOF index of every level-1 interface entry (increasing)."""
+        out = np.zeros(self.n_iface, dtype=np.int64)
+        self._chk(self.lib.mlbddc_interface_dofs(self.h, _ptr(out, C.c_int64)))
         return out
 
     def subdomain_sizes(self, level: int) -> np.ndarray:

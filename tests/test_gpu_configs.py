@@ -1,0 +1,132 @@
+"""Full-size parity of the benchmark workloads against stored FP64 oracle
+values (runs on an MI355X).
+
+tests/golden/<case>.json were written by tests/golden/make_golden.py, which
+calls only the oracle.  For every workload at its full size:
+
+* FP64: M r, S^ r and g^ agree with the oracle to relative 1e-10 at 256
+  seeded sample positions, in norm, and in their dot products with four
+  seeded N(0,1) vectors (which see every entry); the PCG iterate after a
+  fixed 10 iterations agrees likewise (the iterates are unique in exact
+  arithmetic; the solver stops with E_NOT_CONVERGED and returns it); PCG
+  to 1e-8 takes the oracle's iteration count +-1 and its solution agrees
+  with the oracle's within the conditioning bound; lambda_min >= 1 and
+  lambda_max matches the oracle's Lanczos estimate;
+* mixed precision: the same 1e-8 residual with at most 15 % more
+  iterations than the oracle, the apply error against the FP64 oracle
+  printed and bounded.
+
+Workloads: 48^3 (64 subdomains of 12^3) at 2 and 3 levels; 96^3 with 1728
+subdomains of 8^3 and log-uniform moduli at 3 levels (4x4x4 level-2 groups)
+and at 4 levels (1728 / 216 / 27); 80^3 cut by seeded random planes into 512
+uneven boxes of 4..16 elements per side, 3 levels.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import config
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+CASES = {
+    "elasticity48_L2": lambda: config(2, levels=2),
+    "elasticity48_L3": lambda: config(2, levels=3),
+    "elasticity96_L3": lambda: config(3, levels=3),
+    "elasticity96_L4": lambda: config(3, levels=4),
+    "elasticity80_uneven_L3": lambda: config(4),
+}
+RTOL64 = 1e-10
+_problems = {}
+
+
+def _load(name):
+    path = os.path.join(HERE, "golden", f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return json.load(open(path))
+
+
+def _problem(name):
+    from paper_1201_5991_amd import Problem
+    if name not in _problems:
+        _problems.clear()          # one full-size problem on the host at a time
+        prob = Problem(CASES[name]())
+        _problems[name] = (prob, torch.tensor(prob.load_vector(), device="cuda"))
+    return _problems[name]
+
+
+def _check_vec(v, rec, idx, seeds, tol, what):
+    """Samples (max-abs against the largest sampled entry), norm and seeded
+    projections of v against the oracle's record."""
+    v = np.asarray(v)
+    ref = np.asarray(rec["samples"])
+    err_s = np.abs(v[idx] - ref).max() / np.abs(ref).max()
+    err_n = abs(np.linalg.norm(v) - rec["norm"]) / rec["norm"]
+    err_p = max(abs(float(np.random.default_rng(sd).standard_normal(len(v)) @ v) - p) / (np.sqrt(len(v)) * rec["norm"])
+                for sd, p in zip(seeds, rec["proj"]))
+    print(f"  {what}: samples {err_s:.2e}, norm {err_n:.2e}, projections {err_p:.2e}", flush=True)
+    assert err_s < tol and err_n < tol and err_p < tol, what
+    return max(err_s, err_n, err_p)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_config_fp64(name):
+    from paper_1201_5991_amd import Solver
+    print(f"[config] {name} fp64", flush=True)
+    gold = _load(name)
+    prob, f = _problem(name)
+    s = Solver(use_graph=True).setup(prob)
+    L = gold["levels"]
+    assert s.n_iface == gold["n_iface"] and s.n_dofs == gold["n_dofs"]
+    assert [s.num_subdomains(l + 1) for l in range(L - 1)] == gold["subdomains"]
+    assert [s.coarse_size(l + 1) for l in range(L - 1)] == gold["coarse_sizes"]
+    idx, seeds = np.asarray(gold["sample_idx"]), gold["proj_seeds"]
+    r = torch.tensor(np.random.default_rng(gold["r_seed"]).standard_normal(gold["n_iface"]), device="cuda")
+    for key, vec in (("apply", s.apply(r)), ("schur", s.apply_schur(r)), ("condense", s.condense(f))):
+        _check_vec(vec.cpu().numpy(), gold[key], idx, seeds, RTOL64, key)
+    iface = np.asarray(s.interface_dofs())
+    # iterate after a fixed number of iterations
+    fixed = Solver(use_graph=True, max_iter=gold["pcg_fixed"]["iterations"]).setup(prob)
+    u, st = fixed.solve(f, raise_on_error=False)
+    assert st["status"] == "E_NOT_CONVERGED" and st["iterations"] == gold["pcg_fixed"]["iterations"]
+    _check_vec(u.cpu().numpy()[iface], gold["pcg_fixed"]["u_hat"], idx, seeds, RTOL64,
+               f"iterate after {st['iterations']} iterations")
+    fixed.destroy()
+    # PCG to 1e-8
+    u, st = s.solve(f)
+    g = gold["pcg"]
+    print(f"  iterations {st['iterations']} (oracle {g['iterations']}), lambda [{st['lambda_min']:.6f}, "
+          f"{st['lambda_max']:.4f}] (oracle [{g['lambda_min']:.6f}, {g['lambda_max']:.4f}])", flush=True)
+    assert st["converged"] == 1 and st["rel_res"] < 1e-8
+    assert abs(st["iterations"] - g["iterations"]) <= 1
+    assert st["lambda_min"] > 1 - 1e-6
+    assert abs(st["lambda_max"] - g["lambda_max"]) < 1e-3 * g["lambda_max"]
+    kappa = g["lambda_max"] / g["lambda_min"]
+    _check_vec(u.cpu().numpy()[iface], g["u_hat"], idx, seeds, 10 * kappa * 1e-8, "solution")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_config_mixed(name):
+    from paper_1201_5991_amd import Solver
+    print(f"[config] {name} mixed", flush=True)
+    gold = _load(name)
+    prob, f = _problem(name)
+    s = Solver(precision="mixed", use_graph=True).setup(prob)
+    idx, seeds = np.asarray(gold["sample_idx"]), gold["proj_seeds"]
+    r = torch.tensor(np.random.default_rng(gold["r_seed"]).standard_normal(gold["n_iface"]), device="cuda")
+    err = _check_vec(s.apply(r).cpu().numpy(), gold["apply"], idx, seeds, 1e-4, "mixed apply vs FP64 oracle")
+    print(f"  mixed apply error vs FP64 oracle: {err:.2e}", flush=True)
+    _check_vec(s.apply_schur(r).cpu().numpy(), gold["schur"], idx, seeds, RTOL64, "schur (FP64 in mixed mode)")
+    u, st = s.solve(f)
+    g = gold["pcg"]
+    print(f"  mixed iterations {st['iterations']} (oracle {g['iterations']})", flush=True)
+    assert st["converged"] == 1 and st["rel_res"] < 1e-8
+    assert st["iterations"] <= int(np.ceil(1.15 * g["iterations"]))   # +15 %, rounded up
+    kappa = g["lambda_max"] / g["lambda_min"]
+    _check_vec(u.cpu().numpy()[np.asarray(s.interface_dofs())], g["u_hat"], idx, seeds, 10 * kappa * 1e-8, "solution")

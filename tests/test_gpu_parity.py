@@ -39,7 +39,17 @@ CASES = {
     "elast_3x3x3_of_4_hetero": lambda: _cube(3, 4, young=10 ** (3 * np.random.default_rng(7).random(12 ** 3))),
     "elast_4x4x4_of_3_L3": lambda: _cube(4, 3, groups=[(2, 2, 2)],
                                          young=10 ** (2 * np.random.default_rng(8).random(12 ** 3))),
+    # 4x4x4 groups: level-2 interiors of 837 DOFs (14 tiles) and interfaces of
+    # 507 (8 tiles), so the level-2 products take the multi-tile path
+    "elast_8x8x8_of_2_L3_g4": lambda: _cube(8, 2, groups=[(4, 4, 4)],
+                                            young=10 ** (2 * np.random.default_rng(8).random(16 ** 3))),
 }
+
+
+def _mixed_its_bound(ref_its):
+    """At most 15 % more iterations than the FP64 oracle, rounded up to a
+    whole iteration (an iteration count below 7 allows one more)."""
+    return int(np.ceil(1.15 * ref_its))
 
 _cache = {}
 
@@ -122,13 +132,13 @@ def test_mixed_precision(name):
     z = s.apply(torch.tensor(r, device="cuda")).cpu().numpy()
     err = _rel(z, b.apply(r))
     _say(f"  mixed apply rel error vs FP64 oracle: {err:.3e}")
-    assert err < 1e-3
+    assert err < 1e-4
     _, f = fem.assemble_global(w)
     u, st = s.solve(torch.tensor(f, device="cuda"))
     ref = pcg(b.schur_apply, b.condense(f), b.apply, tol=1e-8)
     _say(f"  mixed its {st['iterations']} vs oracle {ref.iterations}")
     assert st["converged"] == 1
-    assert st["iterations"] <= int(np.ceil(1.15 * ref.iterations)) + 1
+    assert st["iterations"] <= _mixed_its_bound(ref.iterations)
     uh = u.cpu().numpy()[b.level1.iface_dofs]
     g = b.condense(f)
     assert np.linalg.norm(g - b.schur_apply(uh)) < 1e-7 * np.linalg.norm(g)
@@ -217,7 +227,7 @@ def test_uneven_boxes_three_levels():
     assert abs(st["iterations"] - ref.iterations) <= 1
     sm = Solver(precision="mixed").setup(Problem(w))
     um, stm = sm.solve(torch.tensor(f, device="cuda"))
-    assert stm["converged"] == 1 and stm["iterations"] <= int(np.ceil(1.15 * ref.iterations)) + 1
+    assert stm["converged"] == 1 and stm["iterations"] <= _mixed_its_bound(ref.iterations)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

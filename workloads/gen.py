@@ -211,7 +211,7 @@ def uniform_cuts(n: int, parts: int) -> np.ndarray:
 CONFIG_NAMES = {
     1: "poisson2d_32x32_4x4sub_L2",
     2: "elasticity3d_48cube_64sub",
-    3: "elasticity3d_96cube_1728sub_L3",
+    3: "elasticity3d_96cube_1728sub",
     4: "elasticity3d_80cube_512uneven_L3",
     5: "elasticity3d_64cube_512sub_L3_grad",
 }
@@ -223,7 +223,8 @@ def config(k: int, levels: int | None = None, seed: int = 0) -> Workload:
     1. 2D Poisson -Lap u = 1, 32x32 Q1, Dirichlet everywhere, 4x4 subdomains, 2 levels, corners.
     2. 3D elasticity 48^3 hex, E=1, nu=0.3, b=(0,0,-1), x=0 clamped, 4^3 subdomains of 12^3;
        2 levels, or 3 levels with 2x2x2 groups (``levels=3``, the default here).
-    3. 3D elasticity 96^3, 12^3 subdomains of 8^3, 3 levels (4x4x4 groups), E = 10^(3U).
+    3. 3D elasticity 96^3, 12^3 subdomains of 8^3, E = 10^(3U); 3 levels (4x4x4 groups, the
+       default here), 4 levels (2x2x2 groups twice: 1728 / 216 / 27) or 2 levels.
     4. 3D elasticity 80^3 cut by seeded random planes into 8^3 uneven boxes, 3 levels (2x2x2).
     5. 3D elasticity 64^3, 8^3 subdomains of 8^3, 3 levels (2x2x2), E = exp(theta), theta~N(0, 0.5^2).
     """
@@ -243,8 +244,11 @@ def config(k: int, levels: int | None = None, seed: int = 0) -> Workload:
         rng = np.random.default_rng(seed)
         young = 10.0 ** (3.0 * rng.random(n))
         lv = 3 if levels is None else levels
-        groups = {2: [], 3: [(4, 4, 4)], 4: [(2, 2, 2), (3, 3, 3)]}[lv]
-        return box_workload(name, "elasticity", (96,) * 3, [uniform_cuts(96, 12)] * 3,
+        if lv not in (2, 3, 4):
+            raise ValueError("config 3 runs with 2, 3 or 4 levels")
+        # 3 levels: 1728 / 27 / 1 (4x4x4 groups); 4 levels: 1728 / 216 / 27 / 1 (2x2x2 twice)
+        groups = {2: [], 3: [(4, 4, 4)], 4: [(2, 2, 2), (2, 2, 2)]}[lv]
+        return box_workload(f"{name}_L{lv}", "elasticity", (96,) * 3, [uniform_cuts(96, 12)] * 3,
                             groups=groups, young=young, seed=seed)
     if k == 4:
         cuts = random_cuts(seed)
