@@ -52,6 +52,7 @@ class MultilevelBDDC:
         self.node_to_free, self.n_free = node_to_free, n_free
         blocks = level_one_blocks(w, Ke0, node_to_free)
         levels: List[Level] = [Level(w.dim, w.ndof, n_free // w.ndof, blocks, constraints[0], weights, structure_only)]
+        del blocks  # the element matrices (E_e K_e^0 per element) are no longer needed
         for l in range(2, L):
             prev = levels[-1]
             parent = np.asarray(w.sub_to_parent[l - 2])

@@ -199,7 +199,8 @@ class Level:
             Ki = self.K[i]
             I, G = self.loc_I[i], self.loc_G[i]
             KII = Ki[I][:, I].tocsc()
-            self.KII_lu.append(spla.splu(KII) if len(I) else None)
+            # symmetric pattern: minimum degree on A^T + A keeps the fill lowest
+            self.KII_lu.append(spla.splu(KII, permc_spec="MMD_AT_PLUS_A") if len(I) else None)
             self.KIG.append(Ki[I][:, G].tocsr())
             self.KGG.append(Ki[G][:, G].tocsr())
 
@@ -209,13 +210,16 @@ class Level:
             Ki, Ci = self.K[i], self.C[i]
             nc = Ci.shape[0]
             A = sp.bmat([[Ki, Ci.T], [Ci, None]], format="csc")
-            lu = spla.splu(A)
+            # the local node order is already banded; keeping it (with the
+            # constraint rows last) gives less fill than a column ordering
+            # here, and the factors of every subdomain are kept for the applies
+            lu = spla.splu(A, permc_spec="NATURAL")
             rhs = np.zeros((Ki.shape[0] + nc, nc))
             rhs[Ki.shape[0]:, :] = np.eye(nc)
             sol = lu.solve(rhs) if nc else np.zeros((Ki.shape[0], 0))
             self.saddle_lu.append(lu)
-            self.Psi.append(sol[:Ki.shape[0], :])
-            self.Lam.append(sol[Ki.shape[0]:, :])
+            self.Psi.append(np.ascontiguousarray(sol[:Ki.shape[0], :]))
+            self.Lam.append(np.ascontiguousarray(sol[Ki.shape[0]:, :]))
             self.KC_loc.append(-self.Lam[-1])
 
         # --- global coarse matrix K_C = sum R_Ci^T K_Ci R_Ci
