@@ -3,7 +3,10 @@ structure and the schedule in which groups of one dissection height advance
 together.  A small C++ program built from the library's planner runs the task
 list of one subdomain in launch order on a random SPD matrix with the
 subdomain's element pattern and compares with a dense partial Cholesky of the
-interior columns (it also checks that no launch writes a tile twice)."""
+interior columns (it also checks that no launch writes a tile twice).  The
+program is built twice: optimized, and with AddressSanitizer and
+UndefinedBehaviorSanitizer, which abort on any memory or undefined-behaviour
+error in the planner."""
 
 import os
 import shutil
@@ -20,14 +23,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1201_5991_amd", "csrc")
 
 
-@pytest.fixture(scope="module")
-def checker(tmp_path_factory):
+# Host-only builds of the planner: optimized, and with AddressSanitizer and
+# UndefinedBehaviorSanitizer (any report aborts the program).
+BUILDS = {
+    "O2": ["-O2"],
+    "asan_ubsan": ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
+}
+SAN_ENV = {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=1", "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1"}
+
+
+@pytest.fixture(scope="module", params=list(BUILDS))
+def checker(request, tmp_path_factory):
     cxx = shutil.which("g++") or shutil.which("clang++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
     d = tmp_path_factory.mktemp("sched")
     exe = str(d / "schedule_check")
-    cmd = [cxx, "-O2", "-std=c++17", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+    cmd = [cxx, *BUILDS[request.param], "-std=c++17", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
            os.path.join(ROOT, "tests", "schedule_check.cpp"), os.path.join(CSRC, "plan.cpp"), "-o", exe, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
@@ -49,7 +61,8 @@ def checker(tmp_path_factory):
 @pytest.mark.parametrize("sub,panel", [(13, 2), (0, 4), (4, 3)])
 def test_schedule_reproduces_dense_cholesky(checker, sub, panel):
     exe, d = checker
-    r = subprocess.run([exe, d, str(sub), str(panel)], capture_output=True, text=True, timeout=300)
+    r = subprocess.run([exe, d, str(sub), str(panel)], capture_output=True, text=True, timeout=600,
+                       env={**os.environ, **SAN_ENV})
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     # the centre subdomain is cut by the dissection (several groups)
