@@ -71,6 +71,9 @@ typedef struct {
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */
+  int32_t side_stream; /* 1 (default): in mixed precision the level-1 local operator product G_i r_i runs
+                          on a second stream beside the coarse levels of the apply.  0: one stream.
+                          Both give bitwise the same results */
 } mlbddc_options;
 
 typedef struct {

@@ -39,7 +39,10 @@ class MultilevelBDDC:
     """
 
     def __init__(self, w, n_levels: Optional[int] = None, constraints: Optional[Sequence[str]] = None,
-                 weights: str = "stiffness", structure_only: bool = False):
+                 weights: str = "stiffness", structure_only: bool = False, level1: Optional[Level] = None):
+        """``level1``: a level 1 already built for the same mesh, partition,
+        moduli, level-1 constraints and weights (it depends on nothing else),
+        reused instead of built again."""
         L = w.n_levels if n_levels is None else n_levels
         if L < 2 or L - 2 > len(w.sub_to_parent):
             raise ValueError("not enough level groupings for the requested number of levels")
@@ -50,9 +53,11 @@ class MultilevelBDDC:
         self.Ke0 = Ke0
         node_to_free, n_free = dof_numbering(w)
         self.node_to_free, self.n_free = node_to_free, n_free
-        blocks = level_one_blocks(w, Ke0, node_to_free)
-        levels: List[Level] = [Level(w.dim, w.ndof, n_free // w.ndof, blocks, constraints[0], weights, structure_only)]
-        del blocks  # the element matrices (E_e K_e^0 per element) are no longer needed
+        if level1 is None:
+            blocks = level_one_blocks(w, Ke0, node_to_free)
+            level1 = Level(w.dim, w.ndof, n_free // w.ndof, blocks, constraints[0], weights, structure_only)
+            del blocks  # the element matrices (E_e K_e^0 per element) are no longer needed
+        levels: List[Level] = [level1]
         for l in range(2, L):
             prev = levels[-1]
             parent = np.asarray(w.sub_to_parent[l - 2])

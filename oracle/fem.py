@@ -125,17 +125,26 @@ def assemble_global(w):
     node_to_free, n = dof_numbering(w)
     edofs = element_dofs(w, node_to_free)
     Ke0 = reference_element_matrix(w)
-    fe = element_load(w)
     nloc = edofs.shape[1]
     rows = np.repeat(edofs, nloc, axis=1)
     cols = np.tile(edofs, (1, nloc))
     vals = w.young[:, None] * Ke0.ravel()[None, :]
     keep = (rows >= 0) & (cols >= 0)
     K = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, n)).tocsr()
+    return K, load_vector(w)
+
+
+def load_vector(w) -> np.ndarray:
+    """Load vector on the free DOFs: every element's consistent load added
+    at its free DOFs (the right-hand side of assemble_global, without the
+    matrix)."""
+    node_to_free, n = dof_numbering(w)
+    edofs = element_dofs(w, node_to_free)
+    fe = element_load(w)
     f = np.zeros(n)
     fv = np.broadcast_to(fe, edofs.shape)
     np.add.at(f, edofs[edofs >= 0], fv[edofs >= 0])
-    return K, f
+    return f
 
 
 def total_load(w) -> np.ndarray:

@@ -16,6 +16,13 @@ namespace {
 // One workgroup per stored tile of the block: reads the tile once and forms
 // both A x_s (for the tile's row) and, for symmetric blocks, A^T x_r (for its
 // column); results go to a partial-sum array reduced by k_mv_reduce.
+// Lane l of the workgroup's 256 keeps rows a0..a0+3 (a0 = 4 (l & 15)) of the
+// columns g, g + 16, g + 32, g + 48 (g = l >> 4), loaded as 32-byte runs of a
+// column.  Runs that hold only padding (rows or columns beyond the block's
+// valid extent) or only upper-triangle entries of a diagonal tile of a
+// symmetric block are not loaded: the diagonal tile contributes L x (its
+// lower triangle with the diagonal) plus L_strict^T x to its own output, so
+// the whole product streams the stored lower triangle and nothing else.
 template <typename TA, typename TX>
 __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __restrict__ d, int nitems,
                                                   const int64_t* __restrict__ prefix, const TA* __restrict__ A,
@@ -42,31 +49,39 @@ __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __rest
   const int R = D.r0 + r, S = D.c0 + s;
   const int t = threadIdx.x;
   __shared__ TA red[16][TS];
+  __shared__ TA vcol[TS];
   const bool zero = D.env && S < D.env[R];
-  TA u_out = 0, v_part[4] = {0, 0, 0, 0};
+  const bool diag = mode == MV_SYM && r == s;
+  TA v_part[4] = {0, 0, 0, 0};
   const int a0 = 4 * (t & 15), g = t >> 4;
+  const int rv = D.vr - r * TS, cv = D.vc - s * TS;  // valid rows / columns of this tile (may exceed 64)
+  const bool need_v = mode == MV_T || mode == MV_SYM;  // transposed product (strictly lower part on a diagonal tile)
+  const bool need_u = mode != MV_T;
   if (!zero) {
     const TA* tile = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
     const TX* xs = x + D.x_off + (int64_t)s * TS;
-    const TX* xr = x + D.x_off + (int64_t)(mode == MV_T ? r : r) * TS;
+    const TX* xr = x + D.x_off + (int64_t)r * TS;
     TA up[4] = {0, 0, 0, 0};
     TA xra[4];
-    const bool need_v = (mode == MV_T) || (mode == MV_SYM && r != s);
-    const bool need_u = mode != MV_T;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) xra[i] = need_v ? (TA)xr[a0 + i] : (TA)0;
+    for (int i = 0; i < 4; ++i) xra[i] = (need_v && a0 + i < rv) ? (TA)xr[a0 + i] : (TA)0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int b = g + 16 * m;
-      const TA* col = tile + b * TS + a0;
-      TA av[4];
+      const bool col_ok = b < cv;
+      TA av[4] = {0, 0, 0, 0};
+      if (col_ok && a0 < rv && (!diag || a0 + 3 >= b)) {
+        const TA* col = tile + b * TS + a0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = col[i];
-      const TA xb = need_u ? (TA)xs[b] : (TA)0;
+        for (int i = 0; i < 4; ++i) av[i] = col[i];
+      }
+      const TA xb = (need_u && col_ok) ? (TA)xs[b] : (TA)0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        up[i] += av[i] * xb;
-        v_part[m] += av[i] * xra[i];
+        const int a = a0 + i;
+        const TA al = (a < rv && (!diag || a >= b)) ? av[i] : (TA)0;  // lower triangle with the diagonal
+        up[i] += al * xb;
+        v_part[m] += (diag && a == b) ? (TA)0 : al * xra[i];
       }
     }
 #pragma unroll
@@ -79,12 +94,16 @@ __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __rest
 #pragma unroll
   for (int m = 0; m < 4; ++m)
     for (int off = 8; off > 0; off >>= 1) v_part[m] += __shfl_xor(v_part[m], off, 16);
+  if (diag && (t & 15) == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) vcol[g + 16 * m] = v_part[m];
   __syncthreads();
+  TA u_out = 0;
   if (t < TS) {
     TA acc = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc += red[q][t];
-    u_out = acc;
+    u_out = diag ? acc + vcol[t] : acc;
   }
   TA* pbase = P + D.p_off;
   if (mode == MV_SYM) {

@@ -78,6 +78,13 @@ struct MvDesc {
   int64_t x_off, y_off;          // vector offsets (x has nc*64 (N, SYM) or nr*64 (T) entries)
   int64_t p_off;                 // partial-sum scratch offset (nr*nc*64 entries)
   const int32_t* env;            // optional first nonzero tile column per row of A (global tile index) or null
+  // Valid rows / columns of the block (the rest of its last tile row / column
+  // is padding).  k_mv_tiles reads no padding entry of A or x and no
+  // upper-triangle entry of a diagonal tile of a symmetric block (it uses the
+  // lower triangle for both products); its outputs at padded positions are
+  // unspecified.  (k_mv_rows reads whole tiles: there padded entries of x
+  // must be finite.)
+  int32_t vr = 1 << 30, vc = 1 << 30;
 };
 // Products with at most SMALL_MV_TILES tiles in all run as one launch with a
 // workgroup per output tile; larger ones as a workgroup per tile plus a

@@ -1103,10 +1103,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         const SubPlan& S = P.subs[b];
         int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
         if (li == 0) {
-          s.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, tI, tG, D.gofs[b], D.gofs[b], 0, nullptr});
+          s.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, tI, tG, D.gofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nG,
+                             (int32_t)S.nG});
         } else if (tI > 0) {
           int tId = tI + tG;
-          pre.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tId, tI, D.iofs[b], D.iofs[b], 0, nullptr});
+          pre.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tId, tI, D.iofs[b], D.iofs[b], 0, nullptr, (int32_t)S.nI,
+                               (int32_t)S.nI});
         }
       }
       if (li == 0) {
@@ -1122,8 +1124,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
             int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
             if (tI == 0 || tG == 0) continue;
             int tId = tI + tG;
-            pt.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.iofs[b], D.gofs[b], 0, nullptr});
-            pn.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.gofs[b], D.iofs[b], 0, nullptr});
+            pt.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.iofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nI,
+                                (int32_t)S.nG});
+            pn.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tI, tG, D.gofs[b], D.iofs[b], 0, nullptr, (int32_t)S.nI,
+                                (int32_t)S.nG});
           }
           if ((st = build_mv(D.mvPreT, MV_T, pt))) return st;
           if ((st = build_mv(D.mvPostN, MV_N, pn))) return st;
@@ -1223,9 +1227,12 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         const SubPlan& S = P.subs[b];
         int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
         int id0 = tG + tC, ic0 = 2 * tG + tC;
-        g.push_back(MvDesc{D.M.off[b], D.M.nt[b], id0, tG, id0, tG, D.gofs[b], D.gofs[b], 0, nullptr});
-        pn.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.gofs[b], D.cofs[b], 0, nullptr});
-        pt.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.cofs[b], D.gofs[b], 0, nullptr});
+        g.push_back(MvDesc{D.M.off[b], D.M.nt[b], id0, tG, id0, tG, D.gofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nG,
+                           (int32_t)S.nG});
+        pn.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.gofs[b], D.cofs[b], 0, nullptr, (int32_t)S.nc,
+                            (int32_t)S.nG});
+        pt.push_back(MvDesc{D.M.off[b], D.M.nt[b], ic0, tC, id0, tG, D.cofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nc,
+                            (int32_t)S.nG});
       }
       if ((st = build_mv(D.mvG, MV_SYM, g))) return st;
       if ((st = build_mv(D.mvPsiN, MV_N, pn))) return st;
@@ -1243,7 +1250,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     // The level-0 G product runs beside the coarse levels when it is FP32: at
     // 48^3 elasticity this took 18 us (9%) off a preconditioner apply, while
     // with an FP64 G product (twice the bytes) the overlap cost 2 us.
-    if (li == 0 && !D.g_psi_sum && D.mfp32 &&
+    if (li == 0 && !D.g_psi_sum && D.mfp32 && opt.side_stream &&
         (st = dalloc((double**)&D.partial_g, std::max<int64_t>(1, D.mvG.partial_elems))))
       return st;
     mark("  constraints, coarse, M mat-vecs");
@@ -2069,6 +2076,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->panel_tiles_precond = 0;
   o->tune_table = nullptr;
   o->lookahead = 0;
+  o->side_stream = 1;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream) {

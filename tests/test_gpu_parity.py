@@ -43,6 +43,9 @@ CASES = {
     # 507 (8 tiles), so the level-2 products take the multi-tile path
     "elast_8x8x8_of_2_L3_g4": lambda: _cube(8, 2, groups=[(4, 4, 4)],
                                             young=10 ** (2 * np.random.default_rng(8).random(16 ** 3))),
+    # four levels: 512 / 64 / 8 / 1 (2x2x2 groups twice)
+    "elast_8x8x8_of_2_L4": lambda: _cube(8, 2, groups=[(2, 2, 2), (2, 2, 2)],
+                                         young=10 ** (2 * np.random.default_rng(9).random(16 ** 3))),
 }
 
 
@@ -250,3 +253,28 @@ def test_lookahead_schedule_same_result(precision):
     u2, st2 = s2.solve(f)
     assert st1["iterations"] == st2["iterations"]
     assert torch.equal(u1, u2)
+
+
+def test_side_stream_same_result():
+    """Mixed precision at 48^3 (the G product takes the side stream there):
+    the level-1 G product beside the coarse levels (fork / join on a second
+    stream) gives bitwise the same applies and solves as one stream, in
+    eager launches and in graph replays."""
+    from paper_1201_5991_amd import Problem, Solver
+    _say("[parity] side-stream G product, 48^3 mixed")
+    prob = Problem(config(2, levels=3))
+    f = torch.tensor(prob.load_vector(), device="cuda")
+    one = Solver(precision="mixed", side_stream=False, use_graph=False).setup(prob)
+    r = torch.tensor(np.random.default_rng(12).standard_normal(one.n_iface), device="cuda")
+    z1 = one.apply(r)
+    u1, st1 = one.solve(f)
+    one.destroy()
+    for graph in (False, True):
+        two = Solver(precision="mixed", side_stream=True, use_graph=graph).setup(prob)
+        for rep in range(3):
+            assert torch.equal(two.apply(r), z1), f"apply, graph={graph}, rep {rep}"
+            u2, st2 = two.solve(f)
+            torch.cuda.synchronize()
+            assert st2["iterations"] == st1["iterations"] and torch.equal(u2, u1), f"solve, graph={graph}, rep {rep}"
+        prof = two.profile()  # noqa: F841 (profiling off: no timing collected)
+        two.destroy()

@@ -182,6 +182,39 @@ def test_condition_grows_with_levels():
     assert kap[0] < kap[1]
 
 
+def test_four_levels_bound_and_trend():
+    # L = 2, 3, 4 on 8^3 subdomains grouped 2x2x2 twice (512 / 64 / 8 / 1, the
+    # paper's 8:1 ratio between levels): lambda_min >= 1 at every depth (the
+    # spectrum of the multilevel operator stays above the exact one), kappa
+    # grows with every added level (Table 1 trend), and the solution agrees
+    # with the direct solve.
+    rng = np.random.default_rng(6)
+    w = cube(8, 2, groups=[(2, 2, 2), (2, 2, 2)], young=10 ** (2 * rng.random(16 ** 3)))
+    ud, _, _ = direct_solve(w)
+    kap = []
+    for L in (2, 3, 4):
+        u, res, b, _ = solve_bddc(w, n_levels=L, tol=1e-12)
+        assert res.converged
+        lo, hi = lanczos_extremes(res.alphas, res.betas)
+        assert lo > 1 - 1e-8
+        kap.append(hi / lo)
+        assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 10 * kap[-1] * 1e-12
+    assert b.coarse_sizes() == [8589, 837, 57]
+    assert kap[0] < kap[1] < kap[2]
+
+
+def test_four_level_with_primal_level_three_equals_three_level():
+    # making every level-3 interface node primal turns level 3 into an exact
+    # solve of the level-3 problem: the 4-level preconditioner is then the
+    # 3-level one, to rounding
+    w = cube(8, 2, groups=[(2, 2, 2), (2, 2, 2)])
+    b3 = MultilevelBDDC(w, n_levels=3)
+    b4 = MultilevelBDDC(w, n_levels=4, constraints=["cef", "cef", "primal"])
+    r = np.random.default_rng(7).standard_normal(b3.level1.n_iface)
+    z3, z4 = b3.apply(r), b4.apply(r)
+    assert np.linalg.norm(z4 - z3) < 1e-11 * np.linalg.norm(z3)
+
+
 def test_condition_grows_with_H_over_h_2d():
     # The bound C (1 + log(H/h))^2: kappa increases with H/h, slower than H/h.
     kap = []
