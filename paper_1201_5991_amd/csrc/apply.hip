@@ -236,12 +236,14 @@ __global__ void k_gather(int64_t n, const int32_t* __restrict__ idx, const doubl
 
 template <typename TI>
 __global__ void k_seg_reduce(int64_t n, const int64_t* __restrict__ ptr, const int64_t* __restrict__ list,
-                             const double* __restrict__ w, const TI* __restrict__ in, double* __restrict__ out, double beta) {
+                             const double* __restrict__ w, const TI* __restrict__ in, const TI* __restrict__ in2,
+                             double* __restrict__ out, double beta) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
     double acc = beta != 0.0 ? beta * out[g] : 0.0;
     for (int64_t j = ptr[g]; j < ptr[g + 1]; ++j) {
       int64_t q = list[j];
-      acc += (w ? w[q] : 1.0) * (double)in[q];
+      const double v = in2 ? (double)in[q] + (double)in2[q] : (double)in[q];
+      acc += (w ? w[q] : 1.0) * v;
     }
     out[g] = acc;
   }
@@ -561,7 +563,8 @@ __global__ void __launch_bounds__(256) k_dot_step(int nb, const double* __restri
 template <typename TI>
 __global__ void __launch_bounds__(256) k_seg_reduce_dot(int64_t n, const int64_t* __restrict__ ptr,
                                                         const int64_t* __restrict__ list, const double* __restrict__ w,
-                                                        const TI* __restrict__ in, double* __restrict__ out,
+                                                        const TI* __restrict__ in, const TI* __restrict__ in2,
+                                                        double* __restrict__ out,
                                                         const double* __restrict__ dotv, double* __restrict__ partial) {
   __shared__ double red[256];
   double v = 0.0;
@@ -569,7 +572,8 @@ __global__ void __launch_bounds__(256) k_seg_reduce_dot(int64_t n, const int64_t
     double acc = 0.0;
     for (int64_t j = ptr[g]; j < ptr[g + 1]; ++j) {
       const int64_t q = list[j];
-      acc += (w ? w[q] : 1.0) * (double)in[q];
+      const double v = in2 ? (double)in[q] + (double)in2[q] : (double)in[q];
+      acc += (w ? w[q] : 1.0) * v;
     }
     out[g] = acc;
     v += acc * dotv[g];
@@ -720,9 +724,9 @@ void launch_gather(hipStream_t st, int64_t n, const int32_t* idx, const double* 
 
 template <typename TI>
 void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
-                       double* out, double beta) {
+                       double* out, double beta, const TI* in2) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_seg_reduce<TI>), dim3(grid_for(n)), dim3(256), 0, st, n, ptr, list, w, in, out, beta);
+  hipLaunchKernelGGL((k_seg_reduce<TI>), dim3(grid_for(n)), dim3(256), 0, st, n, ptr, list, w, in, in2, out, beta);
 }
 
 template <typename TI, typename TO>
@@ -760,15 +764,17 @@ void launch_dot(hipStream_t st, int64_t n, const double* a, const double* b, dou
 template <typename TI>
 void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
                            double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,
-                           int* it, double rtol2) {
+                           int* it, double rtol2, const TI* in2) {
   const unsigned nb = dot_blocks(n);
-  hipLaunchKernelGGL(k_seg_reduce_dot<TI>, dim3(nb), dim3(256), 0, st, n, ptr, list, w, in, out, dotv, partial);
+  hipLaunchKernelGGL(k_seg_reduce_dot<TI>, dim3(nb), dim3(256), 0, st, n, ptr, list, w, in, in2, out, dotv, partial);
   hipLaunchKernelGGL(k_dot_step, dim3(1), dim3(256), 0, st, (int)nb, partial, s, slot, step, hist, it, rtol2);
 }
 template void launch_seg_reduce_dot<double>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const double*,
-                                            double*, const double*, double*, double*, int, int, double*, int*, double);
+                                            double*, const double*, double*, double*, int, int, double*, int*, double,
+                                            const double*);
 template void launch_seg_reduce_dot<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
-                                           double*, const double*, double*, double*, int, int, double*, int*, double);
+                                           double*, const double*, double*, double*, int, int, double*, int*, double,
+                                           const float*);
 
 template <typename TC>
 void launch_pcg_update_xr_check(hipStream_t st, int64_t n, double* x, double* r, const double* p, const double* q,
@@ -832,9 +838,9 @@ template void launch_gather<double, float>(hipStream_t, int64_t, const int32_t*,
 template void launch_gather<float, float>(hipStream_t, int64_t, const int32_t*, const double*, const float*, float*);
 template void launch_gather<float, double>(hipStream_t, int64_t, const int32_t*, const double*, const float*, double*);
 template void launch_seg_reduce<double>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const double*,
-                                        double*, double);
+                                        double*, double, const double*);
 template void launch_seg_reduce<float>(hipStream_t, int64_t, const int64_t*, const int64_t*, const double*, const float*,
-                                       double*, double);
+                                       double*, double, const float*);
 void launch_gather_seg(hipStream_t st, int64_t n, const int32_t* bidx, const double* base, const int64_t* ptr,
                        const int64_t* list, const double* in, double* out) {
   if (n > 0) hipLaunchKernelGGL(k_gather_seg, dim3(grid_for(n)), dim3(256), 0, st, n, bidx, base, ptr, list, in, out);

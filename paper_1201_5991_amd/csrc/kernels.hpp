@@ -106,10 +106,11 @@ void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, i
 // out[i] = (w ? w[i] : 1) * in[idx[i]] (0 where idx < 0), converting types.
 template <typename TI, typename TO>
 void launch_gather(hipStream_t st, int64_t n, const int32_t* idx, const double* w, const TI* in, TO* out);
-// out[g] = beta*out[g] + sum_{j in ptr[g]..ptr[g+1]} (w ? w[list[j]] : 1) * in[list[j]]  (FP64 accumulation)
+// out[g] = beta*out[g] + sum_{j in ptr[g]..ptr[g+1]} (w ? w[list[j]] : 1) * (in[list[j]] (+ in2[list[j]]))
+// (FP64 accumulation; in2 optional)
 template <typename TI>
 void launch_seg_reduce(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
-                       double* out, double beta);
+                       double* out, double beta, const TI* in2 = nullptr);
 // out[g] = base[bidx[g]] + sum_{j in ptr[g]..ptr[g+1]} in[list[j]]  (FP64): a gather and a
 // segmented sum in one launch.
 void launch_gather_seg(hipStream_t st, int64_t n, const int32_t* bidx, const double* base, const int64_t* ptr,
@@ -170,7 +171,7 @@ enum DotStep { DOT_ALPHA = 1, DOT_CHECK = 2, DOT_BETA = 3 };
 template <typename TI>
 void launch_seg_reduce_dot(hipStream_t st, int64_t n, const int64_t* ptr, const int64_t* list, const double* w, const TI* in,
                            double* out, const double* dotv, double* partial, double* s, int slot, int step, double* hist,
-                           int* it, double rtol2);
+                           int* it, double rtol2, const TI* in2 = nullptr);
 // x += alpha p, r -= alpha q (unless done) and the partial sums of r.r in one
 // launch, then the finish of r.r with the stopping test; when copies is given
 // the launch also writes copies[list[j]] = w[list[j]] r[g] for j in

@@ -107,6 +107,7 @@ struct LevelDev {
   // work vectors
   void* rl = nullptr;   // flat interface, M precision
   void* yl = nullptr;   // flat interface, M precision
+  void* yl2 = nullptr;  // flat interface, M precision: Psi_i z_Ci when the G product runs beside the coarse levels
   void* zcl = nullptr;  // flat coarse, M precision
   double* rcl = nullptr;// flat coarse, FP64
   double* rC = nullptr; // level coarse vector (next level's DOFs)
@@ -1250,6 +1251,9 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     // The level-0 G product runs beside the coarse levels when it is FP32: at
     // 48^3 elasticity this took 18 us (9%) off a preconditioner apply, while
     // with an FP64 G product (twice the bytes) the overlap cost 2 us.
+    // Level 0 in mixed precision sums G_i r_i and Psi_i z_Ci in the averaging
+    // (two buffers), so that the G product may run on a stream of its own.
+    if (li == 0 && !D.g_psi_sum && D.mfp32 && (st = dalloc((float**)&D.yl2, std::max<int64_t>(1, D.nG_flat)))) return st;
     if (li == 0 && !D.g_psi_sum && D.mfp32 && opt.side_stream &&
         (st = dalloc((double**)&D.partial_g, std::max<int64_t>(1, D.mvG.partial_elems))))
       return st;
@@ -1681,18 +1685,26 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
       launch_tile_mv_sum<float, float, float>(stream, MV_SYM, D.mvG.d, MV_T, D.mvPsiT.d, (int32_t)D.mvG.h.size(), D.mvG.max_out,
                                               (const float*)D.M.buf, (const float*)D.rl, (const float*)D.zcl, (float*)D.yl, 1.0,
                                               false);
-    } else {
+    } else if (D.yl2) {
+      // Psi_i z_Ci into a buffer of its own (while the G product may still
+      // run beside); the averaging below sums both
+      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl2, 1.0, false, D.partial);
       if (g_side) HIPCHK(hipStreamWaitEvent(stream, ev_gjoin, 0));
       else
         run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial, nullptr,
                                     li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
+    } else {
+      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial, nullptr,
+                                  li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
       run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
     }
+    const float* y2 = D.yl2 ? (const float*)D.yl2 : nullptr;
     if (ds)  // with rhat.zhat and its scalar step
       launch_seg_reduce_dot<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat,
-                                   rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2);
+                                   rhat, d_dotp, d_s, ds->slot, ds->step, d_hist, d_it, ds->rtol2, y2);
     else
-      launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0);
+      launch_seg_reduce<float>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const float*)D.yl, zhat, 0.0,
+                               y2);
   } else {
     launch_gather<double, double>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (double*)D.zcl);
     if (D.g_psi_sum) {

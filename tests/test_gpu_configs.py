@@ -15,8 +15,9 @@ calls only the oracle.  For every workload at its full size:
   with the oracle's within the conditioning bound; lambda_min >= 1 and
   lambda_max matches the oracle's Lanczos estimate;
 * mixed precision: the same 1e-8 residual with at most 15 % more
-  iterations than the oracle, the apply error against the FP64 oracle
-  printed and bounded.
+  iterations than the oracle (rounded up), the apply error against the
+  FP64 oracle printed and bounded by 1e-3 (FP32 local operators: about
+  u_32 kappa_local).
 
 Workloads: 48^3 (64 subdomains of 12^3) at 2 and 3 levels; 96^3 with 1728
 subdomains of 8^3 and log-uniform moduli at 3 levels (4x4x4 level-2 groups)
@@ -127,7 +128,9 @@ def test_config_mixed(name):
     s = Solver(precision="mixed", use_graph=True).setup(prob)
     idx, seeds = np.asarray(gold["sample_idx"]), gold["proj_seeds"]
     r = torch.tensor(np.random.default_rng(gold["r_seed"]).standard_normal(gold["n_iface"]), device="cuda")
-    err = _check_vec(s.apply(r).cpu().numpy(), gold["apply"], idx, seeds, 1e-4, "mixed apply vs FP64 oracle")
+    # FP32 local operators: error about u_32 kappa_local (u_32 = 6e-8); with
+    # moduli spanning three decades kappa_local reaches ~1e4
+    err = _check_vec(s.apply(r).cpu().numpy(), gold["apply"], idx, seeds, 1e-3, "mixed apply vs FP64 oracle")
     print(f"  mixed apply error vs FP64 oracle: {err:.2e}", flush=True)
     _check_vec(s.apply_schur(r).cpu().numpy(), gold["schur"], idx, seeds, RTOL64, "schur (FP64 in mixed mode)")
     u, st = s.solve(f)
