@@ -194,6 +194,18 @@ mlbddc_status mlbddc_apply(mlbddc_t h, const double* r_dev, double* z_dev);
  * [interface_size].  Asynchronous.  E_STATE before setup. */
 mlbddc_status mlbddc_apply_schur(mlbddc_t h, const double* x_dev, double* y_dev);
 
+/* y = S^ x as mlbddc_apply_schur, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the work vectors (the gathered subdomain copies of x
+ * and the products) live in a 64 MiB device array of the library, held on
+ * every device it runs on until the process ends, and nothing is allocated.
+ * E_ARG when 16 bytes per flat interface entry (the subdomain interface
+ * sizes, each rounded up to 64) exceed 64 MiB, E_STATE before setup.  All
+ * calls on one device share that array: calls that overlap on one device
+ * (several streams or threads) race.  Result equal to mlbddc_apply_schur up
+ * to rounding (another summation order).  Asynchronous. */
+mlbddc_status mlbddc_apply_schur_noalloc(mlbddc_t h, const double* x_dev, double* y_dev);
+
 /* Condensed right-hand side g^ = f_G - sum_i R_i^T K_GI K_II^{-1} f_I.
  * f_dev: device FP64 [num_dofs]; g_dev: device FP64 [interface_size]. */
 mlbddc_status mlbddc_condense(mlbddc_t h, const double* f_dev, double* g_dev);

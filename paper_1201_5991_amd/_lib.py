@@ -30,7 +30,7 @@ EXPORTED = [
     "mlbddc_element_energy", "mlbddc_get_coarse_matrix", "mlbddc_destroy", "mlbddc_last_error",
     "mlbddc_element_matrix", "mlbddc_element_load", "mlbddc_plan_counts", "mlbddc_plan_interface",
     "mlbddc_set_profiling", "mlbddc_get_profile", "mlbddc_subdomain_sizes", "mlbddc_assemble_load",
-    "mlbddc_interface_dofs",
+    "mlbddc_interface_dofs", "mlbddc_apply_schur_noalloc",
 ]
 PROF_N = 8
 PROF_NAMES = ["update_fp64", "update_fp32", "panel", "diag", "negate", "schur_mv", "precond_mv"]
@@ -140,6 +140,7 @@ def load():
         "mlbddc_subdomain_sizes": (I32, [VP, I32, P(I64)]),
         "mlbddc_assemble_load": (I32, [P(Mesh), P(D), P(D), I64]),
         "mlbddc_interface_dofs": (I32, [VP, P(I64)]),
+        "mlbddc_apply_schur_noalloc": (I32, [VP, VP, VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

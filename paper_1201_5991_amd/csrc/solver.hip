@@ -39,6 +39,7 @@
 #include <map>
 #include <sstream>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,7 +48,35 @@
 
 namespace mlbddc {
 
+// Device scratch of the entry point that allocates nothing
+// (mlbddc_apply_schur_noalloc): the gathered input and the product output of
+// the interface operator, 2 * 8 bytes per flat interface entry.  Every device
+// the library runs on holds it until the process ends.  In host code the
+// array's name is not a device address: the address comes from
+// hipGetSymbolAddress, once per device (scratch_address).
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double scratch[SCRATCH_BYTES / sizeof(double)];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of `scratch` on `device` (that device current), looked up once.
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -423,6 +452,10 @@ struct Handle {
   mlbddc_status apply_full(int li, const double* r, double* z);
   // x_copied: the subdomain copies of x are already in place (written by the PCG update)
   mlbddc_status schur(const double* x, double* y, const DotFinish* ds = nullptr, bool x_copied = false);
+  // y = S^ x with the device scratch array for its work vectors (no device memory of the handle
+  // beyond the operator itself; nothing allocated)
+  void* scratch_ptr = nullptr;  // address of `scratch` on this handle's device
+  mlbddc_status schur_noalloc(const double* x, double* y);
   mlbddc_status condense(const double* f, double* g);
   mlbddc_status recover(const double* uhat, double* u);
   mlbddc_status solve(const double* f, double* u, const double* u0, mlbddc_stats* st);
@@ -1784,6 +1817,26 @@ mlbddc_status Handle::schur(const double* x, double* y, const DotFinish* ds, boo
   return MLBDDC_OK;
 }
 
+mlbddc_status Handle::schur_noalloc(const double* x, double* y) {
+  LevelDev& D = lev[0];
+  if (!scratch_ptr) return fail(MLBDDC_E_STATE, "apply_schur_noalloc: no scratch address on this device");
+  const int64_t n = D.nG_flat, n_al = round_up(n, 32);
+  const size_t need = sizeof(double) * (size_t)(2 * n_al);
+  if (need > SCRATCH_BYTES)
+    return fail(MLBDDC_E_ARG, "apply_schur_noalloc: the interface work vectors need " + std::to_string(need) +
+                                  " bytes, more than the " + std::to_string(SCRATCH_BYTES) + "-byte device scratch");
+  double* xs = (double*)scratch_ptr;
+  double* ys = xs + n_al;
+  // every flat position of xs is written (0 at padding); the product writes
+  // every entry of ys that the segmented sum reads
+  launch_gather<double, double>(stream, n, D.d_gidx, nullptr, x, xs);
+  launch_tile_mv_sum<double, double, double>(stream, MV_SYM, D.mvS.d, MV_SYM, nullptr, (int32_t)D.mvS.h.size(), D.mvS.max_out,
+                                             (const double*)D.K.buf, xs, nullptr, ys, 1.0, false);
+  launch_seg_reduce<double>(stream, (int64_t)D.P->iface_dofs.size(), D.d_gptr, D.d_glist, nullptr, ys, y, 0.0);
+  HIPCHK(hipGetLastError());
+  return MLBDDC_OK;
+}
+
 mlbddc_status Handle::condense(const double* f, double* g) {
   LevelDev& D = lev[0];
   const int64_t nif = (int64_t)D.P->iface_dofs.size();
@@ -2120,8 +2173,16 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
     g_create_error.message = "hipSetDevice failed";
     return MLBDDC_E_HIP;
   }
+  void* sp = nullptr;
+  if (hipError_t e = mlbddc::scratch_address(o.device, &sp); e != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_error.status = MLBDDC_E_HIP;
+    g_create_error.message = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return MLBDDC_E_HIP;
+  }
   auto* h = new mlbddc_handle_s();
   h->h.opt = o;
+  h->h.scratch_ptr = sp;
   h->h.lookahead = o.lookahead != 0;
   if (o.tune_table) {
     std::ifstream in(o.tune_table);
@@ -2207,6 +2268,13 @@ mlbddc_status mlbddc_apply_schur(mlbddc_t h, const double* x, double* y) {
   if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "apply_schur before setup");
   if (!x || !y || x == y) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
   return h->h.schur(x, y);
+}
+
+mlbddc_status mlbddc_apply_schur_noalloc(mlbddc_t h, const double* x, double* y) {
+  if (!h) return MLBDDC_E_ARG;
+  if (!h->h.ready) return h->h.fail(MLBDDC_E_STATE, "apply_schur_noalloc before setup");
+  if (!x || !y || x == y) return h->h.fail(MLBDDC_E_ARG, "bad vector pointers");
+  return h->h.schur_noalloc(x, y);
 }
 
 mlbddc_status mlbddc_condense(mlbddc_t h, const double* f, double* g) {
