@@ -172,7 +172,9 @@ class Level:
             self.RC.append(np.array(rc, dtype=np.int64))
 
         # --- weights D_i on the local interface DOFs; E_i^T r = D_i (R_i r)
-        if weights == "stiffness":
+        # (index structure only: the matrices of levels >= 2 are not formed, so
+        # the multiplicity weights stand in for the stiffness ratios)
+        if weights == "stiffness" and not structure_only:
             diag_sum = np.zeros(self.n_iface)
             diags = []
             for i in range(self.n_sub):
@@ -180,7 +182,7 @@ class Level:
                 diags.append(d)
                 np.add.at(diag_sum, self.R[i], d)
             self.D = [diags[i] / diag_sum[self.R[i]] for i in range(self.n_sub)]
-        elif weights == "multiplicity":
+        elif weights in ("multiplicity", "stiffness"):
             mult = np.zeros(self.n_iface)
             for i in range(self.n_sub):
                 np.add.at(mult, self.R[i], 1.0)
