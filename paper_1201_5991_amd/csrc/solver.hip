@@ -1684,13 +1684,9 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
     if (D.mfp32) launch_gather<double, float>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (float*)D.rl);
     else launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, D.d_w, rhat, (double*)D.rl);
   }
-  // r_C = sum R_Ci^T Psi_i^T r_i
-  if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
-  else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, 1.0, false, D.partial);
   // y_i = G_i r_i needs no coarse correction: on level 0 it runs on a stream
-  // of its own beside the (latency-bound) coarse levels, forked after the
-  // Psi^T r product so that this widest kernel of the coarse chain has the
-  // whole chip
+  // of its own beside the coarse correction (Psi^T r, the coarse levels,
+  // Psi z_C), which takes less time than this product
   const bool g_side = D.partial_g != nullptr;
   if (g_side) {
     if (!gstream) {
@@ -1708,6 +1704,9 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
                                      alg_bytes_G);
     HIPCHK(hipEventRecord(ev_gjoin, gstream));
   }
+  // r_C = sum R_Ci^T Psi_i^T r_i
+  if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
+  else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, 1.0, false, D.partial);
   launch_seg_reduce<double>(stream, P.n_coarse, D.d_cptr, D.d_clist, nullptr, D.rcl, D.rC, 0.0);
   // coarse correction: the next level
   if ((st = apply_full(li + 1, D.rC, D.zC))) return st;
