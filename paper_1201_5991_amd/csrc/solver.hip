@@ -414,6 +414,7 @@ struct Handle {
   mlbddc_status enqueue_K(int li, bool zero);
   mlbddc_status enqueue_K_assembly(int li, bool zero);
   mlbddc_status enqueue_K_factor(int li);
+  mlbddc_status enqueue_weights(int li);
   mlbddc_status enqueue_rest(int li, bool zero);
   mlbddc_status finish_numeric();
   mlbddc_status numeric();
@@ -897,12 +898,14 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
   // stream sees the same order as a sequential set-up.
   std::future<mlbddc_status> pending;
   auto join = [&]() -> mlbddc_status { return pending.valid() ? pending.get() : MLBDDC_OK; };
-  // part 0: K assembly; 1: interface weights and K factorization; 2: the rest
+  // part 0: K assembly (and the interface diagonal for the weights); 1: K
+  // factorization; 3: interface weights (needs the flat layouts); 2: the rest
   auto enqueue_async = [&](int li, int part) {
     const int dev = opt.device;
     pending = std::async(std::launch::async, [this, li, part, dev]() -> mlbddc_status {
       if (hipSetDevice(dev) != hipSuccess) return herr("hipSetDevice", hipGetLastError());
-      return part == 0 ? enqueue_K_assembly(li, false) : part == 1 ? enqueue_K_factor(li) : enqueue_rest(li, false);
+      return part == 0 ? enqueue_K_assembly(li, false) : part == 1 ? enqueue_K_factor(li)
+                       : part == 3 ? enqueue_weights(li) : enqueue_rest(li, false);
     });
   };
   PlanInput in;
@@ -1044,14 +1047,8 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       }
     }
 
-    mark("  assembly maps");
-    // the device assembles K while the host builds the flat layouts
-    if ((st = checked.get())) return st;
-    mark("  validate (K job)");
-    if ((st = join())) return st;
-    if ((st = upload_fence())) return st;
-    enqueue_async(li, 0);
-    // flat layouts
+    // flat offsets and the positions of the interface diagonal in the K
+    // matrices (the assembly saves that diagonal for the weights)
     D.gofs.assign(ns + 1, 0);
     D.iofs.assign(ns + 1, 0);
     D.cofs.assign(ns + 1, 0);
@@ -1063,9 +1060,31 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     D.nG_flat = D.gofs[ns];
     D.nI_flat = D.iofs[ns];
     D.nC_flat = D.cofs[ns];
+    if (!P.top) {
+      std::vector<int64_t> gdiag(D.nG_flat, 0);
+      parallel_run(std::min(16, ns), [&](int t) {
+        for (int b = t; b < ns; b += std::min(16, ns)) {
+          const SubPlan& S = P.subs[b];
+          for (int64_t k = 0; k < S.nGp; ++k)
+            gdiag[D.gofs[b] + k] = D.K.off[b] + packed_offset(S.nIp + k, S.nIp + k, D.K.nt[b]);
+        }
+      });
+      if ((st = upload(&D.d_gdiag_pos, gdiag))) return st;
+    }
+    if ((st = dalloc(&D.gd, std::max<int64_t>(D.nG_flat, 1)))) return st;
+
+    mark("  assembly maps");
+    // the device assembles and factorizes K while the host builds the flat layouts
+    if ((st = checked.get())) return st;
+    mark("  validate (K job)");
+    if ((st = join())) return st;
+    if ((st = upload_fence())) return st;
+    enqueue_async(li, 0);
+    if ((st = join())) return st;
+    enqueue_async(li, 1);
+    // flat layouts
     {
       std::vector<int32_t> gidx(D.nG_flat, -1), iidx(D.nI_flat, -1), cidx(D.nC_flat, -1);
-      std::vector<int64_t> gdiag(D.nG_flat, 0);
       const int64_t nif = (int64_t)P.iface_dofs.size();
       std::vector<int64_t> gcnt(nif + 1, 0), ccnt(P.n_coarse + 1, 0);
       for (int b = 0; b < ns; ++b) {
@@ -1074,7 +1093,6 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
           gidx[D.gofs[b] + k] = S.iface[k];
           gcnt[S.iface[k] + 1]++;
         }
-        for (int64_t k = 0; k < S.nGp; ++k) gdiag[D.gofs[b] + k] = D.K.off[b] + packed_offset(S.nIp + k, S.nIp + k, D.K.nt[b]);
         for (int64_t k = 0; k < S.nIp; ++k) iidx[D.iofs[b] + k] = (int32_t)S.dofI[k];
         for (int k = 0; k < S.nc; ++k) {
           cidx[D.cofs[b] + k] = S.coarse[k];
@@ -1102,7 +1120,6 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       if ((st = upload(&D.d_glist, glist))) return st;
       if ((st = upload(&D.d_cptr, ccnt))) return st;
       if ((st = upload(&D.d_clist, clist))) return st;
-      if ((st = upload(&D.d_gdiag_pos, gdiag))) return st;
     }
     const size_t mesz = D.mfp32 ? 4 : 8, kesz = D.kfp32 ? 4 : 8;
     auto valloc = [&](void** p, int64_t n, size_t esz) -> mlbddc_status {
@@ -1121,15 +1138,14 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     if ((st = valloc(&D.uI, D.nI_flat, kesz))) return st;
     if ((st = valloc(&D.zG, D.nG_flat, kesz))) return st;
     if ((st = dalloc(&D.tG, std::max<int64_t>(D.nG_flat, 1)))) return st;
-    if ((st = dalloc(&D.gd, std::max<int64_t>(D.nG_flat, 1)))) return st;
     if ((st = dalloc(&D.gd2, std::max<int64_t>(D.nG_flat, 1)))) return st;
     if ((st = dalloc(&D.wI, std::max<int64_t>(D.nI_flat, 1)))) return st;
 
     mark("  flat layouts + vectors");
-    // the device factors this level's K job while the host goes on
+    // the weights, queued behind the K factorization
     if ((st = join())) return st;
     if ((st = upload_fence())) return st;
-    enqueue_async(li, 1);
+    enqueue_async(li, 3);
     // K-job tile mat-vecs
     {
       std::vector<MvDesc> s, pre;
@@ -1543,7 +1559,8 @@ mlbddc_status Handle::validate_level(int li, int part) {
 mlbddc_status Handle::enqueue_K(int li, bool zero) {
   mlbddc_status st;
   if ((st = enqueue_K_assembly(li, zero))) return st;
-  return enqueue_K_factor(li);
+  if ((st = enqueue_K_factor(li))) return st;
+  return enqueue_weights(li);
 }
 
 mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
@@ -1567,30 +1584,33 @@ mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
     launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf);
   else
     launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
+  // the assembled (sub-assembled) interface diagonal, kept for the weights:
+  // the factorization overwrites it with that of the Schur complement
+  if (!P.top) {
+    if (opt.weights == MLBDDC_W_MULTIPLICITY) launch_fill(stream, D.nG_flat, 1.0, D.gd);
+    else if (D.kfp32) launch_gather64<float>(stream, D.nG_flat, D.d_gdiag_pos, (const float*)D.K.buf, D.gd);
+    else launch_gather64<double>(stream, D.nG_flat, D.d_gdiag_pos, (const double*)D.K.buf, D.gd);
+  }
   HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
 
 mlbddc_status Handle::enqueue_K_factor(int li) {
-  mlbddc_status st;
+  LevelDev& D = lev[li];
+  return factor(D.K, D.P->level, false);
+}
+
+// Weights D_i = d_i / sum_j d_j per interface DOF from the diagonal saved by
+// the assembly (needs the flat layouts, so it is queued after them).
+mlbddc_status Handle::enqueue_weights(int li) {
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
-  // weights from the assembled interface diagonal (before factorization)
-  if (!P.top) {
-    const int64_t nif = (int64_t)P.iface_dofs.size();
-    if (opt.weights == MLBDDC_W_MULTIPLICITY) {
-      launch_fill(stream, D.nG_flat, 1.0, D.gd);
-    } else {
-      // gd[i] = K[gdiag_pos[i]]: the assembled (sub-assembled) diagonal at the interface
-      if (D.kfp32) launch_gather64<float>(stream, D.nG_flat, D.d_gdiag_pos, (const float*)D.K.buf, D.gd);
-      else launch_gather64<double>(stream, D.nG_flat, D.d_gdiag_pos, (const double*)D.K.buf, D.gd);
-    }
-    // sum over subdomains per interface DOF, then w = d / sum
-    launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd, D.rhat, 0.0);
-    launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.rhat, D.gd2);
-    launch_ratio(stream, D.nG_flat, D.gd, D.gd2, D.d_gidx, D.d_w);
-  }
-  if ((st = factor(D.K, P.level, false))) return st;
+  if (P.top) return MLBDDC_OK;
+  const int64_t nif = (int64_t)P.iface_dofs.size();
+  launch_seg_reduce<double>(stream, nif, D.d_gptr, D.d_glist, nullptr, D.gd, D.rhat, 0.0);
+  launch_gather<double, double>(stream, D.nG_flat, D.d_gidx, nullptr, D.rhat, D.gd2);
+  launch_ratio(stream, D.nG_flat, D.gd, D.gd2, D.d_gidx, D.d_w);
+  HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
 

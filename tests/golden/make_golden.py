@@ -57,7 +57,18 @@ CASES = {
     "elasticity96_L3": (lambda: config(3, levels=3), None),
     "elasticity96_L4": (lambda: config(3, levels=4), None),
     "elasticity80_uneven_L3": (lambda: config(4), None),
+    "elasticity40_8sub20_L2": (lambda: large_subdomains(), None),
 }
+
+
+def large_subdomains():
+    """Subdomains of 20^3 elements (27,783 DOFs each, the paper's tens of
+    thousands of unknowns per subdomain): 40^3 elements, 2x2x2 subdomains,
+    E = 10^(2U), U ~ U(0,1) from default_rng(3), 2 levels."""
+    n = 40
+    young = 10.0 ** (2.0 * np.random.default_rng(3).random(n ** 3))
+    return box_workload("elasticity3d_40cube_8sub20_L2", "elasticity", (n,) * 3, [uniform_cuts(n, 2)] * 3,
+                        young=young, seed=3)
 
 
 def grad_reduced():
