@@ -418,8 +418,9 @@ __device__ inline double dot64(const double (&a)[TS], const double* __restrict__
 __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvDesc* __restrict__ d,
                                                          const double* __restrict__ A, const double* __restrict__ Inv,
                                                          const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                                         const int32_t* __restrict__ rslot,
                                                          const int32_t* __restrict__ cptr, const int32_t* __restrict__ crow,
-                                                         double* v) {
+                                                         const int32_t* __restrict__ cslot, double* v) {
   const TrsvDesc D = d[blockIdx.x];
   constexpr int LDW = TS + 1;
   __shared__ double sw[TS * LDW];
@@ -443,7 +444,7 @@ __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvD
       for (int q = q0 + w - 1; q < q1; q += TRSV_WAVES - 1) {
         const int s = rcol[q];
         sv[w][lane] = vv[(int64_t)s * TS + lane];
-        load_tile_rows(base + tile_index(k, s, D.a_nt) * TE, lane, a);
+        load_tile_rows(base + (int64_t)rslot[q] * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
         part += dot64(a, sv[w]);
         __builtin_amdgcn_wave_barrier();
@@ -453,7 +454,7 @@ __global__ void __launch_bounds__(TRSV_WAVES * 64) k_trsv(int trans, const TrsvD
       for (int q = q0 + w - 1; q < q1; q += TRSV_WAVES - 1) {
         const int r = crow[q];
         sv[w][lane] = vv[(int64_t)r * TS + lane];
-        load_tile_cols(base + tile_index(r, k, D.a_nt) * TE, lane, a);
+        load_tile_cols(base + (int64_t)cslot[q] * TE, lane, a);
         __builtin_amdgcn_wave_barrier();
         part += dot64(a, sv[w]);
         __builtin_amdgcn_wave_barrier();
@@ -745,10 +746,11 @@ void launch_tile_list_mv(hipStream_t st, bool trans, const TileRef* tiles, int64
 }
 
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
-                 const int32_t* rptr, const int32_t* rcol, const int32_t* cptr, const int32_t* crow, double* v) {
+                 const int32_t* rptr, const int32_t* rcol, const int32_t* rslot, const int32_t* cptr, const int32_t* crow,
+                 const int32_t* cslot, double* v) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(TRSV_WAVES * 64), 0, st, transposed ? 1 : 0, d, A, Inv, rptr, rcol, cptr,
-                     crow, v);
+  hipLaunchKernelGGL(k_trsv, dim3(nitems), dim3(TRSV_WAVES * 64), 0, st, transposed ? 1 : 0, d, A, Inv, rptr, rcol, rslot,
+                     cptr, crow, cslot, v);
 }
 
 static unsigned dot_blocks(int64_t n) {

@@ -26,6 +26,17 @@ constexpr int TE = TS * TS;        // elements per tile
 __host__ __device__ inline int64_t tile_col_start(int64_t s, int64_t nt) { return s * nt - s * (s - 1) / 2; }
 __host__ __device__ inline int64_t tile_index(int64_t r, int64_t s, int64_t nt) { return tile_col_start(s, nt) + (r - s); }
 __host__ __device__ inline int64_t packed_tiles(int64_t nt) { return nt * (nt + 1) / 2; }
+// Storage slot of tile (r, s) of matrix `item`: matrices with a tile map
+// (tmap_off[item] >= 0) store only the tiles some kernel touches, the map
+// gives each packed-lower tile index its slot (-1: not stored); the others
+// are dense packed-lower (slot = tile index).
+__host__ __device__ inline int64_t tile_slot(const int32_t* tmap, const int64_t* tmap_off, int item, int64_t r, int64_t s,
+                                             int64_t nt) {
+  const int64_t ti = tile_index(r, s, nt);
+  if (!tmap) return ti;
+  const int64_t o = tmap_off[item];
+  return o < 0 ? ti : (int64_t)tmap[o + ti];
+}
 
 // Element offset of entry (p, q) (p/64 >= q/64 required) in a tile-packed matrix.
 __host__ __device__ inline int64_t packed_offset(int64_t p, int64_t q, int64_t nt) {

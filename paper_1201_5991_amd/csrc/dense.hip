@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ el
                                                   const int32_t* __restrict__ el_local, int nd, const int32_t* __restrict__ el_sub,
                                                   const int64_t* __restrict__ sub_off, const int32_t* __restrict__ sub_nt,
                                                   const double* __restrict__ Kref, const double* __restrict__ scale,
-                                                  const int64_t* __restrict__ ekc_off, const double* __restrict__ ekc, T* A) {
+                                                  const int64_t* __restrict__ ekc_off, const double* __restrict__ ekc, T* A,
+                                                  const int32_t* __restrict__ tmap, const int64_t* __restrict__ tmap_off) {
   const int64_t e = elems[blockIdx.x];
   const int b = el_sub[e];
   const int32_t base = el_local_ptr[e];
@@ -126,22 +127,19 @@ __global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ el
     if (ka < 0 || kc < 0) continue;
     const int p = ka + (a - na * nd), q = kc + (c - nc * nd);
     if (p / TS < q / TS) continue;
-    A[off + packed_offset(p, q, nt)] += (T)(sc * M[idx]);
+    A[off + tile_slot(tmap, tmap_off, b, p / TS, q / TS, nt) * TE + (q % TS) * TS + (p % TS)] += (T)(sc * M[idx]);
   }
 }
 
-__global__ void __launch_bounds__(256) k_zero_runs(const ZeroRun* __restrict__ runs, char* base) {
-  const ZeroRun z = runs[blockIdx.x];
-  uint4* p = reinterpret_cast<uint4*>(base + z.off);
-  const int64_t n = z.bytes / 16;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 template <typename T>
-__global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A) {
+__global__ void k_set_diag(const DiagSeg* __restrict__ segs, T* A, const int32_t* __restrict__ tmap,
+                           const int64_t* __restrict__ tmap_off) {
   const DiagSeg s = segs[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.count; i += gridDim.x * blockDim.x)
-    A[s.off + packed_offset(s.row0 + i, s.col0 + i, s.nt)] = (T)s.val;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.count; i += gridDim.x * blockDim.x) {
+    const int64_t p = s.row0 + i, q = s.col0 + i;
+    const int64_t slot = s.item >= 0 ? tile_slot(tmap, tmap_off, s.item, p / TS, q / TS, s.nt) : tile_index(p / TS, q / TS, s.nt);
+    A[s.off + slot * TE + (q % TS) * TS + (p % TS)] = (T)s.val;
+  }
 }
 
 // ------------------------------------------------------------ factorization
@@ -240,14 +238,15 @@ __device__ inline void store16t(const typename Mfma<T>::acc_t& acc, T* O) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                               const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
-                                              int32_t* err, T* A, T* Inv) {
+                                              int32_t* err, T* A, T* Inv, const int32_t* __restrict__ tmap,
+                                              const int64_t* __restrict__ tmap_off) {
   __shared__ T sA[TS * LDT];
   __shared__ T colbuf[16];
   typedef typename Mfma<T>::acc_t acc_t;
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), k = task_r(t);
   const int nt = ntv[item];
-  T* gA = A + off[item] + tile_index(k, k, nt) * TE;
+  T* gA = A + off[item] + tile_slot(tmap, tmap_off, item, k, k, nt) * TE;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   stage_tile<T, T>(sA, gA, false);
   __syncthreads();
@@ -437,7 +436,8 @@ __device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
 template <typename T, bool PANEL>
 __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
-                                                    T* A, const T* __restrict__ Inv) {
+                                                    T* A, const T* __restrict__ Inv, const int32_t* __restrict__ tmap,
+                                                    const int64_t* __restrict__ tmap_off) {
   __shared__ T sR[KH * LDU];
   __shared__ T sS[KH * LDU];
   const uint64_t t = tasks[xcd_slice(blockIdx.x, gridDim.x)];
@@ -446,12 +446,25 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
   const int nsteps = PANEL ? 2 : 2 * (task_nk(t) + 1);
   const int nt = ntv[item];
   T* base = A + off[item];
-  T* g = base + tile_index(r, s, nt) * TE;
+  T* g = base + tile_slot(tmap, tmap_off, item, r, s, nt) * TE;
   const bool same = !PANEL && r == s;
-  auto rsrc = [&](int q) { return base + tile_index(r, kf + (q >> 1), nt) * TE + (q & 1) * (TE / 2); };
+  // a tile-mapped matrix: lane j holds the slots of tiles (r, kf + j) and
+  // (s, kf + j), loaded together up front (the schedule keeps at most 64
+  // columns per task on such matrices)
+  const int64_t mo = tmap ? tmap_off[item] : -1;
+  int32_t rslot = 0, sslot = 0;
+  if (mo >= 0) {
+    const int j = threadIdx.x & 63;
+    if (j < (PANEL ? 1 : task_nk(t) + 1)) {
+      rslot = tmap[mo + tile_index(r, kf + j, nt)];
+      if (!PANEL) sslot = tmap[mo + tile_index(s, kf + j, nt)];
+    }
+  }
+  auto rtile = [&](int j) -> int64_t { return mo >= 0 ? __builtin_amdgcn_readlane(rslot, j) : tile_index(r, kf + j, nt); };
+  auto stile = [&](int j) -> int64_t { return mo >= 0 ? __builtin_amdgcn_readlane(sslot, j) : tile_index(s, kf + j, nt); };
+  auto rsrc = [&](int q) { return base + rtile(q >> 1) * TE + (q & 1) * (TE / 2); };
   auto ssrc = [&](int q) -> const T* {
-    return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q & 1) * (TE / 2)
-                 : base + tile_index(s, kf + (q >> 1), nt) * TE + (q & 1) * (TE / 2);
+    return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q & 1) * (TE / 2) : base + stile(q >> 1) * TE + (q & 1) * (TE / 2);
   };
   typename Mfma<T>::acc_t acc[2][2];
   for (int a = 0; a < 2; ++a)
@@ -494,10 +507,11 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_negate(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
-                                                const int32_t* __restrict__ ntv, T* A) {
+                                                const int32_t* __restrict__ ntv, T* A, const int32_t* __restrict__ tmap,
+                                                const int64_t* __restrict__ tmap_off) {
   const uint64_t t = tasks[blockIdx.x];
   const int item = task_item(t), r = task_r(t), s = task_s(t);
-  T* g = A + off[item] + tile_index(r, s, ntv[item]) * TE;
+  T* g = A + off[item] + tile_slot(tmap, tmap_off, item, r, s, ntv[item]) * TE;
   for (int idx = threadIdx.x; idx < TE; idx += blockDim.x) g[idx] = -g[idx];
 }
 
@@ -569,22 +583,19 @@ __global__ void k_coarse_from_M(const KcDesc* __restrict__ d, const TP* __restri
 template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr, const int32_t* el_local,
                      int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt, const double* Kref,
-                     const double* scale, const int64_t* ekc_off, const double* ekc, T* A) {
+                     const double* scale, const int64_t* ekc_off, const double* ekc, T* A, const int32_t* tmap,
+                     const int64_t* tmap_off) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)n), dim3(256), 0, st, elems, el_local_ptr, el_local, nd, el_sub, sub_off,
-                     sub_nt, Kref, scale, ekc_off, ekc, A);
-}
-
-void launch_zero_runs(hipStream_t st, const ZeroRun* runs, int64_t nrun, void* base) {
-  if (nrun <= 0) return;
-  hipLaunchKernelGGL(k_zero_runs, dim3((unsigned)nrun), dim3(256), 0, st, runs, (char*)base);
+                     sub_nt, Kref, scale, ekc_off, ekc, A, tmap, tmap_off);
 }
 
 template <typename T>
-void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t max_count, T* A) {
+void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t max_count, T* A, const int32_t* tmap,
+                     const int64_t* tmap_off) {
   if (nseg <= 0 || max_count <= 0) return;
   unsigned gx = (unsigned)std::min<int64_t>((max_count + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_set_diag<T>, dim3(gx, (unsigned)nseg), dim3(256), 0, st, segs, A);
+  hipLaunchKernelGGL(k_set_diag<T>, dim3(gx, (unsigned)nseg), dim3(256), 0, st, segs, A, tmap, tmap_off);
 }
 
 template <typename T>
@@ -594,11 +605,19 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
   const uint64_t* tk = a.tasks + first;
   dim3 grid((unsigned)count), blk(256);
   switch (kind) {
-    case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A); break;
-    case L_INPANEL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
-    case L_DIAG: hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv); break;
-    case L_PANEL: hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
-    case L_TRAIL: hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv); break;
+    case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A, a.tmap, a.tmap_off); break;
+    case L_INPANEL:
+      hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
+      break;
+    case L_DIAG:
+      hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv, a.tmap, a.tmap_off);
+      break;
+    case L_PANEL:
+      hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
+      break;
+    case L_TRAIL:
+      hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
+      break;
   }
 }
 
@@ -626,8 +645,8 @@ void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32
 #define INST_T(T)                                                                                                         \
   template void launch_assemble<T>(hipStream_t, const int64_t*, int64_t, const int32_t*, const int32_t*, int, const int32_t*, \
                                    const int64_t*, const int32_t*, const double*, const double*, const int64_t*,        \
-                                   const double*, T*);                                                                  \
-  template void launch_set_diag<T>(hipStream_t, const DiagSeg*, int64_t, int32_t, T*);                                 \
+                                   const double*, T*, const int32_t*, const int64_t*);                                  \
+  template void launch_set_diag<T>(hipStream_t, const DiagSeg*, int64_t, int32_t, T*, const int32_t*, const int64_t*); \
   template void launch_factor_step<T>(hipStream_t, int, int, const FactorArgs&, int64_t, int64_t, T*, T*);             \
 
 INST_T(double)

@@ -16,20 +16,19 @@ namespace mlbddc {
 // e of subdomain el_sub[e] adds entry (a, c) of its matrix at local position
 // (el_local[ptr+a], el_local[ptr+c]).  The element matrix is
 // scale[e] * Kref (Kref != null) or ekc[ekc_off[e] ...] (row-major, nloc^2).
+// Subdomain b's matrix is tile-mapped when tmap is set and tmap_off[b] >= 0.
 template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr,
                      const int32_t* el_local, int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
-                     const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A);
+                     const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A,
+                     const int32_t* tmap, const int64_t* tmap_off);
 
-// Zero byte ranges (offsets and lengths multiples of 16) of one buffer, one
-// workgroup per range.
-struct ZeroRun { int64_t off, bytes; };
-void launch_zero_runs(hipStream_t st, const ZeroRun* runs, int64_t nrun, void* base);
-
-// Set entries A[row0+i][col0+i] = val for every segment (tile-packed matrices).
-struct DiagSeg { int64_t off; int32_t nt; int32_t row0, col0, count; double val; };
+// Set entries A[row0+i][col0+i] = val for every segment (tile-packed
+// matrices; `item` indexes the tile map, -1 = dense packed-lower).
+struct DiagSeg { int64_t off; int32_t nt; int32_t row0, col0, count; double val; int32_t item = -1; };
 template <typename T>
-void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t max_count, T* A);
+void launch_set_diag(hipStream_t st, const DiagSeg* segs, int64_t nseg, int32_t max_count, T* A,
+                     const int32_t* tmap = nullptr, const int64_t* tmap_off = nullptr);
 
 // ---------------------------------------------------------- factorization
 struct FactorArgs {
@@ -38,6 +37,8 @@ struct FactorArgs {
   const int32_t* nt;       // tiles per side of each item
   const int64_t* inv_off;  // element offset of each item's inverse diagonal tiles
   int32_t* err;            // [0] = failing item + 1, [1] = column
+  const int32_t* tmap;     // tile maps (tile_slot), or null: every matrix dense packed-lower
+  const int64_t* tmap_off;
 };
 template <typename T>
 void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv);
@@ -142,9 +143,11 @@ void launch_tile_list_mv(hipStream_t st, bool trans, const TileRef* tiles, int64
 // interior tiles: row k holds columns rcol[rptr[p_row + k] .. rptr[p_row + k + 1])
 // (all < k), column k holds rows crow[cptr[p_col + k] .. cptr[p_col + k + 1])
 // (all > k and inside the interior).
+// rslot / cslot: storage slot (relative to a_off) of the tile of every rcol / crow entry.
 struct TrsvDesc { int64_t a_off; int32_t a_nt, k0, k1, p_row, p_col, pad; int64_t inv_off, v_off; };
 void launch_trsv(hipStream_t st, bool transposed, const TrsvDesc* d, int32_t nitems, const double* A, const double* Inv,
-                 const int32_t* rptr, const int32_t* rcol, const int32_t* cptr, const int32_t* crow, double* v);
+                 const int32_t* rptr, const int32_t* rcol, const int32_t* rslot, const int32_t* cptr, const int32_t* crow,
+                 const int32_t* cslot, double* v);
 
 // ------------------------------------------------------------------- PCG
 // Deterministic dot product: partial sums per block then a single-block finish.

@@ -105,6 +105,35 @@ struct Job {
   uint64_t* d_tasks = nullptr;
   int32_t* d_err = nullptr;
   int panel = 4;
+  // Tile maps (tile_slot): a matrix with a tile structure stores only the
+  // tiles some kernel reads; tmap_off[i] = -1 for a dense packed-lower one.
+  // A mapped matrix keeps its eliminated columns at off[i] (nlead[i] tiles)
+  // and its trailing (interface) block, packed like a matrix of its own, in
+  // one region after every matrix's leading part, from slot tslot0[i] on:
+  // the trailing blocks of the job lie back to back.
+  std::vector<int32_t> tmap;
+  std::vector<int64_t> tmap_off;
+  std::vector<int64_t> nlead;   // tiles stored at off[i] (every tile of a dense matrix)
+  std::vector<int64_t> tslot0;  // first slot of the trailing block (mapped matrices), else -1
+  int32_t* d_tmap = nullptr;
+  int64_t* d_tmap_off = nullptr;
+  int64_t slot(size_t i, int r, int s) const {
+    return tile_slot(tmap.empty() ? nullptr : tmap.data(), tmap_off.data(), (int)i, r, s, nt[i]);
+  }
+  // The trailing block of matrix i from tile t0 on (its interface block;
+  // t0 = e1 for a mapped matrix) as a tile-packed matrix: element offset,
+  // tiles per side, first tile.
+  void trailing(size_t i, int t0, int64_t& o, int32_t& n, int32_t& f) const {
+    if (tmap_off[i] >= 0) {
+      o = off[i] + tslot0[i] * TE;
+      n = nt[i] - t0;
+      f = 0;
+    } else {
+      o = off[i];
+      n = nt[i];
+      f = t0;
+    }
+  }
 };
 
 // A batched tile-block matrix-vector product.
@@ -160,8 +189,10 @@ struct LevelDev {
   std::vector<TrsvDesc> trsv_h;
   std::vector<int32_t> trsv_lvl;
   std::vector<int32_t> tr_rptr, tr_rcol, tr_cptr, tr_crow;
+  std::vector<int32_t> tr_rslot, tr_cslot;  // storage slot of each listed tile
   TrsvDesc* d_trsv = nullptr;
   int32_t *d_tr_rptr = nullptr, *d_tr_rcol = nullptr, *d_tr_cptr = nullptr, *d_tr_crow = nullptr;
+  int32_t *d_tr_rslot = nullptr, *d_tr_cslot = nullptr;
   // tile-list products over nonzero tiles of the level-1 factor: L_GI and
   // L_GI^T (condensation, recovery) and, per dissection height, the coupling of
   // a height's groups to lower groups (forward) or higher groups (backward)
@@ -188,6 +219,7 @@ struct LevelDev {
   std::vector<ConsDesc> cons_h;
   ConsDesc* d_cons = nullptr;
   int32_t* d_ccols = nullptr;
+  std::vector<int32_t> ccols_h;
   std::vector<DiagSeg> ksegs_h, msegs_h;
   DiagSeg* d_ksegs = nullptr;
   DiagSeg* d_msegs = nullptr;
@@ -553,6 +585,8 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
   D.tr_rcol.clear();
   D.tr_cptr.clear();
   D.tr_crow.clear();
+  D.tr_rslot.clear();
+  D.tr_cslot.clear();
   D.lgiN = LevelDev::TileList{};
   D.lgiT = LevelDev::TileList{};
   D.trF.clear();
@@ -565,7 +599,12 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
     const SubPlan& S = P.subs[b];
     const int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS), nt = D.K.nt[b];
     const int64_t aoff = D.K.off[b], io = D.iofs[b], go = D.gofs[b];
-    auto tile = [&](int r, int c) { return aoff + tile_index(r, c, nt) * TE; };
+    bool unstored = false;
+    auto tile = [&](int r, int c) {
+      const int64_t q = D.K.slot(b, r, c);
+      unstored = unstored || q < 0;
+      return aoff + q * TE;
+    };
     cols.assign(tI, {});
     for (int k = 0; k < tI; ++k) {
       if (!S.sptr.empty()) {
@@ -608,7 +647,12 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
     for (int k = 0; k < tI; ++k) {
       D.tr_cptr.push_back((int32_t)D.tr_crow.size());
       for (int32_t r : cols[k])
-        if (r < tI && grp[r] == grp[k]) D.tr_crow.push_back(r);
+        if (r < tI && grp[r] == grp[k]) {
+          D.tr_crow.push_back(r);
+          const int64_t q = D.K.slot(b, r, k);
+          unstored = unstored || q < 0;
+          D.tr_cslot.push_back((int32_t)q);
+        }
     }
     D.tr_cptr.push_back((int32_t)D.tr_crow.size());
     rcnt.assign(tI + 1, 0);
@@ -616,9 +660,14 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
     for (int r = 0; r < tI; ++r) rcnt[r + 1] += rcnt[r];
     const int32_t r0 = (int32_t)D.tr_rcol.size();
     D.tr_rcol.resize(D.tr_rcol.size() + (D.tr_crow.size() - c0));
+    D.tr_rslot.resize(D.tr_rcol.size());
     for (int r = 0; r <= tI; ++r) D.tr_rptr.push_back(r0 + rcnt[r]);
     for (int k = 0; k < tI; ++k)
-      for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) D.tr_rcol[r0 + rcnt[D.tr_crow[q]]++] = k;
+      for (int32_t q = D.tr_cptr[p_col + k]; q < D.tr_cptr[p_col + k + 1]; ++q) {
+        const int32_t pos = r0 + rcnt[D.tr_crow[q]]++;
+        D.tr_rcol[pos] = k;
+        D.tr_rslot[pos] = D.tr_cslot[q];
+      }
     for (size_t g = 0; g < g0v.size(); ++g) {
       if (g1v[g] <= g0v[g]) continue;
       if ((int)by_h.size() <= hgt[g]) by_h.resize(hgt[g] + 1);
@@ -664,6 +713,7 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
         D.lgiN.o.push_back(OutRef{go + (int64_t)r * TS, q0, (int32_t)D.lgiN.t.size()});
       }
     }
+    if (unstored) return fail(MLBDDC_E_ARG, "internal layout check failed: a factor tile of the solves is not stored");
   }
   D.trsv_lvl.assign(1, 0);
   for (auto& v : by_h) {
@@ -680,6 +730,8 @@ mlbddc_status Handle::build_trsv(LevelDev& D) {
   if ((st = upload(&D.d_tr_rcol, D.tr_rcol))) return st;
   if ((st = upload(&D.d_tr_cptr, D.tr_cptr))) return st;
   if ((st = upload(&D.d_tr_crow, D.tr_crow))) return st;
+  if ((st = upload(&D.d_tr_rslot, D.tr_rslot))) return st;
+  if ((st = upload(&D.d_tr_cslot, D.tr_cslot))) return st;
   int64_t pmax = 1;
   auto up = [&](LevelDev::TileList& T) -> mlbddc_status {
     pmax = std::max<int64_t>(pmax, (int64_t)T.t.size());
@@ -703,7 +755,8 @@ void Handle::run_trsv(LevelDev& D, bool transposed) {
     launch_tile_list_mv(stream, transposed, C.dt, (int64_t)C.t.size(), C.dout, (int64_t)C.o.size(), (const double*)D.K.buf,
                         D.wI, D.tl_partial, D.wI, -1.0, true);
     launch_trsv(stream, transposed, D.d_trsv + D.trsv_lvl[h], D.trsv_lvl[h + 1] - D.trsv_lvl[h], (const double*)D.K.buf,
-                (const double*)D.K.inv, D.d_tr_rptr, D.d_tr_rcol, D.d_tr_cptr, D.d_tr_crow, D.wI);
+                (const double*)D.K.inv, D.d_tr_rptr, D.d_tr_rcol, D.d_tr_rslot, D.d_tr_cptr, D.d_tr_crow, D.d_tr_cslot,
+                D.wI);
   }
 }
 
@@ -724,61 +777,91 @@ int Handle::pick_panel(int job, bool fp32, int ntmax) const {
   return best > 0 ? best : 4;
 }
 
-// Matrix layout and storage of a job (J.nt and the items' e1, e2 set): the
-// matrices are zeroed on the upload stream right away, while the host keeps
-// preparing (the upload fence orders this before the assembly).
+// Matrix layout and storage of a job (J.nt and the items' e1, e2 and tile
+// structure set): the matrices are zeroed on the upload stream right away,
+// while the host keeps preparing (the upload fence orders this before the
+// assembly).  A matrix with a tile structure stores only the tiles that the
+// factorization, the assembly and the solves read (read_before_write_tiles):
+// the tiles of its eliminated columns in the order listed there, then, in a
+// region shared by the job's mapped matrices, its trailing block packed like
+// a matrix of its own.
 mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
   J.fp32 = fp32;
   const size_t esz = fp32 ? 4 : 8;
-  J.off.resize(J.nt.size());
-  J.inv_off.resize(J.nt.size());
+  const int ni = (int)J.nt.size();
+  J.off.resize(ni);
+  J.inv_off.resize(ni);
+  J.tmap_off.assign(ni, -1);
+  J.nlead.resize(ni);
+  J.tslot0.assign(ni, -1);
+  int64_t msz = 0;
+  for (int i = 0; i < ni; ++i)
+    if (J.items[i].sptr) {
+      J.tmap_off[i] = msz;
+      msz += packed_tiles(J.nt[i]);
+    }
+  J.tmap.assign(msz, -1);
+  const int T = std::min(16, std::max(1, ni / 4));
+  parallel_run(T, [&](int t) {  // the leading tiles of every matrix
+    for (int i = ni * t / T; i < ni * (t + 1) / T; ++i) {
+      if (J.tmap_off[i] < 0) {
+        J.nlead[i] = packed_tiles(J.nt[i]);
+        continue;
+      }
+      int32_t* m = J.tmap.data() + J.tmap_off[i];
+      const int nt = J.nt[i], e1 = J.items[i].e1;
+      int32_t next = 0;
+      read_before_write_tiles(J.items[i], [&](int r0, int k, int count) {
+        if (k < e1)
+          for (int c = 0; c < count; ++c) m[tile_index(r0 + c, k, nt)] = next++;
+      });
+      J.nlead[i] = next;
+    }
+  });
   int64_t tot = 0, itot = 0;
-  for (size_t i = 0; i < J.nt.size(); ++i) {
+  for (int i = 0; i < ni; ++i) {
     J.off[i] = tot;
-    tot += packed_tiles(J.nt[i]) * TE;
+    tot += J.nlead[i] * TE;
     J.inv_off[i] = itot;
     itot += (int64_t)(J.items[i].e1 + J.items[i].e2) * TE;
   }
+  for (int i = 0; i < ni; ++i)  // the trailing blocks, back to back
+    if (J.tmap_off[i] >= 0) {
+      J.tslot0[i] = (tot - J.off[i]) / TE;
+      tot += packed_tiles(J.nt[i] - J.items[i].e1) * TE;
+    }
+  if (tot / TE >= INT32_MAX) return fail(MLBDDC_E_ARG, "matrix job too large for 32-bit tile slots");
+  parallel_run(T, [&](int t) {
+    for (int i = ni * t / T; i < ni * (t + 1) / T; ++i) {
+      if (J.tmap_off[i] < 0) continue;
+      int32_t* m = J.tmap.data() + J.tmap_off[i];
+      const int nt = J.nt[i], e1 = J.items[i].e1;
+      for (int c = e1; c < nt; ++c)
+        for (int r = c; r < nt; ++r) m[tile_index(r, c, nt)] = (int32_t)(J.tslot0[i] + tile_index(r - e1, c - e1, nt - e1));
+    }
+  });
   J.elems = tot;
   J.inv_elems = itot;
+  if (verbose && msz > 0) {
+    int64_t dense = 0;
+    for (int i = 0; i < ni; ++i) dense += packed_tiles(J.nt[i]);
+    std::fprintf(stderr, "[mlbddc setup]     tile-mapped storage: %lld of %lld tiles (%.1f%%)\n", (long long)(tot / TE),
+                 (long long)dense, 100.0 * (double)(tot / TE) / (double)std::max<int64_t>(dense, 1));
+  }
   void* b = nullptr;
   void* iv = nullptr;
-  mlbddc_status st = fp32 ? dalloc((float**)&b, tot) : dalloc((double**)&b, tot);
+  mlbddc_status st = fp32 ? dalloc((float**)&b, std::max<int64_t>(tot, 1)) : dalloc((double**)&b, std::max<int64_t>(tot, 1));
   if (st) return st;
   st = fp32 ? dalloc((float**)&iv, std::max<int64_t>(itot, 1)) : dalloc((double**)&iv, std::max<int64_t>(itot, 1));
   if (st) return st;
   J.buf = b;
   J.inv = iv;
   if ((st = ensure_ustream())) return st;
-  bool structured = false;
-  for (const FactorItemDesc& it : J.items) structured = structured || it.sptr;
-  if (!structured) {
-    HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
-    return MLBDDC_OK;
+  if (tot > 0) HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
+  if (msz > 0) {
+    if ((st = upload(&J.d_tmap, J.tmap))) return st;
+    if ((st = upload(&J.d_tmap_off, J.tmap_off))) return st;
   }
-  // tile-structured matrices: only the tiles some kernel reads before writing
-  std::vector<ZeroRun> runs;
-  const int ni = (int)J.nt.size();
-  std::vector<std::vector<ZeroRun>> per(ni);  // per matrix, built on several threads
-  parallel_run(std::min(16, std::max(1, ni / 4)), [&](int t) {
-    const int T = std::min(16, std::max(1, ni / 4));
-    for (int i = ni * t / T; i < ni * (t + 1) / T; ++i) {
-      const int nt = J.nt[i];
-      auto add = [&](int64_t off_elems, int64_t ntiles) {  // at most 8 tiles per workgroup
-        for (int64_t q = 0; q < ntiles; q += 8)
-          per[i].push_back(ZeroRun{off_elems * (int64_t)esz + q * TE * (int64_t)esz,
-                                   std::min<int64_t>(8, ntiles - q) * TE * (int64_t)esz});
-      };
-      if (!J.items[i].sptr) add(J.off[i], packed_tiles(nt));
-      else
-        read_before_write_tiles(J.items[i], [&](int r0, int k, int count) { add(J.off[i] + tile_index(r0, k, nt) * TE, count); });
-    }
-  });
-  for (auto& v : per) runs.insert(runs.end(), v.begin(), v.end());
-  ZeroRun* d_runs = nullptr;
-  if ((st = upload(&d_runs, runs))) return st;
-  launch_zero_runs(ustream, d_runs, (int64_t)runs.size(), J.buf);
-  HIPCHK(hipGetLastError());
   return MLBDDC_OK;
 }
 
@@ -795,6 +878,7 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
+  if (!J.tmap.empty()) J.panel = std::min(J.panel, 64);  // k_tile_mm holds a task's tile slots in one wavefront
   if (ntmax >= panel_nt[job]) {  // report the panel width of the largest job of the set-up
     panel_nt[job] = ntmax;
     pdata.panel[job] = J.panel;
@@ -814,7 +898,7 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
   if (prof) HIPCHK(hipStreamSynchronize(stream));  // job time excludes earlier queued work
   const double tj0 = prof ? now() : 0.0;
-  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err};
+  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off};
   const size_t nl = J.sched.launches.size();
   if (prof)
     while (events.size() < 2 * nl) {
@@ -1012,7 +1096,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       const SubPlan& S = P.subs[b];
       int32_t nt = D.K.nt[b];
       auto add = [&](int64_t r0, int64_t c0, int64_t cnt, double v) {
-        if (cnt > 0) D.ksegs_h.push_back(DiagSeg{D.K.off[b], nt, (int32_t)r0, (int32_t)c0, (int32_t)cnt, v});
+        if (cnt > 0) D.ksegs_h.push_back(DiagSeg{D.K.off[b], nt, (int32_t)r0, (int32_t)c0, (int32_t)cnt, v, b});
       };
       for (size_t q = 0; q + 1 < S.padI.size(); q += 2) add(S.padI[q], S.padI[q], S.padI[q + 1], 1.0);
       add(S.nIp + S.nG, S.nIp + S.nG, S.nGp - S.nG, 1.0);
@@ -1065,10 +1149,14 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       parallel_run(std::min(16, ns), [&](int t) {
         for (int b = t; b < ns; b += std::min(16, ns)) {
           const SubPlan& S = P.subs[b];
-          for (int64_t k = 0; k < S.nGp; ++k)
-            gdiag[D.gofs[b] + k] = D.K.off[b] + packed_offset(S.nIp + k, S.nIp + k, D.K.nt[b]);
+          int64_t o;
+          int32_t n, f;
+          D.K.trailing(b, (int)(S.nIp / TS), o, n, f);
+          for (int64_t k = 0; k < S.nGp; ++k) gdiag[D.gofs[b] + k] = o + packed_offset(f * TS + k, f * TS + k, n);
         }
       });
+      for (int64_t v : gdiag)
+        if (v < 0 || v >= D.K.elems) return fail(MLBDDC_E_ARG, "internal layout check failed: interface diagonal position");
       if ((st = upload(&D.d_gdiag_pos, gdiag))) return st;
     }
     if ((st = dalloc(&D.gd, std::max<int64_t>(D.nG_flat, 1)))) return st;
@@ -1153,8 +1241,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
         const SubPlan& S = P.subs[b];
         int tI = (int)(S.nIp / TS), tG = (int)(S.nGp / TS);
         if (li == 0) {
-          s.push_back(MvDesc{D.K.off[b], D.K.nt[b], tI, tG, tI, tG, D.gofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nG,
-                             (int32_t)S.nG});
+          int64_t o;
+          int32_t n, f;
+          D.K.trailing(b, tI, o, n, f);
+          s.push_back(MvDesc{o, n, f, tG, f, tG, D.gofs[b], D.gofs[b], 0, nullptr, (int32_t)S.nG, (int32_t)S.nG});
         } else if (tI > 0) {
           int tId = tI + tG;
           pre.push_back(MvDesc{D.K.off[b], D.K.nt[b], tId, tI, tId, tI, D.iofs[b], D.iofs[b], 0, nullptr, (int32_t)S.nI,
@@ -1218,7 +1308,10 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
         int tG = (int)(S.nGp / TS);
-        D.copy_h.push_back(CopyDesc{D.K.off[b], D.K.nt[b], (int32_t)(S.nIp / TS), D.M.off[b], D.M.nt[b], tG});
+        int64_t ko;
+        int32_t kn, kf;
+        D.K.trailing(b, (int)(S.nIp / TS), ko, kn, kf);
+        D.copy_h.push_back(CopyDesc{ko, kn, kf, D.M.off[b], D.M.nt[b], tG});
         D.copy_max = std::max(D.copy_max, tG);
         auto add = [&](int64_t r0, int64_t c0, int64_t cnt, double v) {
           if (cnt > 0) D.msegs_h.push_back(DiagSeg{D.M.off[b], D.M.nt[b], (int32_t)r0, (int32_t)c0, (int32_t)cnt, v});
@@ -1230,14 +1323,15 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       for (auto& s : D.msegs_h) D.mseg_max = std::max(D.mseg_max, s.count);
       if ((st = upload(&D.d_msegs, D.msegs_h))) return st;
       if ((st = upload(&D.d_copy, D.copy_h))) return st;
-      std::vector<int32_t> ccols;
+      std::vector<int32_t>& ccols = D.ccols_h;
+      ccols.clear();
       for (int b = 0; b < ns; ++b) {
         const SubPlan& S = P.subs[b];
         for (int c = 0; c < S.nc; ++c) {
           ConsDesc cd;
-          cd.kdiag_off = D.K.off[b];
-          cd.k_nt = D.K.nt[b];
-          cd.k_g0 = (int32_t)S.nIp;
+          int32_t kf;
+          D.K.trailing(b, (int)(S.nIp / TS), cd.kdiag_off, cd.k_nt, kf);
+          cd.k_g0 = kf * TS;
           cd.p_off = D.M.off[b];
           cd.p_nt = D.M.nt[b];
           cd.c_row0 = (int32_t)S.nGp + c;
@@ -1368,8 +1462,45 @@ mlbddc_status Handle::validate_level(int li, int part) {
   auto job_ok = [&](const Job& J) -> mlbddc_status {
     if (J.nt.empty()) return MLBDDC_OK;
     const size_t ni = J.nt.size();
+    if (J.tmap_off.size() != ni || J.nlead.size() != ni || J.tslot0.size() != ni) return bad(L + "tile maps");
+    int64_t lead_end = 0, trail_end = -1;  // the leading parts, then the trailing blocks, in item order without overlap
     for (size_t i = 0; i < ni; ++i) {
-      if (J.off[i] + packed_tiles(J.nt[i]) * TE > J.elems) return bad(L + "job matrix extent");
+      if (J.off[i] < lead_end || J.nlead[i] < 0) return bad(L + "job matrix extent");
+      lead_end = J.off[i] + J.nlead[i] * TE;
+      if (lead_end > J.elems) return bad(L + "job matrix extent");
+      if (J.tmap_off[i] >= 0) {  // a tile map: slots in range, the trailing block packed on its own
+        const int nt = J.nt[i], e1 = J.items[i].e1;
+        if (!J.items[i].sptr || J.tmap_off[i] + packed_tiles(nt) > (int64_t)J.tmap.size() || e1 > nt)
+          return bad(L + "tile map extent");
+        const int64_t t0 = J.off[i] + J.tslot0[i] * TE, t1 = t0 + packed_tiles(nt - e1) * TE;
+        if (J.tslot0[i] < 0 || t0 < std::max(trail_end, (int64_t)0) || t1 > J.elems) return bad(L + "tile map trailing block");
+        trail_end = t1;
+        const int32_t* m = J.tmap.data() + J.tmap_off[i];
+        for (int c = 0; c < e1; ++c)
+          for (int r = c; r < nt; ++r) {
+            const int32_t q = m[tile_index(r, c, nt)];
+            if (q < -1 || q >= J.nlead[i]) return bad(L + "tile map entry");
+          }
+        for (int c = e1; c < nt; ++c)
+          for (int r = c; r < nt; ++r)
+            if (m[tile_index(r, c, nt)] != J.tslot0[i] + tile_index(r - e1, c - e1, nt - e1))
+              return bad(L + "tile map trailing block");
+        for (int k = 0; k < e1; ++k)  // the structure's tiles and the diagonal
+          if (m[tile_index(k, k, nt)] < 0) return bad(L + "tile map misses a tile");
+        for (int k = 0; k < e1; ++k)
+          for (int32_t q = J.items[i].sptr[k]; q < J.items[i].sptr[k + 1]; ++q)
+            if (J.items[i].srow[q] > k && J.items[i].srow[q] < nt && m[tile_index(J.items[i].srow[q], k, nt)] < 0)
+              return bad(L + "tile map misses a tile");
+      } else if (J.nlead[i] != packed_tiles(J.nt[i]) || J.tslot0[i] != -1) {
+        return bad(L + "job matrix extent");
+      }
+    }
+    for (size_t i = 0; i < ni; ++i)  // the first trailing block lies after every leading part
+      if (J.tmap_off[i] >= 0) {
+        if (J.off[i] + J.tslot0[i] * TE < lead_end) return bad(L + "tile map trailing block");
+        break;
+      }
+    for (size_t i = 0; i < ni; ++i) {
       if (J.inv_off[i] + (int64_t)(J.items[i].e1 + J.items[i].e2) * TE > std::max<int64_t>(J.inv_elems, 1))
         return bad(L + "inverse tile extent");
       if (J.items[i].e1 + J.items[i].e2 > J.nt[i]) return bad(L + "elimination beyond the matrix");
@@ -1407,6 +1538,15 @@ mlbddc_status Handle::validate_level(int li, int part) {
           if (it >= ni) return "task item";
           int nt = J.nt[it], ee = J.items[it].e1 + J.items[it].e2;
           if (r >= nt || c > r) return "task tile";
+          if (J.tmap_off[it] >= 0) {  // every tile the task reads or writes is stored
+            const int32_t* m = J.tmap.data() + J.tmap_off[it];
+            if (m[tile_index(r, c, nt)] < 0) return "task tile not stored";
+            if (F.kind == L_INPANEL || F.kind == L_TRAIL) {
+              if (kl - kf + 1 > 64 || kl >= c) return "task columns";
+              for (int kk = kf; kk <= kl; ++kk)
+                if (m[tile_index(r, kk, nt)] < 0 || m[tile_index(c, kk, nt)] < 0) return "task tile not stored";
+            }
+          }
           switch (F.kind) {
             case L_DIAG: if (r != c || c >= ee) return "diag task"; break;
             case L_PANEL: if (r <= c || c >= ee) return "panel task"; break;
@@ -1428,9 +1568,12 @@ mlbddc_status Handle::validate_level(int li, int part) {
     return MLBDDC_OK;
   };
   auto seg_ok = [&](const std::vector<DiagSeg>& v) {
-    for (const DiagSeg& g : v)
+    for (const DiagSeg& g : v) {
       if (g.row0 < g.col0 || (int64_t)g.row0 + g.count > (int64_t)g.nt * TS || (int64_t)g.col0 + g.count > (int64_t)g.nt * TS)
         return false;
+      // a segment of a tile-mapped matrix lies on its diagonal (diagonal tiles are always stored)
+      if (g.item >= 0 && (g.item >= (int32_t)D.K.nt.size() || (D.K.tmap_off[g.item] >= 0 && g.row0 != g.col0))) return false;
+    }
     return true;
   };
   mlbddc_status st;
@@ -1441,11 +1584,25 @@ mlbddc_status Handle::validate_level(int li, int part) {
     const int T = (int)std::min<int64_t>(16, std::max<int64_t>(1, ne / 4096));
     std::vector<const char*> whys(T, nullptr);
     parallel_run(T, [&](int t) {
+      std::vector<int32_t> tl;  // distinct tiles of an element's DOFs
       for (int64_t e = ne * t / T; e < ne * (t + 1) / T; ++e) {
         int b = P.el_sub[e];
+        if (b < 0 || b >= (int64_t)P.subs.size()) { whys[t] = "element subdomain"; return; }
         int64_t nK = (int64_t)D.K.nt[b] * TS;
         for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
           if (P.el_local[j] < -1 || (int64_t)P.el_local[j] + P.ndof > nK) { whys[t] = "element map"; return; }
+        if (D.K.tmap_off[b] >= 0) {  // every tile the element's entries fall in is stored
+          tl.clear();
+          for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
+            if (P.el_local[j] >= 0)
+              for (int32_t q : {P.el_local[j] / TS, (P.el_local[j] + P.ndof - 1) / TS})  // a node's DOFs span <= 2 tiles
+                if (std::find(tl.begin(), tl.end(), q) == tl.end()) tl.push_back(q);
+          const int32_t* m = D.K.tmap.data() + D.K.tmap_off[b];
+          const int nt = D.K.nt[b];
+          for (int32_t a : tl)
+            for (int32_t c : tl)
+              if (a >= c && m[tile_index(a, c, nt)] < 0) { whys[t] = "element tile not stored"; return; }
+        }
         if (li > 0) {
           const LevelPlan& PP = *lev[li - 1].P;
           int64_t nloc = (int64_t)(P.el_local_ptr[e + 1] - P.el_local_ptr[e]) * P.ndof;
@@ -1510,10 +1667,14 @@ mlbddc_status Handle::validate_level(int li, int part) {
         const int32_t b0 = D.tr_cptr[t.p_col + k], b1 = D.tr_cptr[t.p_col + k + 1];
         if (a0 < 0 || a1 < a0 || a1 > (int64_t)D.tr_rcol.size() || b0 < 0 || b1 < b0 || b1 > (int64_t)D.tr_crow.size())
           return bad(L + "triangular solve lists");
+        if (D.tr_rslot.size() != D.tr_rcol.size() || D.tr_cslot.size() != D.tr_crow.size())
+          return bad(L + "triangular solve lists");
         for (int32_t q = a0; q < a1; ++q)
-          if (D.tr_rcol[q] < 0 || D.tr_rcol[q] >= k) return bad(L + "triangular solve row list");
+          if (D.tr_rcol[q] < 0 || D.tr_rcol[q] >= k || D.tr_rslot[q] < 0 || t.a_off + (int64_t)(D.tr_rslot[q] + 1) * TE > D.K.elems)
+            return bad(L + "triangular solve row list");
         for (int32_t q = b0; q < b1; ++q)
-          if (D.tr_crow[q] <= k || D.tr_crow[q] >= t.a_nt || t.v_off + (int64_t)(D.tr_crow[q] + 1) * TS > D.nI_flat)
+          if (D.tr_crow[q] <= k || D.tr_crow[q] >= t.a_nt || t.v_off + (int64_t)(D.tr_crow[q] + 1) * TS > D.nI_flat ||
+              D.tr_cslot[q] < 0 || t.a_off + (int64_t)(D.tr_cslot[q] + 1) * TE > D.K.elems)
             return bad(L + "triangular solve column list");
       }
     }
@@ -1540,7 +1701,17 @@ mlbddc_status Handle::validate_level(int li, int part) {
       if (rows != (int64_t)D.cons_h.size()) return bad(L + "constraint rows vs coarse DOFs");
     }
     for (const CopyDesc& c : D.copy_h)
-      if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt) return bad(L + "copy descriptor");
+      if (c.src_t0 + c.nblk > c.src_nt || c.nblk > c.dst_nt || c.src_off + packed_tiles(c.src_nt) * TE > D.K.elems ||
+          c.dst_off + packed_tiles(c.dst_nt) * TE > D.M.elems)
+        return bad(L + "copy descriptor");
+    for (const ConsDesc& c : D.cons_h) {
+      int32_t mx = -1;
+      if (c.ptr0 < 0 || c.ptr1 < c.ptr0 || c.ptr1 > (int32_t)D.ccols_h.size()) return bad(L + "constraint descriptor");
+      for (int32_t q = c.ptr0; q < c.ptr1; ++q) mx = std::max(mx, D.ccols_h[q]);
+      if (c.kdiag_off + packed_tiles(c.k_nt) * TE > D.K.elems || (int64_t)c.k_g0 + mx >= (int64_t)c.k_nt * TS ||
+          c.p_off + packed_tiles(c.p_nt) * TE > D.M.elems)
+        return bad(L + "constraint descriptor");
+    }
     for (size_t b = 0; b < P.subs.size(); ++b) {
       const SubPlan& S = P.subs[b];
       for (int32_t col : S.crow_col)
@@ -1575,15 +1746,18 @@ mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
     const double* ekc = li == 0 ? nullptr : lev[li - 1].kc_compact;
     if (D.kfp32)
       launch_assemble<float>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                             d_scale, D.d_ekc_off, ekc, (float*)D.K.buf);
+                             d_scale, D.d_ekc_off, ekc, (float*)D.K.buf, D.K.d_tmap, D.K.d_tmap_off);
     else
       launch_assemble<double>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                              d_scale, D.d_ekc_off, ekc, (double*)D.K.buf);
+                              d_scale, D.d_ekc_off, ekc, (double*)D.K.buf, D.K.d_tmap,
+                              D.K.d_tmap_off);
   }
   if (D.kfp32)
-    launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf);
+    launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf, D.K.d_tmap,
+                           D.K.d_tmap_off);
   else
-    launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf);
+    launch_set_diag<double>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (double*)D.K.buf, D.K.d_tmap,
+                            D.K.d_tmap_off);
   // the assembled (sub-assembled) interface diagonal, kept for the weights:
   // the factorization overwrites it with that of the Schur complement
   if (!P.top) {

@@ -40,7 +40,7 @@ from oracle.bddc import MultilevelBDDC  # noqa: E402
 from oracle.direct import direct_solve  # noqa: E402
 from oracle.grad import compliance_gradient  # noqa: E402
 from oracle.krylov import lanczos_extremes, pcg  # noqa: E402
-from workloads import box_workload, config  # noqa: E402
+from workloads import box_workload, config, large_subdomains  # noqa: E402
 from workloads.gen import uniform_cuts  # noqa: E402
 
 R_SEED = 2024
@@ -59,16 +59,6 @@ CASES = {
     "elasticity80_uneven_L3": (lambda: config(4), None),
     "elasticity40_8sub20_L2": (lambda: large_subdomains(), None),
 }
-
-
-def large_subdomains():
-    """Subdomains of 20^3 elements (27,783 DOFs each, the paper's tens of
-    thousands of unknowns per subdomain): 40^3 elements, 2x2x2 subdomains,
-    E = 10^(2U), U ~ U(0,1) from default_rng(3), 2 levels."""
-    n = 40
-    young = 10.0 ** (2.0 * np.random.default_rng(3).random(n ** 3))
-    return box_workload("elasticity3d_40cube_8sub20_L2", "elasticity", (n,) * 3, [uniform_cuts(n, 2)] * 3,
-                        young=young, seed=3)
 
 
 def grad_reduced():

@@ -22,7 +22,9 @@ calls only the oracle.  For every workload at its full size:
 Workloads: 48^3 (64 subdomains of 12^3) at 2 and 3 levels; 96^3 with 1728
 subdomains of 8^3 and log-uniform moduli at 3 levels (4x4x4 level-2 groups)
 and at 4 levels (1728 / 216 / 27); 80^3 cut by seeded random planes into 512
-uneven boxes of 4..16 elements per side, 3 levels.
+uneven boxes of 4..16 elements per side, 3 levels; 40^3 with 8 subdomains of
+20^3 (27,783 DOFs each), 2 levels, where the factors keep only the tiles of
+their nested-dissection structure (the device memory is printed).
 """
 
 import json
@@ -32,7 +34,7 @@ import numpy as np
 import pytest
 import torch
 
-from workloads import config
+from workloads import config, large_subdomains
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +45,7 @@ CASES = {
     "elasticity96_L3": lambda: config(3, levels=3),
     "elasticity96_L4": lambda: config(3, levels=4),
     "elasticity80_uneven_L3": lambda: config(4),
+    "elasticity40_8sub20_L2": large_subdomains,
 }
 RTOL64 = 1e-10
 _problems = {}
@@ -84,7 +87,11 @@ def test_config_fp64(name):
     print(f"[config] {name} fp64", flush=True)
     gold = _load(name)
     prob, f = _problem(name)
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
     s = Solver(use_graph=True).setup(prob)
+    torch.cuda.synchronize()
+    print(f"  device memory of the solver: {(torch.cuda.memory_allocated() - m0) / 2**30:.2f} GiB", flush=True)
     L = gold["levels"]
     assert s.n_iface == gold["n_iface"] and s.n_dofs == gold["n_dofs"]
     assert [s.num_subdomains(l + 1) for l in range(L - 1)] == gold["subdomains"]

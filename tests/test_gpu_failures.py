@@ -14,6 +14,8 @@ fault or hang:
   goes back to it on destroy.
 """
 
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -104,6 +106,7 @@ def test_device_memory_from_torch_allocator():
     print("[allocator]", flush=True)
     w = _cube(3, 4)
     prob = Problem(w)
+    gc.collect()           # handles of earlier tests left in reference cycles release their blocks now, not mid-test
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     s = Solver(use_graph=True).setup(prob)

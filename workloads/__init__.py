@@ -15,5 +15,6 @@ from .gen import (  # noqa: F401
     random_cuts,
     box_workload,
     config,
+    large_subdomains,
     CONFIG_NAMES,
 )

@@ -208,6 +208,17 @@ def uniform_cuts(n: int, parts: int) -> np.ndarray:
     return np.arange(0, n + 1, n // parts)
 
 
+def large_subdomains(n: int = 40, parts: int = 2, seed: int = 3) -> Workload:
+    """Subdomains of (n/parts)^3 elements (20^3 by default: 27,783 DOFs each,
+    the tens of thousands of unknowns per subdomain of the paper's runs):
+    3D elasticity on n^3 elements, parts^3 box subdomains, 2 levels,
+    E = 10^(2U), U ~ U(0,1) from default_rng(seed)."""
+    young = 10.0 ** (2.0 * np.random.default_rng(seed).random(n ** 3))
+    sub = n // parts
+    return box_workload(f"elasticity3d_{n}cube_{parts ** 3}sub{sub}_L2", "elasticity", (n,) * 3,
+                        [uniform_cuts(n, parts)] * 3, young=young, seed=seed)
+
+
 CONFIG_NAMES = {
     1: "poisson2d_32x32_4x4sub_L2",
     2: "elasticity3d_48cube_64sub",
