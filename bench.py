@@ -158,7 +158,10 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
              lookahead: bool = False):
     import torch
     from paper_1201_5991_amd import Solver
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
     s = Solver(precision=precision, panel_tiles=panel, use_graph=graph, lookahead=lookahead)
+    mem = None
     t_cold = None
     for _ in range(warmup):
         tc = time.perf_counter()
@@ -167,6 +170,7 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
         torch.cuda.synchronize()
         if t_cold is None:
             t_cold = time.perf_counter() - tc
+            mem = torch.cuda.memory_allocated() - m0   # the handle's device blocks (set-up + solve)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = None
@@ -227,6 +231,7 @@ def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, pan
         "apply_alg_GBps": nbytes["apply"] / t_apply * 1e-9,
         "schur_ms": t_schur * 1e3,
         "schur_alg_GBps": nbytes["schur"] / t_schur * 1e-9,
+        "device_memory_GB": None if mem is None else mem * 1e-9,
         "profile": prof,
     }
     s.destroy()

@@ -5,7 +5,8 @@ Follows section 2 and the body of Algorithm 1 of the paper:
 * local subdomain matrices K_i by sub-assembly of element matrices;
 * the interface = level nodes shared by two or more subdomains;
 * interface classification into faces / edges / vertices (globs = classes of
-  interface nodes with the same set of subdomains) and corner selection;
+  interface nodes with the same set of subdomains, each split into the parts
+  that elements connect) and corner selection;
 * the constraint matrix C_i (one row per constraint: corner values, and
   arithmetic averages over edges and faces, per component);
 * the weights E_i that distribute the interface residual;
@@ -14,10 +15,17 @@ Follows section 2 and the body of Algorithm 1 of the paper:
 
 Readings where the paper is silent (kept identical in the GPU library):
 
-* corner selection on box partitions: a glob shared by three or more
-  subdomains that consists of a single node is a corner; in 3D a glob of two
-  subdomains is a face and one of three or more subdomains with several nodes
-  is an edge; in 2D a glob of two subdomains is an edge;
+* a glob is a connected part of a class of interface nodes with the same
+  subdomain set, two nodes of a class being connected when one element holds
+  both (on box partitions every class is connected; on general partitions two
+  subdomains can touch in separate patches, each of which gets its own
+  averages);
+* corner selection: a glob shared by three or more subdomains that consists
+  of a single node is a corner; in 3D a glob of two subdomains is a face and
+  one of three or more subdomains with several nodes is an edge; in 2D a glob
+  of two subdomains is an edge (no further corners are selected on general
+  partitions: the face-based algorithm the paper uses is not described
+  there);
 * Dirichlet nodes are removed before the interface is formed, so a glob that
   touches the Dirichlet boundary keeps only its free nodes;
 * averages use equal weights 1/m over the m nodes of a glob, one row per
@@ -124,8 +132,12 @@ class Level:
             for n in iface_nodes:
                 globs.append(Glob(np.array([n]), tuple(node_subs[n]), CORNER))
         else:
+            part = self._connected_parts(blocks, groups)
             for subs, nodes in groups.items():
-                globs.append(Glob(np.array(sorted(nodes)), subs, classify(len(subs), len(nodes), dim)))
+                nodes = np.array(sorted(nodes))
+                for lab in np.unique(part[nodes]):
+                    g_nodes = nodes[part[nodes] == lab]
+                    globs.append(Glob(g_nodes, subs, classify(len(subs), len(g_nodes), dim)))
         globs.sort(key=lambda g: int(g.nodes[0]))
         n_coarse_nodes = 0
         for g in globs:
@@ -232,6 +244,34 @@ class Level:
         self.KC = KC
 
     # ------------------------------------------------------------------ Schur
+    def _connected_parts(self, blocks, groups) -> np.ndarray:
+        """Label of the connected part of every node: nodes of one class of
+        `groups` are joined when an element holds both."""
+        nd = self.ndof
+        cls = -np.ones(self.n_nodes, dtype=np.int64)
+        for c, nodes in enumerate(groups.values()):
+            cls[np.asarray(nodes, dtype=np.int64)] = c
+        rows, cols = [], []
+        for blk in blocks:
+            for edofs, _ in blk:
+                e = np.asarray(edofs)
+                nn = e.shape[1] // nd
+                # node of each element slot (its DOFs are node * nd + c; -1 where eliminated)
+                en = np.stack([e[:, k * nd:(k + 1) * nd].max(axis=1) for k in range(nn)], axis=1)
+                en = np.where(en >= 0, en // nd, -1)
+                for p in range(nn):
+                    for q in range(p + 1, nn):
+                        a, b = en[:, p], en[:, q]
+                        ok = (a >= 0) & (b >= 0)
+                        a, b = a[ok], b[ok]
+                        same = (cls[a] >= 0) & (cls[a] == cls[b])
+                        rows.append(a[same]); cols.append(b[same])
+        rows = np.concatenate(rows) if rows else np.zeros(0, dtype=np.int64)
+        cols = np.concatenate(cols) if cols else np.zeros(0, dtype=np.int64)
+        A = sp.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(self.n_nodes, self.n_nodes))
+        from scipy.sparse.csgraph import connected_components
+        return connected_components(A, directed=False)[1]
+
     def schur_local(self, i: int, v_loc: np.ndarray) -> np.ndarray:
         """S_i v = K_GG v - K_GI K_II^{-1} K_IG v (a discrete Dirichlet problem)."""
         y = self.KGG[i] @ v_loc

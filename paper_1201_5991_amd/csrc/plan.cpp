@@ -2,9 +2,11 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <iterator>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <unordered_map>
 #include <numeric>
 #include <thread>
@@ -420,6 +422,161 @@ void tile_structure(const LevelPlan& L, const SubPlan& S, int nd, int tI, int nt
   }
 }
 
+// Globs of a level: the classes of interface nodes with one subdomain set,
+// each split into its connected parts (two nodes of a class are connected
+// when one element holds both).  Every class has an owner, the first
+// subdomain of its set, which holds all its nodes; the owners form their
+// classes and split them along their own elements, on several threads.  A
+// class left in several parts by its owner's elements is joined again over
+// the elements of all its subdomains (the only elements holding its nodes).
+// Globs come out in no particular order; nodes increase within each.
+void build_globs(LevelPlan& L, const std::vector<int64_t>& node_iface, const std::vector<int64_t>& nptr,
+                 const std::vector<int32_t>& nsub, const std::vector<std::vector<int64_t>>& sub_nodes, Plan& plan) {
+  const int32_t ns = L.n_sub;
+  auto set_less = [&](int64_t a, int64_t b) {  // lexicographic order of the subdomain sets of nodes a, b
+    return std::lexicographical_compare(nsub.begin() + nptr[a], nsub.begin() + nptr[a + 1], nsub.begin() + nptr[b],
+                                        nsub.begin() + nptr[b + 1]);
+  };
+  auto set_equal = [&](int64_t a, int64_t b) {
+    return nptr[a + 1] - nptr[a] == nptr[b + 1] - nptr[b] &&
+           std::equal(nsub.begin() + nptr[a], nsub.begin() + nptr[a + 1], nsub.begin() + nptr[b]);
+  };
+  auto find = [](std::vector<int32_t>& par, int32_t x) {
+    while (par[x] != x) x = par[x] = par[par[x]];
+    return x;
+  };
+  std::vector<std::vector<Glob>> cand(ns);
+  std::vector<std::vector<char>> whole(ns);  // per candidate: its class is in one part at its owner
+  if ((int)plan.scratch.size() < plan_threads(ns)) plan.scratch.resize(plan_threads(ns));
+  parallel_ranges(ns, [&](int t, int64_t b0, int64_t b1) {
+    PlanScratch& W = plan.scratch[t];
+    W.ensure(L.n_nodes);
+    std::vector<int32_t>& loc = W.node_local;  // node -> index among the owned nodes, -1
+    std::vector<int64_t> own;
+    std::vector<int32_t> ord, cls, par, ii;
+    std::vector<std::array<int32_t, 3>> key;  // (class, part root, owned index)
+    for (int64_t b = b0; b < b1; ++b) {
+      own.clear();
+      for (int64_t n : sub_nodes[b])
+        if (node_iface[n] >= 0 && nsub[nptr[n]] == b) own.push_back(n);
+      const int32_t m = (int32_t)own.size();
+      if (m == 0) continue;
+      ord.resize(m);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        return set_less(own[x], own[y]) || (!set_less(own[y], own[x]) && x < y);
+      });
+      cls.assign(m, 0);
+      for (int32_t q = 1; q < m; ++q) cls[ord[q]] = cls[ord[q - 1]] + (set_equal(own[ord[q]], own[ord[q - 1]]) ? 0 : 1);
+      par.resize(m);
+      for (int32_t k = 0; k < m; ++k) {
+        loc[own[k]] = k;
+        par[k] = k;
+      }
+      for (int64_t e : L.subs[b].elems) {
+        ii.clear();
+        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+          const int64_t v = L.el_nodes[j];
+          if (v >= 0 && loc[v] >= 0) ii.push_back(loc[v]);
+        }
+        for (size_t q = 1; q < ii.size(); ++q)
+          for (size_t p = 0; p < q; ++p)
+            if (cls[ii[p]] == cls[ii[q]]) {
+              const int32_t x = find(par, ii[p]), y = find(par, ii[q]);
+              if (x != y) par[std::max(x, y)] = std::min(x, y);
+              break;
+            }
+      }
+      key.resize(m);
+      for (int32_t k = 0; k < m; ++k) key[k] = {cls[k], find(par, k), k};
+      std::sort(key.begin(), key.end());
+      for (int32_t q = 0; q < m;) {
+        int32_t q1 = q;
+        while (q1 < m && key[q1][0] == key[q][0]) ++q1;  // one class
+        const bool one = key[q][1] == key[q1 - 1][1];
+        for (int32_t r = q; r < q1;) {
+          int32_t r1 = r;
+          while (r1 < q1 && key[r1][1] == key[r][1]) ++r1;  // one part
+          Glob g;
+          const int64_t n0 = own[key[r][2]];
+          g.subs.assign(nsub.begin() + nptr[n0], nsub.begin() + nptr[n0 + 1]);
+          for (int32_t z = r; z < r1; ++z) g.nodes.push_back(own[key[z][2]]);
+          cand[b].push_back(std::move(g));
+          whole[b].push_back(one ? 1 : 0);
+          r = r1;
+        }
+        q = q1;
+      }
+      for (int64_t n : own) loc[n] = -1;
+    }
+  });
+  L.globs.clear();
+  std::vector<std::vector<int64_t>> rejoin;  // classes in several parts at their owner: all nodes
+  for (int32_t b = 0; b < ns; ++b) {
+    std::vector<int64_t>* cur = nullptr;
+    const std::vector<int32_t>* cur_subs = nullptr;
+    for (size_t c = 0; c < cand[b].size(); ++c) {
+      if (whole[b][c]) {
+        L.globs.push_back(std::move(cand[b][c]));
+        continue;
+      }
+      if (!cur || *cur_subs != cand[b][c].subs) {  // parts of one class are adjacent in cand[b]
+        rejoin.emplace_back();
+        cur = &rejoin.back();
+        cur_subs = &cand[b][c].subs;
+      }
+      cur->insert(cur->end(), cand[b][c].nodes.begin(), cand[b][c].nodes.end());
+    }
+  }
+  if (rejoin.empty()) return;
+  // classes split at their owner: union-find over the elements of all their subdomains
+  const int64_t ni = (int64_t)L.iface_dofs.size() / L.ndof;
+  std::vector<int32_t> rc(ni, -1), par(ni);
+  std::iota(par.begin(), par.end(), 0);
+  std::vector<char> sub_in(ns, 0);
+  for (size_t c = 0; c < rejoin.size(); ++c) {
+    std::sort(rejoin[c].begin(), rejoin[c].end());
+    for (int64_t n : rejoin[c]) rc[node_iface[n]] = (int32_t)c;
+    const int64_t n0 = rejoin[c][0];
+    for (int64_t q = nptr[n0]; q < nptr[n0 + 1]; ++q) sub_in[nsub[q]] = 1;
+  }
+  std::vector<int32_t> ii;
+  for (int32_t b = 0; b < ns; ++b) {
+    if (!sub_in[b]) continue;
+    for (int64_t e : L.subs[b].elems) {
+      ii.clear();
+      for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+        const int64_t v = L.el_nodes[j];
+        if (v >= 0 && node_iface[v] >= 0 && rc[node_iface[v]] >= 0) ii.push_back((int32_t)node_iface[v]);
+      }
+      for (size_t q = 1; q < ii.size(); ++q)
+        for (size_t p = 0; p < q; ++p)
+          if (rc[ii[p]] == rc[ii[q]]) {
+            const int32_t x = find(par, ii[p]), y = find(par, ii[q]);
+            if (x != y) par[std::max(x, y)] = std::min(x, y);
+            break;
+          }
+    }
+  }
+  std::vector<int32_t> roots;
+  for (auto& nodes : rejoin) {
+    roots.clear();
+    for (int64_t n : nodes) {
+      const int32_t r = find(par, (int32_t)node_iface[n]);
+      if (std::find(roots.begin(), roots.end(), r) == roots.end()) roots.push_back(r);
+    }
+    const size_t base = L.globs.size();
+    for (size_t k = 0; k < roots.size(); ++k) {
+      L.globs.emplace_back();
+      L.globs.back().subs.assign(nsub.begin() + nptr[nodes[0]], nsub.begin() + nptr[nodes[0] + 1]);
+    }
+    for (int64_t n : nodes) {  // increasing within every part
+      const int32_t r = find(par, (int32_t)node_iface[n]);
+      L.globs[base + (std::find(roots.begin(), roots.end(), r) - roots.begin())].nodes.push_back(n);
+    }
+  }
+}
+
 // Build one level from its elements (node lists, -1 = eliminated node) and
 // the subdomain of every element.
 mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan) {
@@ -514,31 +671,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
       L.globs.push_back(std::move(g));
     }
   } else {
-    // group interface nodes by their subdomain set: hash of the sorted set,
-    // exact comparison on a hash hit
-    std::unordered_map<uint64_t, std::vector<size_t>> by_hash;
-    by_hash.reserve(iface_nodes.size() / 4 + 16);
-    for (int64_t n : iface_nodes) {
-      const int32_t* sb = nsub.data() + nptr[n];
-      const size_t sl = (size_t)(nptr[n + 1] - nptr[n]);
-      uint64_t h = 1469598103934665603ull ^ sl;
-      for (size_t q = 0; q < sl; ++q) h = (h ^ (uint64_t)(uint32_t)sb[q]) * 1099511628211ull;
-      auto& cand = by_hash[h];
-      size_t found = SIZE_MAX;
-      for (size_t gi : cand) {
-        const auto& gs = L.globs[gi].subs;
-        if (gs.size() == sl && std::equal(gs.begin(), gs.end(), sb)) { found = gi; break; }
-      }
-      if (found == SIZE_MAX) {
-        cand.push_back(L.globs.size());
-        Glob g;
-        g.subs.assign(sb, sb + sl);
-        g.nodes = {n};
-        L.globs.push_back(std::move(g));
-      } else {
-        L.globs[found].nodes.push_back(n);
-      }
-    }
+    build_globs(L, node_iface, nptr, nsub, sub_nodes, plan);
     for (auto& g : L.globs) g.kind = classify(g.subs.size(), g.nodes.size(), L.dim);
   }
   std::sort(L.globs.begin(), L.globs.end(), [](const Glob& a, const Glob& b) { return a.nodes[0] < b.nodes[0]; });

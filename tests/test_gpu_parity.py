@@ -7,7 +7,9 @@ preconditioner, condensation and the coarse matrices; PCG iteration counts
 within +-1 of the oracle at rel. residual 1e-8.  Mixed precision: the same
 1e-8 residual with at most 15 % more iterations, and the apply error against
 the FP64 oracle reported.  Sizes span several 64-wide tiles with ragged
-tails (interior blocks of 81..375 DOFs, interfaces of 100..700 DOFs).
+tails (interior blocks of 81..375 DOFs, interfaces of 100..700 DOFs); box
+divisions and non-box ones (k-d bisection, graph-grown subdomains and
+groups, a 2D ring whose subdomains touch in separate patches).
 """
 
 import sys
@@ -23,6 +25,8 @@ from oracle.grad import element_energy
 from oracle.krylov import pcg
 from workloads import box_workload, config
 from workloads.gen import uniform_cuts
+
+from nonbox import nonbox, ring_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +50,22 @@ CASES = {
     # four levels: 512 / 64 / 8 / 1 (2x2x2 groups twice)
     "elast_8x8x8_of_2_L4": lambda: _cube(8, 2, groups=[(2, 2, 2), (2, 2, 2)],
                                          young=10 ** (2 * np.random.default_rng(9).random(16 ** 3))),
+    # non-box divisions: subdomains touching in separate patches (globs split
+    # into connected parts), k-d bisection with T-junctions, graph-grown
+    # subdomains and graph-grown level-2 groups
+    "ring2d_poisson_corners": ring_2d,
+    "elast_kd27_L2": lambda: nonbox("kd", 2),
+    "elast_grown27_L3": lambda: nonbox("grown", 3),
+    "elast_grown64_16cube_L3": lambda: nonbox("grown", 3, n=16, parts=64, groups=8, seed=2),
 }
+
+
+# Bar of the mixed apply against the FP64 oracle: FP32 local operators give
+# an error of about u_32 kappa_local (u_32 = 6e-8).  Box subdomains stay
+# below 1e-4; graph-grown subdomains (staircase faces, pieces one element
+# thick) with moduli over two decades reach local condition numbers of
+# ~1e4, so their bar is 1e-3.
+MIXED_APPLY_BAR = {"elast_grown27_L3": 1e-3, "elast_grown64_16cube_L3": 1e-3}
 
 
 def _mixed_its_bound(ref_its):
@@ -134,8 +153,9 @@ def test_mixed_precision(name):
     r = rng.standard_normal(b.level1.n_iface)
     z = s.apply(torch.tensor(r, device="cuda")).cpu().numpy()
     err = _rel(z, b.apply(r))
-    _say(f"  mixed apply rel error vs FP64 oracle: {err:.3e}")
-    assert err < 1e-4
+    bar = MIXED_APPLY_BAR.get(name, 1e-4)
+    _say(f"  mixed apply rel error vs FP64 oracle: {err:.3e} (bar {bar:.0e})")
+    assert err < bar
     _, f = fem.assemble_global(w)
     u, st = s.solve(torch.tensor(f, device="cuda"))
     ref = pcg(b.schur_apply, b.condense(f), b.apply, tol=1e-8)

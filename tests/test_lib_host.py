@@ -64,6 +64,26 @@ def test_plan_counts_and_load_match_oracle(k):
     assert np.allclose(pr.load_vector(), f, rtol=0, atol=1e-15)
 
 
+def _nonbox_workloads():
+    from nonbox import nonbox, ring_2d
+    return {"ring2d": ring_2d, "kd_L2": lambda: nonbox("kd", 2), "grown_L2": lambda: nonbox("grown", 2),
+            "grown_L3": lambda: nonbox("grown", 3)}
+
+
+@pytest.mark.parametrize("name", ["ring2d", "kd_L2", "grown_L2", "grown_L3"])
+def test_plan_counts_nonbox_match_oracle(name):
+    # k-d and graph-grown divisions: classes of equal subdomain sets split into
+    # connected parts on both sides (the ring has the closed-form count 4/7/0)
+    from paper_1201_5991_amd import Problem
+    w = _nonbox_workloads()[name]()
+    counts = Problem(w).counts()
+    b = MultilevelBDDC(w, structure_only=True)
+    assert len(counts) == len(b.levels)
+    for l, lev in enumerate(b.levels):
+        c = lev.glob_counts()
+        assert counts[l].tolist() == [lev.n_sub, lev.n_iface, lev.n_coarse, c["corner"], c["edge"], c["face"]]
+
+
 def test_plan_counts_large_configs_closed_form():
     # 12^3 boxes (config 3): corners 11^3, edges 3*12*11^2, faces 3*12^2*11; level 2 (3^3): 8/36/54.
     from paper_1201_5991_amd import Problem

@@ -18,6 +18,8 @@ from oracle.krylov import lanczos_extremes, pcg
 from workloads import box_workload, config
 from workloads.gen import uniform_cuts
 
+from nonbox import nonbox as _nonbox, ring_2d as _ring_2d
+
 
 def cube(n_sub, el_per_sub, groups=(), young=None, **kw):
     n = n_sub * el_per_sub
@@ -245,3 +247,55 @@ def test_pcg_identity_is_textbook_cg():
     Kry = np.column_stack([b, A @ b, A @ A @ b])
     y = np.linalg.solve(Kry.T @ A @ Kry, Kry.T @ b)
     assert np.allclose(res3.x, Kry @ y, atol=1e-10)
+
+
+# ---------------------------------------------------------------- non-box partitions
+
+def test_glob_split_closed_form_2d():
+    # Hand count (interior nodes (i, j), 1 <= i <= 7, 1 <= j <= 5): {A,Y} at
+    # (1,2), (1,4); {A,B,Y} at (2,2), (2,4); {A,B} at (3,2), (3,4); {A,B,X} at
+    # (4,2), (4,4); {A,X} the chain (5,2)-(6,2)-(6,3)-(6,4)-(5,4); {Y,B} (2,3);
+    # {B,X} (4,3).  Split into connected parts: 4 single-node globs of three
+    # subdomains (corners) and 7 edges; without the split {A,B,Y} and {A,B,X}
+    # would be two-node edges and there would be no corner at all.
+    b = MultilevelBDDC(_ring_2d())
+    lv = b.level1
+    assert lv.glob_counts() == {"corner": 4, "edge": 7, "face": 0}
+    assert lv.n_coarse == 4
+    sizes = sorted(len(g.nodes) for g in lv.globs)
+    assert sizes == [1] * 10 + [5]
+
+
+def test_ring_partition_solves():
+    # corners only: B and X float and are held by their corners alone
+    w = _ring_2d()
+    u, res, b, f = solve_bddc(w, tol=1e-12)
+    lo, hi = lanczos_extremes(res.alphas, res.betas)
+    assert res.converged and lo > 1 - 1e-8
+    ud, _, _ = direct_solve(w)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 1e-10
+
+
+@pytest.mark.parametrize("kind,L", [("kd", 2), ("grown", 2), ("grown", 3)])
+def test_nonbox_partitions_bound_and_direct_agreement(kind, L):
+    # k-d (T-junction) and graph-grown level-1 divisions, graph-grown level-2
+    # groups: lambda_min >= 1 and the direct solution, as on boxes
+    w = _nonbox(kind, L)
+    u, res, b, _ = solve_bddc(w, tol=1e-12)
+    assert res.converged and b.n_levels == L
+    lo, hi = lanczos_extremes(res.alphas, res.betas)
+    assert lo > 1 - 1e-8
+    ud, _, _ = direct_solve(w)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) < 10 * (hi / lo) * 1e-12
+
+
+def test_grown_partition_splits_classes():
+    # the graph-grown division has subdomain pairs touching in separate
+    # patches: more globs than classes of equal subdomain sets, and every glob
+    # lies in one class
+    b = MultilevelBDDC(_nonbox("grown", 2))
+    lv = b.level1
+    classes = {g.subs for g in lv.globs}
+    assert len(lv.globs) > len(classes)
+    for g in lv.globs:
+        assert all(tuple(lv.node_subs[int(n)]) == g.subs for n in g.nodes)

@@ -149,6 +149,50 @@ def random_cuts(seed: int, n: int = 80, parts: int = 8, lo: int = 4, hi: int = 1
     return cuts
 
 
+def partition_workload(
+    name: str,
+    physics: str,
+    n_el: Sequence[int],
+    elem_to_sub: np.ndarray,
+    sub_to_parent: Sequence[np.ndarray] = (),
+    young: np.ndarray | None = None,
+    poisson_ratio: float = 0.3,
+    body_force: Sequence[float] | None = None,
+    dirichlet: str = "x0",
+    constraints: str = "cef",
+    seed: int = 0,
+    cuts: Sequence[Sequence[int]] = (),
+) -> Workload:
+    """Workload on the structured mesh with any division: ``elem_to_sub`` for
+    level 1 and ``sub_to_parent`` for levels 2..L-1 (L = len + 2).
+    ``dirichlet`` is "x0" (face x = 0 clamped) or "all" (whole boundary)."""
+    dim = len(n_el)
+    n_el = tuple(int(n) for n in n_el)
+    elem_nodes = structured_mesh(n_el)
+    coords = _node_grid(n_el)
+    if dirichlet == "x0":
+        dir_nodes = coords[0] == 0
+    elif dirichlet == "all":
+        dir_nodes = np.zeros(coords[0].shape, dtype=bool)
+        for d in range(dim):
+            dir_nodes |= (coords[d] == 0) | (coords[d] == n_el[d])
+    else:
+        raise ValueError(dirichlet)
+    n_elems = int(np.prod(n_el))
+    if young is None:
+        young = np.ones(n_elems)
+    if body_force is None:
+        body_force = (1.0,) if physics == "poisson" else tuple([0.0] * (dim - 1) + [-1.0])
+    return Workload(
+        name=name, physics=physics, dim=dim, n_el=n_el, elem_nodes=elem_nodes,
+        dirichlet_nodes=dir_nodes, young=np.asarray(young, dtype=np.float64),
+        poisson_ratio=poisson_ratio, body_force=tuple(body_force), cuts=[np.asarray(c, dtype=np.int64) for c in cuts],
+        elem_to_sub=np.asarray(elem_to_sub, dtype=np.int32),
+        sub_to_parent=[np.asarray(p, dtype=np.int32) for p in sub_to_parent], constraints=constraints,
+        n_levels=len(sub_to_parent) + 2, seed=seed,
+    )
+
+
 def box_workload(
     name: str,
     physics: str,
@@ -168,18 +212,6 @@ def box_workload(
     form one level-l subdomain; the number of levels is ``len(groups) + 2``.
     ``dirichlet`` is "x0" (face x = 0 clamped) or "all" (whole boundary).
     """
-    dim = len(n_el)
-    n_el = tuple(int(n) for n in n_el)
-    elem_nodes = structured_mesh(n_el)
-    coords = _node_grid(n_el)
-    if dirichlet == "x0":
-        dir_nodes = coords[0] == 0
-    elif dirichlet == "all":
-        dir_nodes = np.zeros(coords[0].shape, dtype=bool)
-        for d in range(dim):
-            dir_nodes |= (coords[d] == 0) | (coords[d] == n_el[d])
-    else:
-        raise ValueError(dirichlet)
     cuts = [np.asarray(c, dtype=np.int64) for c in cuts]
     elem_to_sub = box_partition(n_el, cuts)
     n_boxes = tuple(len(c) - 1 for c in cuts)
@@ -188,18 +220,9 @@ def box_workload(
     for g in groups:
         p, cur = group_parents(cur, g)
         parents.append(p)
-    n_elems = int(np.prod(n_el))
-    if young is None:
-        young = np.ones(n_elems)
-    if body_force is None:
-        body_force = (1.0,) if physics == "poisson" else tuple([0.0] * (dim - 1) + [-1.0])
-    return Workload(
-        name=name, physics=physics, dim=dim, n_el=n_el, elem_nodes=elem_nodes,
-        dirichlet_nodes=dir_nodes, young=np.asarray(young, dtype=np.float64),
-        poisson_ratio=poisson_ratio, body_force=tuple(body_force), cuts=cuts,
-        elem_to_sub=elem_to_sub, sub_to_parent=parents, constraints=constraints,
-        n_levels=len(groups) + 2, seed=seed,
-    )
+    return partition_workload(name, physics, n_el, elem_to_sub, parents, young=young, poisson_ratio=poisson_ratio,
+                              body_force=body_force, dirichlet=dirichlet, constraints=constraints, seed=seed,
+                              cuts=cuts)
 
 
 def uniform_cuts(n: int, parts: int) -> np.ndarray:
@@ -225,11 +248,12 @@ CONFIG_NAMES = {
     3: "elasticity3d_96cube_1728sub",
     4: "elasticity3d_80cube_512uneven_L3",
     5: "elasticity3d_64cube_512sub_L3_grad",
+    6: "elasticity3d_40cube_8sub20_L2",
 }
 
 
 def config(k: int, levels: int | None = None, seed: int = 0) -> Workload:
-    """The five benchmark workloads, numbered 1..5.
+    """The benchmark workloads, numbered 1..6.
 
     1. 2D Poisson -Lap u = 1, 32x32 Q1, Dirichlet everywhere, 4x4 subdomains, 2 levels, corners.
     2. 3D elasticity 48^3 hex, E=1, nu=0.3, b=(0,0,-1), x=0 clamped, 4^3 subdomains of 12^3;
@@ -238,6 +262,8 @@ def config(k: int, levels: int | None = None, seed: int = 0) -> Workload:
        default here), 4 levels (2x2x2 groups twice: 1728 / 216 / 27) or 2 levels.
     4. 3D elasticity 80^3 cut by seeded random planes into 8^3 uneven boxes, 3 levels (2x2x2).
     5. 3D elasticity 64^3, 8^3 subdomains of 8^3, 3 levels (2x2x2), E = exp(theta), theta~N(0, 0.5^2).
+    6. 3D elasticity 40^3, 2^3 subdomains of 20^3 (27,783 DOFs each), 2 levels, E = 10^(2U)
+       (``large_subdomains``, its own seed 3).
     """
     name = CONFIG_NAMES[k]
     if k == 1:
@@ -270,4 +296,6 @@ def config(k: int, levels: int | None = None, seed: int = 0) -> Workload:
         theta = rng.normal(0.0, 0.5, n)
         return box_workload(name, "elasticity", (64,) * 3, [uniform_cuts(64, 8)] * 3,
                             groups=[(2, 2, 2)], young=np.exp(theta), seed=seed)
+    if k == 6:
+        return large_subdomains()
     raise KeyError(k)
