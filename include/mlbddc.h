@@ -67,13 +67,16 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   int32_t panel_tiles_precond; /* same for the constrained local problems (0 = tune table / 4) */
   const char* tune_table;      /* path of a tune table written by the autotuner, or NULL;
-                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel>" */
+                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]" */
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */
   int32_t side_stream; /* 1 (default): in mixed precision the level-1 local operator product G_i r_i runs
                           on a second stream beside the coarse levels of the apply.  0: one stream.
                           Both give bitwise the same results */
+  int32_t stage_cols;  /* columns of a tile staged per step of the MFMA tile products of the
+                          factorizations: 16, 32 or 64 (0 = from the tune table, else 32).  Every value
+                          gives bitwise the same results */
 } mlbddc_options;
 
 typedef struct {
@@ -260,6 +263,7 @@ typedef struct {
                                      matrices (all levels), [1] constrained local problems */
   int32_t panel[2];               /* panel widths of the largest K and M jobs of the last set-up */
   double bytes[MLBDDC_PROF_N];    /* algorithmic bytes of the product classes */
+  int32_t stage[2];               /* staged columns of the largest K and M jobs of the last set-up */
 } mlbddc_profile;
 mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable);
 mlbddc_status mlbddc_get_profile(mlbddc_t h, mlbddc_profile* out);

@@ -40,7 +40,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_iter", C.c_int32), ("weights", C.c_int32),
                 ("use_graph", C.c_int32), ("panel_tiles", C.c_int32), ("device", C.c_int32),
                 ("panel_tiles_precond", C.c_int32), ("tune_table", C.c_char_p), ("lookahead", C.c_int32),
-                ("side_stream", C.c_int32)]
+                ("side_stream", C.c_int32), ("stage_cols", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -75,13 +75,14 @@ class Stats(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("time_s", C.c_double * 8), ("flops", C.c_double * 8), ("launches", C.c_int64 * 8),
                 ("tiles", C.c_int64 * 8), ("job_time_s", C.c_double * 2), ("panel", C.c_int32 * 2),
-                ("bytes", C.c_double * 8)]
+                ("bytes", C.c_double * 8), ("stage", C.c_int32 * 2)]
 
     def as_dict(self):
         d = {n: {"time_s": self.time_s[i], "flops": self.flops[i], "launches": self.launches[i],
                  "tiles": self.tiles[i], "bytes": self.bytes[i]} for i, n in enumerate(PROF_NAMES)}
         d["jobs"] = {"K_time_s": self.job_time_s[0], "M_time_s": self.job_time_s[1],
-                     "panel_K": self.panel[0], "panel_M": self.panel[1]}
+                     "panel_K": self.panel[0], "panel_M": self.panel[1],
+                     "stage_K": self.stage[0], "stage_M": self.stage[1]}
         return d
 
 

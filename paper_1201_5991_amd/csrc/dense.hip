@@ -413,7 +413,6 @@ __device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T*
 }
 
 constexpr int LDU = TS + 16;  // keeps the four k-groups of a fragment read on distinct LDS banks
-constexpr int KH = TS / 2;    // columns of a tile staged at a time
 
 // Workgroups are dealt to the 8 XCDs of the chip round-robin by launch
 // index; this maps launch index b to a task index so that each XCD receives
@@ -428,22 +427,28 @@ __device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
 // Tile products on MFMA, one 64x64 output tile per workgroup:
 //   UPDATE  A_rs <- A_rs - sum_{kk=kf..kf+nk} A_{r,kk} A_{s,kk}^T   (kf, nk from the task)
 //   PANEL   A_rk <- A_rk inv(L_kk)^T
-// The k dimension advances in half tiles (32 columns; 2 x 32 x LDU values of
-// LDS, so that four workgroups share a CU).  The next pair of half tiles is
-// loaded into registers while the current pair is multiplied from LDS; during
-// the last pair the registers freed by that prefetch receive the output tile
-// of an UPDATE.
-template <typename T, bool PANEL>
-__global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
-                                                    const int32_t* __restrict__ ntv, const int64_t* __restrict__ inv_off,
-                                                    T* A, const T* __restrict__ Inv, const int32_t* __restrict__ tmap,
-                                                    const int64_t* __restrict__ tmap_off) {
-  __shared__ T sR[KH * LDU];
-  __shared__ T sS[KH * LDU];
+// The k dimension advances KS columns at a time (KS = 16, 32 or 64, a tuning
+// parameter; 2 x KS x LDU values of LDS).  The next pair of column blocks is
+// loaded into registers while the current pair is multiplied from LDS;
+// during the last pair the registers freed by that prefetch receive the
+// output tile of an UPDATE.  The products accumulate over k in the same order
+// for every KS, so the results do not depend on it.
+template <int KS> struct StageOcc { static constexpr int blocks = 4; };
+template <> struct StageOcc<64> { static constexpr int blocks = 2; };  // twice the LDS and staging registers
+
+template <typename T, bool PANEL, int KS>
+__global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
+    const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off, const int32_t* __restrict__ ntv,
+    const int64_t* __restrict__ inv_off, T* A, const T* __restrict__ Inv, const int32_t* __restrict__ tmap,
+    const int64_t* __restrict__ tmap_off) {
+  static_assert(KS == 16 || KS == 32 || KS == 64, "staged columns");
+  constexpr int SPT = TS / KS;  // steps per tile
+  __shared__ T sR[KS * LDU];
+  __shared__ T sS[KS * LDU];
   const uint64_t t = tasks[xcd_slice(blockIdx.x, gridDim.x)];
   const int item = task_item(t), r = task_r(t), s = task_s(t);
   const int kf = PANEL ? s : task_kf(t);
-  const int nsteps = PANEL ? 2 : 2 * (task_nk(t) + 1);
+  const int nsteps = PANEL ? SPT : SPT * (task_nk(t) + 1);
   const int nt = ntv[item];
   T* base = A + off[item];
   T* g = base + tile_slot(tmap, tmap_off, item, r, s, nt) * TE;
@@ -462,14 +467,15 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
   }
   auto rtile = [&](int j) -> int64_t { return mo >= 0 ? __builtin_amdgcn_readlane(rslot, j) : tile_index(r, kf + j, nt); };
   auto stile = [&](int j) -> int64_t { return mo >= 0 ? __builtin_amdgcn_readlane(sslot, j) : tile_index(s, kf + j, nt); };
-  auto rsrc = [&](int q) { return base + rtile(q >> 1) * TE + (q & 1) * (TE / 2); };
+  auto rsrc = [&](int q) { return base + rtile(q / SPT) * TE + (q % SPT) * (TE / SPT); };
   auto ssrc = [&](int q) -> const T* {
-    return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q & 1) * (TE / 2) : base + stile(q >> 1) * TE + (q & 1) * (TE / 2);
+    return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q % SPT) * (TE / SPT)
+                 : base + stile(q / SPT) * TE + (q % SPT) * (TE / SPT);
   };
   typename Mfma<T>::acc_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
-  ChunkRegs<T, TE / 2> pr, ps;
+  ChunkRegs<T, KS * TS> pr, ps;
   pr.load(rsrc(0));
   if (!same) ps.load(ssrc(0));
   for (int q = 0; q + 1 < nsteps; ++q) {
@@ -478,7 +484,7 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
     __syncthreads();
     pr.load(rsrc(q + 1));
     if (!same) ps.load(ssrc(q + 1));
-    tile_nt_ld<T, LDU, KH>(acc, sR, same ? sR : sS);
+    tile_nt_ld<T, LDU, KS>(acc, sR, same ? sR : sS);
     __syncthreads();
   }
   pr.template store<LDU>(sR);
@@ -499,7 +505,7 @@ __global__ void __launch_bounds__(256, 4) k_tile_mm(const uint64_t* __restrict__
           creg[n++] = g[j * TS + i];
         }
   }
-  tile_nt_ld<T, LDU, KH>(acc, sR, same ? sR : sS);
+  tile_nt_ld<T, LDU, KS>(acc, sR, same ? sR : sS);
   int n = 0;
   if (PANEL) for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = v; });
   else for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - v; });
@@ -604,20 +610,26 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
   if (count <= 0) return;
   const uint64_t* tk = a.tasks + first;
   dim3 grid((unsigned)count), blk(256);
+  auto mm = [&](bool panel) {
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off); };
+    if (panel) {
+      if (a.stage == 16) go(k_tile_mm<T, true, 16>);
+      else if (a.stage == 64) go(k_tile_mm<T, true, 64>);
+      else go(k_tile_mm<T, true, 32>);
+    } else {
+      if (a.stage == 16) go(k_tile_mm<T, false, 16>);
+      else if (a.stage == 64) go(k_tile_mm<T, false, 64>);
+      else go(k_tile_mm<T, false, 32>);
+    }
+  };
   switch (kind) {
     case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A, a.tmap, a.tmap_off); break;
-    case L_INPANEL:
-      hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
-      break;
+    case L_INPANEL: mm(false); break;
     case L_DIAG:
       hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv, a.tmap, a.tmap_off);
       break;
-    case L_PANEL:
-      hipLaunchKernelGGL((k_tile_mm<T, true>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
-      break;
-    case L_TRAIL:
-      hipLaunchKernelGGL((k_tile_mm<T, false>), grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off);
-      break;
+    case L_PANEL: mm(true); break;
+    case L_TRAIL: mm(false); break;
   }
 }
 

@@ -39,6 +39,7 @@ struct FactorArgs {
   int32_t* err;            // [0] = failing item + 1, [1] = column
   const int32_t* tmap;     // tile maps (tile_slot), or null: every matrix dense packed-lower
   const int64_t* tmap_off;
+  int stage = 32;          // columns staged per step of the tile products: 16, 32 or 64
 };
 template <typename T>
 void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv);

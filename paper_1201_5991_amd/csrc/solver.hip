@@ -105,6 +105,7 @@ struct Job {
   uint64_t* d_tasks = nullptr;
   int32_t* d_err = nullptr;
   int panel = 4;
+  int stage = 32;  // staged columns of the tile products
   // Tile maps (tile_slot): a matrix with a tile structure stores only the
   // tiles some kernel reads; tmap_off[i] = -1 for a dense packed-lower one.
   // A mapped matrix keeps its eliminated columns at off[i] (nlead[i] tiles)
@@ -451,8 +452,9 @@ struct Handle {
   mlbddc_status finish_numeric();
   mlbddc_status numeric();
   bool lookahead = false;
-  std::vector<std::array<int, 4>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel)
+  std::vector<std::array<int, 5>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel, staged columns or 0)
   int pick_panel(int job, bool fp32, int ntmax) const;
+  int pick_stage(int job, bool fp32, int ntmax) const;
   mlbddc_status reserve_job(Job& J, bool fp32);
   mlbddc_status prepare_job(Job& J, bool fp32, int job = 0);
   mlbddc_status factor(Job& J, int level, bool precond);
@@ -777,6 +779,21 @@ int Handle::pick_panel(int job, bool fp32, int ntmax) const {
   return best > 0 ? best : 4;
 }
 
+// Staged columns of the tile products of a job: explicit option, else the
+// tune table's entry chosen as for the panel width, else 32.
+int Handle::pick_stage(int job, bool fp32, int ntmax) const {
+  if (opt.stage_cols > 0) return opt.stage_cols;
+  int bucket = 0;
+  while ((1 << bucket) < ntmax) ++bucket;
+  int best = 0, bestd = 1 << 30;
+  for (const auto& t : tune) {
+    if (t[0] != job || t[1] != (fp32 ? 1 : 0)) continue;
+    int d = std::abs(t[2] - bucket);
+    if (d < bestd) { bestd = d; best = t[4]; }
+  }
+  return best > 0 ? best : 32;
+}
+
 // Matrix layout and storage of a job (J.nt and the items' e1, e2 and tile
 // structure set): the matrices are zeroed on the upload stream right away,
 // while the host keeps preparing (the upload fence orders this before the
@@ -878,10 +895,12 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   int ntmax = 1;
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
+  J.stage = pick_stage(job, fp32, ntmax);
   if (!J.tmap.empty()) J.panel = std::min(J.panel, 64);  // k_tile_mm holds a task's tile slots in one wavefront
   if (ntmax >= panel_nt[job]) {  // report the panel width of the largest job of the set-up
     panel_nt[job] = ntmax;
     pdata.panel[job] = J.panel;
+    pdata.stage[job] = J.stage;
   }
   build_factor_schedule(J.items, J.panel, J.sched, lookahead);
   mark("schedule");
@@ -898,7 +917,7 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
   if (prof) HIPCHK(hipStreamSynchronize(stream));  // job time excludes earlier queued work
   const double tj0 = prof ? now() : 0.0;
-  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off};
+  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off, J.stage};
   const size_t nl = J.sched.launches.size();
   if (prof)
     while (events.size() < 2 * nl) {
@@ -2335,6 +2354,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->tune_table = nullptr;
   o->lookahead = 0;
   o->side_stream = 1;
+  o->stage_cols = 0;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream) {
@@ -2356,7 +2376,8 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
   mlbddc_default_options(&o);
   if (opt) o = *opt;
   if (o.device < 0 || o.device >= ndev || !(o.rtol > 0) || o.max_iter < 1 ||
-      (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED)) {
+      (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED) ||
+      (o.stage_cols != 0 && o.stage_cols != 16 && o.stage_cols != 32 && o.stage_cols != 64)) {
     g_create_error.status = MLBDDC_E_ARG;
     g_create_error.message = "invalid options";
     return MLBDDC_E_ARG;
@@ -2384,9 +2405,10 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
       if (line.empty() || line[0] == '#') continue;
       std::istringstream ls(line);
       std::string job, prec;
-      int bucket = 0, panel = 0;
+      int bucket = 0, panel = 0, stage = 0;
       if (!(ls >> job >> prec >> bucket >> panel) || panel < 1 || panel > 16) continue;
-      h->h.tune.push_back({job == "M" ? 1 : 0, prec == "f32" ? 1 : 0, bucket, panel});
+      if (!(ls >> stage) || (stage != 16 && stage != 32 && stage != 64)) stage = 0;
+      h->h.tune.push_back({job == "M" ? 1 : 0, prec == "f32" ? 1 : 0, bucket, panel, stage});
     }
     h->h.opt.tune_table = nullptr;  // the path is not kept
   }
@@ -2526,10 +2548,12 @@ mlbddc_status mlbddc_set_profiling(mlbddc_t h, int32_t enable) {
   if (!h) return MLBDDC_E_ARG;
   if (mlbddc_status st = h->h.collect_mv_timing()) return st;
   h->h.prof = enable != 0;
-  int p0 = h->h.pdata.panel[0], p1 = h->h.pdata.panel[1];
+  int p0 = h->h.pdata.panel[0], p1 = h->h.pdata.panel[1], s0 = h->h.pdata.stage[0], s1 = h->h.pdata.stage[1];
   h->h.pdata = mlbddc_profile{};
   h->h.pdata.panel[0] = p0;
   h->h.pdata.panel[1] = p1;
+  h->h.pdata.stage[0] = s0;
+  h->h.pdata.stage[1] = s1;
   return MLBDDC_OK;
 }
 

@@ -275,6 +275,36 @@ def test_lookahead_schedule_same_result(precision):
     assert torch.equal(u1, u2)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_staged_columns_same_result(precision):
+    """The tile products stage 16, 32 or 64 columns per step and accumulate
+    over k in the same order for each, so every choice gives bitwise the same
+    operators and solve; the 32-column results also match the oracle."""
+    from paper_1201_5991_amd import Problem, Solver
+    _say(f"[parity] staged columns 16 / 32 / 64, {precision}")
+    w = _cube(2, 8, young=10 ** (2 * np.random.default_rng(10).random(16 ** 3)))
+    prob = Problem(w)
+    f = torch.tensor(prob.load_vector(), device="cuda")
+    r = None
+    out = {}
+    for stage in (16, 32, 64):
+        s = Solver(precision=precision, stage_cols=stage, panel_tiles=3, panel_tiles_precond=3).setup(prob)
+        assert s.profile()["jobs"]["stage_K"] == stage
+        if r is None:
+            r = torch.tensor(np.random.default_rng(9).standard_normal(s.n_iface), device="cuda")
+        u, st = s.solve(f)
+        out[stage] = (s.apply_schur(r), s.apply(r), u, st["iterations"])
+        s.destroy()
+    for stage in (16, 64):
+        for a, b in zip(out[stage], out[32]):
+            assert (a == b) if isinstance(a, int) else torch.equal(a, b), stage
+    b = MultilevelBDDC(w)
+    rr = r.cpu().numpy()
+    assert _rel(out[32][0].cpu().numpy(), b.schur_apply(rr)) < RTOL64
+    if precision == "fp64":
+        assert _rel(out[32][1].cpu().numpy(), b.apply(rr)) < RTOL64
+
+
 def test_side_stream_same_result():
     """Mixed precision at 48^3 (the G product takes the side stream there):
     the level-1 G product beside the coarse levels (fork / join on a second
