@@ -577,9 +577,54 @@ void build_globs(LevelPlan& L, const std::vector<int64_t>& node_iface, const std
   }
 }
 
+// Subdomains with the same local structure get the same interior order and
+// tile structure: the key lists the local slot of every node of every element
+// (interior nodes in node order, then interface nodes) and, per interface
+// node, the ranks of its other subdomains among the subdomain's neighbours,
+// which is everything the nested dissection and the tile structure read.
+// Entries are compared in full; a box division repeats few structures.
+struct LayoutCache {
+  struct Entry {
+    std::vector<int32_t> key;
+    std::vector<int32_t> order, gsize, gheight, sptr, srow;
+    bool ready = false;  // guarded by the cache's mutex
+  };
+  std::mutex mx;
+  std::condition_variable cv;
+  std::unordered_map<uint64_t, std::vector<std::shared_ptr<Entry>>> map;
+  static uint64_t hash(const std::vector<int32_t>& k) {
+    uint64_t h = 1469598103934665603ull;
+    for (int32_t v : k) h = (h ^ (uint64_t)(uint32_t)v) * 1099511628211ull;
+    return h;
+  }
+  // The entry of key k, waiting while another thread computes it; or a new
+  // entry that the caller computes and then publishes (claimed = true).
+  std::shared_ptr<Entry> get(std::vector<int32_t>& k, uint64_t h, bool& claimed) {
+    std::unique_lock<std::mutex> g(mx);
+    for (const auto& e : map[h])
+      if (e->key == k) {
+        cv.wait(g, [&] { return e->ready; });
+        claimed = false;
+        return e;
+      }
+    auto e = std::make_shared<Entry>();
+    e->key = std::move(k);
+    map[h].push_back(e);
+    claimed = true;
+    return e;
+  }
+  void publish(const std::shared_ptr<Entry>& e) {
+    {
+      std::lock_guard<std::mutex> g(mx);
+      e->ready = true;
+    }
+    cv.notify_all();
+  }
+};
+
 // Build one level from its elements (node lists, -1 = eliminated node) and
 // the subdomain of every element.
-mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan) {
+mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan, bool reuse_layouts) {
   const bool verbose = std::getenv("MLBDDC_VERBOSE") != nullptr;
   auto t_last = std::chrono::steady_clock::now();
   auto mark = [&](const char* what) {
@@ -715,6 +760,8 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
   // Per-subdomain work is independent: split the subdomains over threads, each
   // with its own node-indexed scratch (reset only where it was touched).
   if ((int)plan.scratch.size() < plan_threads(ns)) plan.scratch.resize(plan_threads(ns));
+  LayoutCache cache;
+  std::atomic<int32_t> reused{0};
   auto work = [&](int t, int64_t b_begin, int64_t b_end) {
   PlanScratch& W = plan.scratch[t];
   W.ensure(L.n_nodes);
@@ -735,7 +782,39 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
     // local position of its first DOF
     std::vector<int32_t> iorder, gsize;
     const bool use_nd = L.level == 1 && !L.top && S.nI >= ND_MIN_DOFS;
-    if (use_nd) {
+    const bool keyed = use_nd && reuse_layouts;
+    std::vector<int32_t> skey;
+    std::shared_ptr<LayoutCache::Entry> mine, hit;  // the entry this subdomain computes, or reuses
+    if (keyed) {
+      const int32_t ni = (int32_t)inodes.size();
+      skey = {ni, (int32_t)gnodes.size(), nd, (int32_t)S.elems.size()};
+      for (int64_t e : S.elems)
+        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+          const int64_t v = L.el_nodes[j];
+          skey.push_back(v < 0 ? -1 : node_is_g[v] ? ni + node_local[v] : node_local[v]);
+        }
+      std::vector<int32_t> nb;
+      for (int64_t v : gnodes)
+        for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
+          if (nsub[q] != b) nb.push_back(nsub[q]);
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      for (int64_t v : gnodes) {
+        for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
+          if (nsub[q] != b) skey.push_back((int32_t)(std::lower_bound(nb.begin(), nb.end(), nsub[q]) - nb.begin()));
+        skey.push_back(-2);
+      }
+      const uint64_t h = LayoutCache::hash(skey);
+      bool claimed = false;
+      auto e = cache.get(skey, h, claimed);
+      (claimed ? mine : hit) = std::move(e);
+    }
+    if (hit) {
+      iorder = hit->order;
+      gsize = hit->gsize;
+      S.gheight = hit->gheight;
+      reused++;
+    } else if (use_nd) {
       nd_interior(L, S, b, inodes, gnodes, node_local, node_is_g, nptr.data(), nsub.data(), nd, iorder, gsize,
                   S.gheight);
     } else {
@@ -833,7 +912,20 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
       for (int64_t p = r * TS; p < (r + 1) * TS; ++p) m = std::min(m, first[p]);
       S.envK[r] = (int32_t)(m / TS);
     }
-    if (use_nd) tile_structure(L, S, nd, (int)(S.nIp / TS), (int)ntK, S.sptr, S.srow);
+    if (hit) {
+      S.sptr = hit->sptr;
+      S.srow = hit->srow;
+    } else if (use_nd) {
+      tile_structure(L, S, nd, (int)(S.nIp / TS), (int)ntK, S.sptr, S.srow);
+    }
+    if (mine) {
+      mine->order = iorder;
+      mine->gsize = gsize;
+      mine->gheight = S.gheight;
+      mine->sptr = S.sptr;
+      mine->srow = S.srow;
+      cache.publish(mine);
+    }
 
     // constraint rows and R_Ci
     S.crow_ptr.assign(1, 0);
@@ -882,6 +974,9 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan)
       for (int32_t i = next++; i < ns; i = next++) work(t, order[i], order[i] + 1);
     });
   }
+  if (verbose && reused > 0)
+    std::fprintf(stderr, "[mlbddc plan L%d] %d of %d subdomain layouts reuse the dissection of an equal structure\n", L.level,
+                 (int)reused, (int)ns);
   mark("local layouts (parallel)");
   for (int32_t b = 0; b < ns; ++b) {
     if (sub_fail[b] == 1)
@@ -971,7 +1066,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
   L1.el_ptr[in.n_elems] = in.n_elems * npe;
   L1.n_sub = nsub;
   mark("level-1 element arrays");
-  mlbddc_status st = build_level(L1, in.constraints, err, plan);
+  mlbddc_status st = build_level(L1, in.constraints, err, plan, in.reuse_layouts);
   if (st != MLBDDC_OK) return st;
   plan.levels.push_back(std::move(L1));
 
@@ -1007,7 +1102,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
       }
     }
     L.n_sub = ns;
-    st = build_level(L, L.top ? 0 : (in.constraints & ~MLBDDC_ALL_PRIMAL), err, plan);
+    st = build_level(L, L.top ? 0 : (in.constraints & ~MLBDDC_ALL_PRIMAL), err, plan, in.reuse_layouts);
     if (st != MLBDDC_OK) return st;
     plan.levels.push_back(std::move(L));
   }

@@ -98,6 +98,7 @@ struct PlanInput {
   const int32_t* elem_to_sub = nullptr;
   const int32_t* const* sub_to_parent = nullptr;
   int constraints = MLBDDC_CORNERS | MLBDDC_EDGES | MLBDDC_FACES;
+  bool reuse_layouts = true;  // structurally equal subdomains share one dissection (same result)
 };
 
 // Per-thread host scratch of the planner, kept by the plan between set-ups.

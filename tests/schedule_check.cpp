@@ -6,7 +6,9 @@
 // of the interior columns, and checks that no two tasks of one launch write
 // the same tile.  Tiles outside the set the library zeroes before the
 // assembly (read_before_write_tiles) start as NaN: a task that read one would
-// spread NaN into the compared tiles.
+// spread NaN into the compared tiles.  Before that, the level-1 layouts of
+// the plan must equal those of a plan built without reusing the dissection of
+// structurally equal subdomains.
 //
 // usage: schedule_check <dir with meta.txt and *.bin> <subdomain> <panel>
 // prints one line; exit status 0 when the comparison passes.
@@ -60,6 +62,34 @@ int main(int argc, char** argv) {
   if (build_plan(in, plan, err) != MLBDDC_OK) {
     std::printf("plan failed: %s\n", err.message.c_str());
     return 1;
+  }
+  // the same plan without reusing the dissection of structurally equal
+  // subdomains: every level-1 layout must come out the same
+  {
+    PlanInput in2 = in;
+    in2.reuse_layouts = false;
+    Plan plan2;
+    Error err2;
+    if (build_plan(in2, plan2, err2) != MLBDDC_OK) {
+      std::printf("plan without reuse failed: %s\n", err2.message.c_str());
+      return 1;
+    }
+    const LevelPlan& A = plan.levels[0];
+    const LevelPlan& B = plan2.levels[0];
+    for (int b = 0; b < A.n_sub; ++b) {
+      const SubPlan& x = A.subs[b];
+      const SubPlan& y = B.subs[b];
+      if (x.dofI != y.dofI || x.dofG != y.dofG || x.iface != y.iface || x.padI != y.padI || x.gtile != y.gtile ||
+          x.gheight != y.gheight || x.sptr != y.sptr || x.srow != y.srow || x.envK != y.envK || x.nIp != y.nIp ||
+          x.nGp != y.nGp || x.crow_col != y.crow_col) {
+        std::printf("layout of subdomain %d differs with reuse\n", b);
+        return 1;
+      }
+    }
+    if (A.el_local != B.el_local || A.el_color != B.el_color) {
+      std::printf("element maps differ with reuse\n");
+      return 1;
+    }
   }
   const LevelPlan& P = plan.levels[0];
   if (want < 0 || want >= P.n_sub) return 2;

@@ -58,6 +58,40 @@ def checker(request, tmp_path_factory):
     return exe, str(d)
 
 
+@pytest.mark.parametrize("build", ["asan_ubsan", "tsan"])
+def test_layout_reuse_matches_fresh_dissection(tmp_path, build):
+    """4x4x4 subdomains of 8^3: the eight interior ones (and the other
+    repeated shapes) reuse one dissection; the checker compares every level-1
+    layout with a plan that dissects each subdomain afresh, then runs a
+    reused subdomain's schedule against the dense Cholesky.  Built with
+    ASan + UBSan and with ThreadSanitizer (threads wait for an equal
+    structure that another thread is dissecting)."""
+    cxx = shutil.which("g++") or shutil.which("clang++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "schedule_check")
+    flags = {**BUILDS, "tsan": ["-O1", "-g", "-fsanitize=thread"]}[build]
+    cmd = [cxx, *flags, "-std=c++17", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+           os.path.join(ROOT, "tests", "schedule_check.cpp"), os.path.join(CSRC, "plan.cpp"), "-o", exe, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    n = 32
+    w = box_workload("reuse", "elasticity", (n,) * 3, [uniform_cuts(n, 4)] * 3, groups=(), young=None, seed=0)
+    p = Problem(w)
+    p.elem_nodes.tofile(tmp_path / "elem_nodes.bin")
+    p.dirichlet.tofile(tmp_path / "dirichlet.bin")
+    p.elem_to_sub.tofile(tmp_path / "elem_to_sub.bin")
+    (tmp_path / "meta.txt").write_text(f"{p.dim} {p.ndof} {p.n_nodes} {p.n_elems} {p.nodes_per_elem} {p.n_levels} "
+                                       f"0 {p.constraints}\n")
+    sub = 1 + 4 + 16 * 2     # an interior subdomain
+    env = {**os.environ, **SAN_ENV, "MLBDDC_VERBOSE": "1", "TSAN_OPTIONS": "halt_on_error=1"}
+    r = subprocess.run([exe, str(tmp_path), str(sub), "3"], capture_output=True, text=True, timeout=900, env=env)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr[-3000:]
+    reused = [l for l in r.stderr.splitlines() if "layouts reuse" in l]
+    assert reused and int(reused[0].split("] ")[1].split()[0]) >= 30, r.stderr[-2000:]
+
+
 @pytest.mark.parametrize("sub,panel", [(13, 2), (0, 4), (4, 3)])
 def test_schedule_reproduces_dense_cholesky(checker, sub, panel):
     exe, d = checker
