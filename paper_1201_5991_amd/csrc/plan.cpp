@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <unordered_map>
+#include <unordered_set>
 #include <numeric>
 #include <thread>
 #include <mutex>
@@ -586,7 +587,10 @@ void build_globs(LevelPlan& L, const std::vector<int64_t>& node_iface, const std
 struct LayoutCache {
   struct Entry {
     std::vector<int32_t> key;
-    std::vector<int32_t> order, gsize, gheight, sptr, srow;
+    std::vector<int32_t> order, gsize, gheight, sptr, srow;  // dissection and tile structure
+    std::vector<int32_t> gperm;                              // interface order (positions in node order)
+    std::vector<int32_t> elocal, envK, ecolor;               // element maps, envelope, element colours
+    int32_t ncolor = 0;
     bool ready = false;  // guarded by the cache's mutex
   };
   std::mutex mx;
@@ -676,10 +680,19 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
 
   mark("subdomain node sets");
   // --- node -> subdomains (CSR, sorted by subdomain)
+  // (threads own node ranges; each visits every subdomain's sorted node list
+  // from the first node of its range, so subdomains stay in increasing order)
   std::vector<int32_t>& cnt = plan.w_cnt;
   cnt.assign(L.n_nodes + 1, 0);
-  for (int32_t b = 0; b < ns; ++b)
-    for (int64_t n : sub_nodes[b]) cnt[n + 1]++;
+  const int TN = std::min(plan_threads(L.n_nodes), std::max(1, (int)std::min<int64_t>(16, L.n_nodes / 65536)));
+  auto node_range = [&](int t, auto&& visit) {
+    const int64_t n0 = L.n_nodes * t / TN, n1 = L.n_nodes * (t + 1) / TN;
+    for (int32_t b = 0; b < ns; ++b) {
+      const auto& v = sub_nodes[b];
+      for (auto it = std::lower_bound(v.begin(), v.end(), n0); it != v.end() && *it < n1; ++it) visit(*it, b);
+    }
+  };
+  parallel_run(TN, [&](int t) { node_range(t, [&](int64_t n, int32_t) { cnt[n + 1]++; }); });
   std::vector<int64_t>& nptr = plan.w_nptr;
   nptr.assign(L.n_nodes + 1, 0);
   for (int64_t n = 0; n < L.n_nodes; ++n) nptr[n + 1] = nptr[n] + cnt[n + 1];
@@ -688,8 +701,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
   {
     std::vector<int64_t>& pos = plan.w_pos;
     pos.assign(nptr.begin(), nptr.end() - 1);
-    for (int32_t b = 0; b < ns; ++b)
-      for (int64_t n : sub_nodes[b]) nsub[pos[n]++] = b;
+    parallel_run(TN, [&](int t) { node_range(t, [&](int64_t n, int32_t b) { nsub[pos[n]++] = b; }); });
   }
   auto mult = [&](int64_t n) { return nptr[n + 1] - nptr[n]; };
 
@@ -852,8 +864,9 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
 
     // interface nodes sorted by the first interior position they couple to, so
     // that the tile envelope of the interface rows is tight
-    std::vector<int64_t> key(gnodes.size(), INT64_MAX);
+    std::vector<int64_t> key(hit ? 0 : gnodes.size(), INT64_MAX);
     for (int64_t e : S.elems) {
+      if (hit) break;
       int64_t mn = INT64_MAX;
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
         int64_t n = L.el_nodes[j];
@@ -864,11 +877,15 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
         if (n >= 0 && node_is_g[n]) key[node_local[n]] = std::min(key[node_local[n]], mn);
       }
     }
-    std::vector<size_t> order(gnodes.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) {
-      return key[a] != key[c] ? key[a] < key[c] : gnodes[a] < gnodes[c];
-    });
+    std::vector<int32_t> order(gnodes.size());
+    if (hit) {
+      order = hit->gperm;
+    } else {
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return key[a] != key[c] ? key[a] < key[c] : gnodes[a] < gnodes[c];
+      });
+    }
     std::vector<int64_t> gsorted(gnodes.size());
     for (size_t i = 0; i < order.size(); ++i) gsorted[i] = gnodes[order[i]];
     gnodes.swap(gsorted);
@@ -888,6 +905,12 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     };
     const int64_t nK = S.nIp + S.nGp + (L.augmentK ? S.nIp : 0);
     const int64_t ntK = nK / TS;
+    if (hit) {  // the element maps and the envelope of the equal structure
+      size_t q = 0;
+      for (int64_t e : S.elems)
+        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) L.el_local[j] = hit->elocal[q++];
+      S.envK = hit->envK;
+    } else {
     std::vector<int64_t> first(nK);
     for (int64_t p = 0; p < nK; ++p) first[p] = p;
     if (L.augmentK)
@@ -912,6 +935,7 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
       for (int64_t p = r * TS; p < (r + 1) * TS; ++p) m = std::min(m, first[p]);
       S.envK[r] = (int32_t)(m / TS);
     }
+    }
     if (hit) {
       S.sptr = hit->sptr;
       S.srow = hit->srow;
@@ -924,7 +948,10 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
       mine->gheight = S.gheight;
       mine->sptr = S.sptr;
       mine->srow = S.srow;
-      cache.publish(mine);
+      mine->gperm = order;
+      mine->envK = S.envK;
+      for (int64_t e : S.elems)
+        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) mine->elocal.push_back(L.el_local[j]);
     }
 
     // constraint rows and R_Ci
@@ -946,7 +973,14 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     // greedy colouring of the subdomain's elements: elements sharing a node get
     // different colours (only elements of one subdomain write the same matrix)
     int ncol = 0;
+    if (hit) {
+      if (hit->ecolor.size() != S.elems.size()) sub_fail[b] = 2;  // the colouring of the structure failed
+      else
+        for (size_t q = 0; q < S.elems.size(); ++q) L.el_color[S.elems[q]] = hit->ecolor[q];
+      ncol = hit->ncolor;
+    }
     for (int64_t e : S.elems) {
+      if (hit) break;
       uint64_t used = 0;
       for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j)
         if (L.el_nodes[j] >= 0) used |= node_mask[L.el_nodes[j]];
@@ -958,6 +992,11 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
         if (L.el_nodes[j] >= 0) node_mask[L.el_nodes[j]] |= (1ull << c);
     }
     sub_colors[b] = ncol;
+    if (mine) {
+      for (int64_t e : S.elems) mine->ecolor.push_back(L.el_color[e]);
+      mine->ncolor = ncol;
+      cache.publish(mine);
+    }
 
     for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_mask[n] = 0; }
   }
@@ -969,6 +1008,16 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t c) { return sub_nodes[a].size() > sub_nodes[c].size(); });
+    if (reuse_layouts) {  // one subdomain of every (node count, element count) first, so that few wait
+      std::unordered_set<uint64_t> seen;
+      std::vector<int32_t> lead, rest;
+      for (int32_t b : order) {
+        const uint64_t sig = ((uint64_t)sub_nodes[b].size() << 32) ^ (uint64_t)L.subs[b].elems.size();
+        (seen.insert(sig).second ? lead : rest).push_back(b);
+      }
+      order = lead;
+      order.insert(order.end(), rest.begin(), rest.end());
+    }
     std::atomic<int32_t> next{0};
     parallel_run(plan_threads(ns), [&](int t) {
       for (int32_t i = next++; i < ns; i = next++) work(t, order[i], order[i] + 1);

@@ -1487,62 +1487,76 @@ mlbddc_status Handle::validate_level(int li, int part) {
       if (J.off[i] < lead_end || J.nlead[i] < 0) return bad(L + "job matrix extent");
       lead_end = J.off[i] + J.nlead[i] * TE;
       if (lead_end > J.elems) return bad(L + "job matrix extent");
-      if (J.tmap_off[i] >= 0) {  // a tile map: slots in range, the trailing block packed on its own
+      if (J.tmap_off[i] >= 0) {
         const int nt = J.nt[i], e1 = J.items[i].e1;
         if (!J.items[i].sptr || J.tmap_off[i] + packed_tiles(nt) > (int64_t)J.tmap.size() || e1 > nt)
           return bad(L + "tile map extent");
         const int64_t t0 = J.off[i] + J.tslot0[i] * TE, t1 = t0 + packed_tiles(nt - e1) * TE;
         if (J.tslot0[i] < 0 || t0 < std::max(trail_end, (int64_t)0) || t1 > J.elems) return bad(L + "tile map trailing block");
         trail_end = t1;
-        const int32_t* m = J.tmap.data() + J.tmap_off[i];
-        for (int c = 0; c < e1; ++c)
-          for (int r = c; r < nt; ++r) {
-            const int32_t q = m[tile_index(r, c, nt)];
-            if (q < -1 || q >= J.nlead[i]) return bad(L + "tile map entry");
-          }
-        for (int c = e1; c < nt; ++c)
-          for (int r = c; r < nt; ++r)
-            if (m[tile_index(r, c, nt)] != J.tslot0[i] + tile_index(r - e1, c - e1, nt - e1))
-              return bad(L + "tile map trailing block");
-        for (int k = 0; k < e1; ++k)  // the structure's tiles and the diagonal
-          if (m[tile_index(k, k, nt)] < 0) return bad(L + "tile map misses a tile");
-        for (int k = 0; k < e1; ++k)
-          for (int32_t q = J.items[i].sptr[k]; q < J.items[i].sptr[k + 1]; ++q)
-            if (J.items[i].srow[q] > k && J.items[i].srow[q] < nt && m[tile_index(J.items[i].srow[q], k, nt)] < 0)
-              return bad(L + "tile map misses a tile");
       } else if (J.nlead[i] != packed_tiles(J.nt[i]) || J.tslot0[i] != -1) {
         return bad(L + "job matrix extent");
       }
+      if (J.inv_off[i] + (int64_t)(J.items[i].e1 + J.items[i].e2) * TE > std::max<int64_t>(J.inv_elems, 1))
+        return bad(L + "inverse tile extent");
+      if (J.items[i].e1 + J.items[i].e2 > J.nt[i]) return bad(L + "elimination beyond the matrix");
+      if ((int)J.env[i].size() != J.nt[i]) return bad(L + "envelope size");
+      if (J.nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
     }
     for (size_t i = 0; i < ni; ++i)  // the first trailing block lies after every leading part
       if (J.tmap_off[i] >= 0) {
         if (J.off[i] + J.tslot0[i] * TE < lead_end) return bad(L + "tile map trailing block");
         break;
       }
-    for (size_t i = 0; i < ni; ++i) {
-      if (J.inv_off[i] + (int64_t)(J.items[i].e1 + J.items[i].e2) * TE > std::max<int64_t>(J.inv_elems, 1))
-        return bad(L + "inverse tile extent");
-      if (J.items[i].e1 + J.items[i].e2 > J.nt[i]) return bad(L + "elimination beyond the matrix");
-      if ((int)J.env[i].size() != J.nt[i]) return bad(L + "envelope size");
-      if (J.nt[i] >= 8192) return bad(L + "matrix too large for the task encoding");
-      // tile structure: a column's rows below the diagonal lie in its own group or in higher groups
+    // per matrix (on several threads): map entries in range, the trailing block
+    // packed on its own, every tile of the structure stored, and a column's rows
+    // below the diagonal in its own dissection group or in higher groups
+    auto item_ok = [&](size_t i) -> const char* {
       const FactorItemDesc& it = J.items[i];
+      const int nt = J.nt[i];
+      if (J.tmap_off[i] >= 0) {
+        const int e1 = it.e1;
+        const int32_t* m = J.tmap.data() + J.tmap_off[i];
+        for (int c = 0; c < e1; ++c)
+          for (int r = c; r < nt; ++r) {
+            const int32_t q = m[tile_index(r, c, nt)];
+            if (q < -1 || q >= J.nlead[i]) return "tile map entry";
+          }
+        for (int c = e1; c < nt; ++c)
+          for (int r = c; r < nt; ++r)
+            if (m[tile_index(r, c, nt)] != J.tslot0[i] + tile_index(r - e1, c - e1, nt - e1)) return "tile map trailing block";
+        for (int k = 0; k < e1; ++k)  // the structure's tiles and the diagonal
+          if (m[tile_index(k, k, nt)] < 0) return "tile map misses a tile";
+        for (int k = 0; k < e1; ++k)
+          for (int32_t q = it.sptr[k]; q < it.sptr[k + 1]; ++q)
+            if (it.srow[q] > k && it.srow[q] < nt && m[tile_index(it.srow[q], k, nt)] < 0) return "tile map misses a tile";
+      }
       if (it.sptr) {
         if (it.e2 != 0 || !it.gtile || !it.gheight || it.ngroups < 1 || it.gtile[0] != 0 || it.gtile[it.ngroups] != it.e1)
-          return bad(L + "tile structure groups");
+          return "tile structure groups";
         std::vector<int32_t> grp(it.e1, 0);
         for (int g = 0; g < it.ngroups; ++g) {
-          if (it.gtile[g + 1] < it.gtile[g]) return bad(L + "tile structure groups");
+          if (it.gtile[g + 1] < it.gtile[g]) return "tile structure groups";
           for (int k = it.gtile[g]; k < it.gtile[g + 1]; ++k) grp[k] = g;
         }
         for (int k = 0; k < it.e1; ++k)
           for (int32_t q = it.sptr[k]; q < it.sptr[k + 1]; ++q) {
             const int r = it.srow[q];
-            if (r <= k || r >= J.nt[i]) return bad(L + "tile structure rows");
+            if (r <= k || r >= nt) return "tile structure rows";
             if (r < it.e1 && grp[r] != grp[k] && it.gheight[grp[r]] <= it.gheight[grp[k]])
-              return bad(L + "dissection groups couple out of order");
+              return "dissection groups couple out of order";
           }
       }
+      return nullptr;
+    };
+    {
+      const int T = (int)std::min<size_t>(16, std::max<size_t>(1, ni / 8));
+      std::vector<const char*> whys(T, nullptr);
+      parallel_run(T, [&](int t) {
+        for (size_t i = ni * t / T; i < ni * (t + 1) / T && !whys[t]; ++i) whys[t] = item_ok(i);
+      });
+      for (const char* w : whys)
+        if (w) return bad(L + w);
     }
     if ((int64_t)ni >= MAX_TASK_ITEMS) return bad(L + "too many matrices for the task encoding");
     // every task against its launch kind and its matrix (launches split over threads)
