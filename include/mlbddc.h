@@ -67,7 +67,8 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   int32_t panel_tiles_precond; /* same for the constrained local problems (0 = tune table / 4) */
   const char* tune_table;      /* path of a tune table written by the autotuner, or NULL;
-                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]" */
+                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]"
+                                  and "MV <f64|f32> 0 <tiles per workgroup>" */
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */
@@ -77,6 +78,9 @@ typedef struct {
   int32_t stage_cols;  /* columns of a tile staged per step of the MFMA tile products of the
                           factorizations: 16, 32 or 64 (0 = from the tune table, else 32).  Every value
                           gives bitwise the same results */
+  int32_t mv_group_tiles; /* stored tiles per workgroup of the large tile matrix-vector products (S^,
+                          the level-1 local operators): 1 or 2 (0 = from the tune table per precision,
+                          else 1).  Both give bitwise the same results */
 } mlbddc_options;
 
 typedef struct {

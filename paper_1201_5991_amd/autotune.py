@@ -1,4 +1,5 @@
-"""Autotuner for the batched tile factorizations: panel width and staged columns.
+"""Autotuner: panel width and staged columns of the batched tile
+factorizations, tiles per workgroup of the tile matrix-vector products.
 
 For each workload and precision, every candidate pair (panel width in tile
 columns per panel, columns of a tile staged per step of the MFMA tile
@@ -8,6 +9,7 @@ and the fastest pair per (job kind, precision, size bucket) is written to the
 tune table that the library reads at set-up:
 
     <K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> <stage>
+    MV <f64|f32> 0 <tiles per workgroup of the tile matrix-vector products>
 
 The staged columns do not change the results (the products accumulate in the
 same order); the panel width changes only the order of independent updates.
@@ -24,6 +26,7 @@ import sys
 
 CANDIDATES = (2, 3, 4, 6)        # panel widths
 STAGES = (16, 32, 64)            # staged columns per step
+MV_GROUP_TILES = (1, 2)          # stored tiles per workgroup of the tile products
 
 
 def _bucket(n: int) -> int:
@@ -70,11 +73,45 @@ def tune(configs, reps: int = 2, log=print):
                         agg[key][(p, sc)] += t
                     log(f"config {k} {prec} panel {p} stage {sc}: K {best[0]*1e3:.2f} ms ({keyK[2]}), "
                         f"M {best[1]*1e3:.2f} ms ({keyM[1]} {keyM[2]})")
+    # tiles per workgroup of the large tile products: S^ and G products timed
+    # with events, summed over the workloads, per product precision
+    mv = {("MV", "f64", 0): {}, ("MV", "f32", 0): {}}
+    for k in configs:
+        prob = Problem(config(k))
+        for prec in ("fp64", "mixed"):
+            for tpw in MV_GROUP_TILES:
+                s = Solver(precision=prec, mv_group_tiles=tpw, tune_table=None)
+                s.setup(prob)
+                r = torch.randn(s.n_iface, dtype=torch.float64, device="cuda")
+                z = torch.empty_like(r)
+                for _ in range(5):
+                    s.apply_into(r, z)
+                    s.apply_schur_into(r, z)
+                s.set_profiling(True)
+                for _ in range(20):
+                    s.apply_schur_into(r, z)
+                    s.apply_into(r, z)
+                torch.cuda.synchronize()
+                p = s.profile()
+                s.set_profiling(False)
+                s.destroy()
+                t_s = p["schur_mv"]["time_s"] / max(p["schur_mv"]["launches"], 1)
+                t_g = p["precond_mv"]["time_s"] / max(p["precond_mv"]["launches"], 1)
+                mv[("MV", "f64", 0)][tpw] = mv[("MV", "f64", 0)].get(tpw, 0.0) + t_s
+                gkey = ("MV", "f32" if prec == "mixed" else "f64", 0)
+                mv[gkey][tpw] = mv[gkey].get(tpw, 0.0) + t_g
+                log(f"config {k} {prec} tiles per workgroup {tpw}: S^ product {t_s*1e3:.3f} ms, "
+                    f"G product {t_g*1e3:.3f} ms")
+    agg.update(mv)
     table = {}
     for key, cand in agg.items():
         table[key] = min(cand, key=lambda q: cand[q])
-        log(f"{' '.join(map(str, key))}: panel {table[key][0]} stage {table[key][1]} "
-            f"({cand[table[key]]*1e3:.2f} ms summed; panel 4 stage 32: {cand.get((4, 32), math.nan)*1e3:.2f} ms)")
+        if key[0] == "MV":
+            log(f"{' '.join(map(str, key))}: {table[key]} tiles per workgroup "
+                f"({', '.join(f'{q}: {v*1e3:.3f} ms' for q, v in sorted(cand.items()))} summed)")
+        else:
+            log(f"{' '.join(map(str, key))}: panel {table[key][0]} stage {table[key][1]} "
+                f"({cand[table[key]]*1e3:.2f} ms summed; panel 4 stage 32: {cand.get((4, 32), math.nan)*1e3:.2f} ms)")
     return table
 
 
@@ -82,8 +119,8 @@ def write_table(table, path):
     with open(path, "w") as fh:
         fh.write("# panel widths and staged columns chosen by paper_1201_5991_amd/autotune.py on gfx950\n")
         fh.write("# job precision ceil(log2(max tiles per side)) panel stage\n")
-        for (job, prec, b), (p, sc) in sorted(table.items()):
-            fh.write(f"{job} {prec} {b} {p} {sc}\n")
+        for (job, prec, b), v in sorted(table.items()):
+            fh.write(f"{job} {prec} {b} {v}\n" if job == "MV" else f"{job} {prec} {b} {v[0]} {v[1]}\n")
 
 
 if __name__ == "__main__":

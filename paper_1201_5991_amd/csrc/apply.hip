@@ -13,9 +13,12 @@ namespace mlbddc {
 namespace {
 
 // ---------------------------------------------------------------- tile mv
-// One workgroup per stored tile of the block: reads the tile once and forms
-// both A x_s (for the tile's row) and, for symmetric blocks, A^T x_r (for its
-// column); results go to a partial-sum array reduced by k_mv_reduce.
+// A workgroup per TPW consecutive stored tiles of a block (TPW = 1 or 2, a
+// tuning parameter; tiles in column-major order for symmetric blocks): it
+// loads all its tiles, then forms for each tile both A x_s (for the tile's
+// row) and, for symmetric blocks, A^T x_r (for its column); results go to a
+// partial-sum array reduced by k_mv_reduce.  The arithmetic of a tile does
+// not depend on TPW, so neither do the results.
 // Lane l of the workgroup's 256 keeps rows a0..a0+3 (a0 = 4 (l & 15)) of the
 // columns g, g + 16, g + 32, g + 48 (g = l >> 4), loaded as 32-byte runs of a
 // column.  Runs that hold only padding (rows or columns beyond the block's
@@ -23,7 +26,8 @@ namespace {
 // symmetric block are not loaded: the diagonal tile contributes L x (its
 // lower triangle with the diagonal) plus L_strict^T x to its own output, so
 // the whole product streams the stored lower triangle and nothing else.
-template <typename TA, typename TX>
+// `prefix` counts workgroups per block (ceil(tiles / TPW)).
+template <typename TA, typename TX, int TPW>
 __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __restrict__ d, int nitems,
                                                   const int64_t* __restrict__ prefix, const TA* __restrict__ A,
                                                   const TX* __restrict__ x, TA* __restrict__ P) {
@@ -34,87 +38,125 @@ __global__ void __launch_bounds__(256) k_mv_tiles(int mode, const MvDesc* __rest
     if (prefix[mid] <= bid) lo = mid; else hi = mid;
   }
   const MvDesc D = d[lo];
-  int64_t local = bid - prefix[lo];
-  int r, s;
+  const int64_t ntiles = mode == MV_SYM ? (int64_t)D.nr * (D.nr + 1) / 2 : (int64_t)D.nr * D.nc;
+  const int64_t local0 = (bid - prefix[lo]) * TPW;
+  const int nt = (int)(ntiles - local0 < TPW ? ntiles - local0 : TPW);
+  int rr[TPW], ss[TPW];
   if (mode == MV_SYM) {
     // column-major unranking of the lower tiles of an nr x nr block
-    s = 0;
-    int64_t rem = local;
-    while (rem >= D.nr - s) { rem -= D.nr - s; ++s; }
-    r = s + (int)rem;
+    int s0 = 0;
+    int64_t rem = local0;
+    while (rem >= D.nr - s0) { rem -= D.nr - s0; ++s0; }
+    rr[0] = s0 + (int)rem;
+    ss[0] = s0;
+#pragma unroll
+    for (int j = 1; j < TPW; ++j) {
+      rr[j] = rr[j - 1] + 1;
+      ss[j] = ss[j - 1];
+      if (rr[j] >= D.nr) ss[j] = rr[j] = ss[j - 1] + 1;
+    }
   } else {
-    r = (int)(local % D.nr);
-    s = (int)(local / D.nr);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      rr[j] = (int)((local0 + j) % D.nr);
+      ss[j] = (int)((local0 + j) / D.nr);
+    }
   }
-  const int R = D.r0 + r, S = D.c0 + s;
   const int t = threadIdx.x;
-  __shared__ TA red[16][TS];
-  __shared__ TA vcol[TS];
-  const bool zero = D.env && S < D.env[R];
-  const bool diag = mode == MV_SYM && r == s;
-  TA v_part[4] = {0, 0, 0, 0};
+  __shared__ TA red[TPW][16][TS];
+  __shared__ TA vcol[TPW][TS];
   const int a0 = 4 * (t & 15), g = t >> 4;
-  const int rv = D.vr - r * TS, cv = D.vc - s * TS;  // valid rows / columns of this tile (may exceed 64)
   const bool need_v = mode == MV_T || mode == MV_SYM;  // transposed product (strictly lower part on a diagonal tile)
   const bool need_u = mode != MV_T;
-  if (!zero) {
-    const TA* tile = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
-    const TX* xs = x + D.x_off + (int64_t)s * TS;
-    const TX* xr = x + D.x_off + (int64_t)r * TS;
-    TA up[4] = {0, 0, 0, 0};
-    TA xra[4];
+  // all tiles of the workgroup in flight before any is multiplied
+  TA av[TPW][4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) xra[i] = (need_v && a0 + i < rv) ? (TA)xr[a0 + i] : (TA)0;
+  for (int j = 0; j < TPW; ++j) {
+    const int r = rr[j], s = ss[j];
+    const int R = D.r0 + r, S = D.c0 + s;
+    const bool live = j < nt && !(D.env && S < D.env[R]);
+    const bool diag = mode == MV_SYM && r == s;
+    const int rv = D.vr - r * TS, cv = D.vc - s * TS;  // valid rows / columns of this tile (may exceed 64)
+    const TA* tile = A + D.a_off + tile_index(R, S, D.a_nt) * TE;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int b = g + 16 * m;
-      const bool col_ok = b < cv;
-      TA av[4] = {0, 0, 0, 0};
-      if (col_ok && a0 < rv && (!diag || a0 + 3 >= b)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[j][m][i] = 0;
+      if (live && b < cv && a0 < rv && (!diag || a0 + 3 >= b)) {
         const TA* col = tile + b * TS + a0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = col[i];
-      }
-      const TA xb = (need_u && col_ok) ? (TA)xs[b] : (TA)0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int a = a0 + i;
-        const TA al = (a < rv && (!diag || a >= b)) ? av[i] : (TA)0;  // lower triangle with the diagonal
-        up[i] += al * xb;
-        v_part[m] += (diag && a == b) ? (TA)0 : al * xra[i];
+        for (int i = 0; i < 4; ++i) av[j][m][i] = col[i];
       }
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) red[g][a0 + i] = up[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) red[g][a0 + i] = 0;
   }
-  // reduce v over the 16 lanes sharing g
+  TA v_part[TPW][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-    for (int off = 8; off > 0; off >>= 1) v_part[m] += __shfl_xor(v_part[m], off, 16);
-  if (diag && (t & 15) == 0)
+  for (int j = 0; j < TPW; ++j) {
+    const int r = rr[j], s = ss[j];
+    const bool live = j < nt && !(D.env && D.c0 + s < D.env[D.r0 + r]);
+    const bool diag = mode == MV_SYM && r == s;
+    const int rv = D.vr - r * TS, cv = D.vc - s * TS;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) vcol[g + 16 * m] = v_part[m];
+    for (int m = 0; m < 4; ++m) v_part[j][m] = 0;
+    if (live) {
+      const TX* xs = x + D.x_off + (int64_t)s * TS;
+      const TX* xr = x + D.x_off + (int64_t)r * TS;
+      TA up[4] = {0, 0, 0, 0};
+      TA xra[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xra[i] = (need_v && a0 + i < rv) ? (TA)xr[a0 + i] : (TA)0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int b = g + 16 * m;
+        const bool col_ok = b < cv;
+        const TA xb = (need_u && col_ok) ? (TA)xs[b] : (TA)0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int a = a0 + i;
+          const TA al = (a < rv && (!diag || a >= b)) ? av[j][m][i] : (TA)0;  // lower triangle with the diagonal
+          up[i] += al * xb;
+          v_part[j][m] += (diag && a == b) ? (TA)0 : al * xra[i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[j][g][a0 + i] = up[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[j][g][a0 + i] = 0;
+    }
+    // reduce v over the 16 lanes sharing g
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      for (int off = 8; off > 0; off >>= 1) v_part[j][m] += __shfl_xor(v_part[j][m], off, 16);
+    if (diag && (t & 15) == 0)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) vcol[j][g + 16 * m] = v_part[j][m];
+  }
   __syncthreads();
-  TA u_out = 0;
-  if (t < TS) {
-    TA acc = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc += red[q][t];
-    u_out = diag ? acc + vcol[t] : acc;
-  }
   TA* pbase = P + D.p_off;
-  if (mode == MV_SYM) {
-    if (t < TS) pbase[((int64_t)r * D.nr + s) * TS + t] = u_out;
-    if (r != s && (t & 15) == 0)
-      for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[m];
-  } else if (mode == MV_N) {
-    if (t < TS) pbase[((int64_t)r * D.nc + s) * TS + t] = u_out;
-  } else {
-    if ((t & 15) == 0)
-      for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[m];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    if (j >= nt) break;
+    const int r = rr[j], s = ss[j];
+    const bool diag = mode == MV_SYM && r == s;
+    TA u_out = 0;
+    if (t < TS) {
+      TA acc = 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc += red[j][q][t];
+      u_out = diag ? acc + vcol[j][t] : acc;
+    }
+    if (mode == MV_SYM) {
+      if (t < TS) pbase[((int64_t)r * D.nr + s) * TS + t] = u_out;
+      if (r != s && (t & 15) == 0)
+        for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[j][m];
+    } else if (mode == MV_N) {
+      if (t < TS) pbase[((int64_t)r * D.nc + s) * TS + t] = u_out;
+    } else {
+      if ((t & 15) == 0)
+        for (int m = 0; m < 4; ++m) pbase[((int64_t)s * D.nr + r) * TS + g + 16 * m] = v_part[j][m];
+    }
   }
 }
 
@@ -693,7 +735,7 @@ inline unsigned grid_for(int64_t n, int block = 256) {
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles, const int64_t* tile_prefix,
                     const TA* A, const TX* x, TY* y, double alpha, bool accumulate, TA* partials, int32_t max_out_tiles,
-                    hipEvent_t ev0, hipEvent_t ev1) {
+                    hipEvent_t ev0, hipEvent_t ev1, int tpw, int64_t groups2, const int64_t* group_prefix2) {
   if (nitems <= 0 || total_tiles <= 0) return;
   if (ev0) (void)hipEventRecord(ev0, st);
   if (total_tiles <= SMALL_MV_TILES) {  // coarse levels: one launch, no partial tiles
@@ -702,8 +744,12 @@ void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, i
     if (ev1) (void)hipEventRecord(ev1, st);
     return;
   }
-  hipLaunchKernelGGL((k_mv_tiles<TA, TX>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A, x,
-                     partials);
+  if (tpw == 2)
+    hipLaunchKernelGGL((k_mv_tiles<TA, TX, 2>), dim3((unsigned)groups2), dim3(256), 0, st, mode, d, nitems, group_prefix2, A, x,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_mv_tiles<TA, TX, 1>), dim3((unsigned)total_tiles), dim3(256), 0, st, mode, d, nitems, tile_prefix, A,
+                       x, partials);
   if (ev1) (void)hipEventRecord(ev1, st);
   hipLaunchKernelGGL((k_mv_reduce<TA, TY>), dim3((unsigned)max_out_tiles, (unsigned)nitems), dim3(256), 0, st, mode, d,
                      partials, y, alpha, accumulate ? 1 : 0);
@@ -829,7 +875,8 @@ void launch_scatter_idx(hipStream_t st, int64_t n, const int32_t* idx, const dou
   template void launch_tile_mv_sum<TA, TX, TY>(hipStream_t, int, const MvDesc*, int, const MvDesc*, int32_t, int32_t, \
                                                const TA*, const TX*, const TX*, TY*, double, bool);                   \
   template void launch_tile_mv<TA, TX, TY>(hipStream_t, int, const MvDesc*, int32_t, int64_t, const int64_t*, const TA*, \
-                                           const TX*, TY*, double, bool, TA*, int32_t, hipEvent_t, hipEvent_t);
+                                           const TX*, TY*, double, bool, TA*, int32_t, hipEvent_t, hipEvent_t, int, int64_t, \
+                                           const int64_t*);
 INST_MV(double, double, double)
 INST_MV(float, float, float)
 INST_MV(float, float, double)

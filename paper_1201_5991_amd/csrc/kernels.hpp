@@ -99,11 +99,14 @@ template <typename TA, typename TX, typename TY>
 void launch_tile_mv_sum(hipStream_t st, int mode, const MvDesc* d, int mode2, const MvDesc* d2, int32_t nitems,
                         int32_t max_out_tiles, const TA* A, const TX* x, const TX* x2, TY* y, double alpha, bool accumulate);
 // ev0 / ev1 (optional): recorded on `st` right before and after the product
-// kernel itself (k_mv_tiles or k_mv_rows), for kernel timing.
+// kernel itself (k_mv_tiles or k_mv_rows), for kernel timing.  tpw = 2: two
+// tiles per workgroup, groups2 workgroups with per-item prefix group_prefix2
+// (ceil(tiles / 2) per item); else one tile per workgroup (tile_prefix).
 template <typename TA, typename TX, typename TY>
 void launch_tile_mv(hipStream_t st, int mode, const MvDesc* d, int32_t nitems, int64_t total_tiles,
                     const int64_t* tile_prefix, const TA* A, const TX* x, TY* y, double alpha, bool accumulate,
-                    TA* partials, int32_t max_out_tiles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    TA* partials, int32_t max_out_tiles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int tpw = 1,
+                    int64_t groups2 = 0, const int64_t* group_prefix2 = nullptr);
 
 // out[i] = (w ? w[i] : 1) * in[idx[i]] (0 where idx < 0), converting types.
 template <typename TI, typename TO>

@@ -143,7 +143,8 @@ struct MvSet {
   std::vector<MvDesc> h;
   MvDesc* d = nullptr;
   int64_t* d_prefix = nullptr;
-  int64_t tiles = 0;
+  int64_t* d_prefix2 = nullptr;  // workgroups per item with two tiles per workgroup
+  int64_t tiles = 0, groups2 = 0;
   int32_t max_out = 0;
   int64_t partial_elems = 0;
 };
@@ -453,6 +454,7 @@ struct Handle {
   mlbddc_status numeric();
   bool lookahead = false;
   std::vector<std::array<int, 5>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel, staged columns or 0)
+  int mv_tpw[2] = {1, 1};                 // tiles per workgroup of the large tile products: [0] FP64, [1] FP32
   int pick_panel(int job, bool fp32, int ntmax) const;
   int pick_stage(int job, bool fp32, int ntmax) const;
   mlbddc_status reserve_job(Job& J, bool fp32);
@@ -503,21 +505,24 @@ struct Handle {
 mlbddc_status Handle::build_mv(MvSet& s, int mode, std::vector<MvDesc> descs) {
   s.mode = mode;
   s.h = std::move(descs);
-  std::vector<int64_t> prefix(s.h.size() + 1, 0);
+  std::vector<int64_t> prefix(s.h.size() + 1, 0), prefix2(s.h.size() + 1, 0);
   int64_t poff = 0;
   s.max_out = 0;
   for (size_t i = 0; i < s.h.size(); ++i) {
     MvDesc& d = s.h[i];
     int64_t tiles = mode == MV_SYM ? (int64_t)d.nr * (d.nr + 1) / 2 : (int64_t)d.nr * d.nc;
     prefix[i + 1] = prefix[i] + tiles;
+    prefix2[i + 1] = prefix2[i] + (tiles + 1) / 2;
     d.p_off = poff;
     poff += (int64_t)d.nr * d.nc * TS;
     s.max_out = std::max(s.max_out, mode == MV_T ? d.nc : d.nr);
   }
   s.tiles = prefix.back();
+  s.groups2 = prefix2.back();
   s.partial_elems = poff;
   mlbddc_status st = upload(&s.d, s.h);
   if (st) return st;
+  if ((st = upload(&s.d_prefix2, prefix2))) return st;
   return upload(&s.d_prefix, prefix);
 }
 
@@ -528,7 +533,8 @@ void Handle::run_mv(MvSet& s, const Job& J, const TX* x, TY* y, double alpha, bo
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (cls >= 0 && prof) mv_timing(cls, bytes, st, &e0, &e1);
   launch_tile_mv<TA, TX, TY>(st, s.mode, s.d, (int32_t)s.h.size(), s.tiles, s.d_prefix, (const TA*)J.buf, x, y, alpha, acc,
-                             (TA*)partial, s.max_out, e0, e1);
+                             (TA*)partial, s.max_out, e0, e1, sizeof(TA) == 4 ? mv_tpw[1] : mv_tpw[0], s.groups2,
+                             s.d_prefix2);
 }
 
 void Handle::mv_timing(int cls, double bytes, hipStream_t on, hipEvent_t* e0, hipEvent_t* e1) {
@@ -2369,6 +2375,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->lookahead = 0;
   o->side_stream = 1;
   o->stage_cols = 0;
+  o->mv_group_tiles = 0;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream) {
@@ -2391,7 +2398,8 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
   if (opt) o = *opt;
   if (o.device < 0 || o.device >= ndev || !(o.rtol > 0) || o.max_iter < 1 ||
       (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED) ||
-      (o.stage_cols != 0 && o.stage_cols != 16 && o.stage_cols != 32 && o.stage_cols != 64)) {
+      (o.stage_cols != 0 && o.stage_cols != 16 && o.stage_cols != 32 && o.stage_cols != 64) ||
+      (o.mv_group_tiles != 0 && o.mv_group_tiles != 1 && o.mv_group_tiles != 2)) {
     g_create_error.status = MLBDDC_E_ARG;
     g_create_error.message = "invalid options";
     return MLBDDC_E_ARG;
@@ -2420,12 +2428,18 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
       std::istringstream ls(line);
       std::string job, prec;
       int bucket = 0, panel = 0, stage = 0;
-      if (!(ls >> job >> prec >> bucket >> panel) || panel < 1 || panel > 16) continue;
+      if (!(ls >> job >> prec >> bucket >> panel)) continue;
+      if (job == "MV") {  // tiles per workgroup of the tile products
+        if (panel == 1 || panel == 2) h->h.mv_tpw[prec == "f32" ? 1 : 0] = panel;
+        continue;
+      }
+      if (panel < 1 || panel > 16) continue;
       if (!(ls >> stage) || (stage != 16 && stage != 32 && stage != 64)) stage = 0;
       h->h.tune.push_back({job == "M" ? 1 : 0, prec == "f32" ? 1 : 0, bucket, panel, stage});
     }
     h->h.opt.tune_table = nullptr;  // the path is not kept
   }
+  if (o.mv_group_tiles > 0) h->h.mv_tpw[0] = h->h.mv_tpw[1] = o.mv_group_tiles;
   h->h.stream = (hipStream_t)stream;
   if (alloc) {
     h->h.ext_alloc = *alloc;

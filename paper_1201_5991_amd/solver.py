@@ -142,7 +142,7 @@ class Solver:
     def __init__(self, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000, weights: str = "stiffness",
                  device: int = 0, panel_tiles: int = 0, use_graph: bool = False, panel_tiles_precond: int = 0,
                  tune_table: Optional[str] = TUNE_TABLE, lookahead: bool = False, side_stream: bool = True,
-                 stage_cols: int = 0):
+                 stage_cols: int = 0, mv_group_tiles: int = 0):
         lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the BDDC library needs a HIP device")
@@ -162,6 +162,7 @@ class Solver:
         opt.lookahead = 1 if lookahead else 0
         opt.side_stream = 1 if side_stream else 0
         opt.stage_cols = stage_cols
+        opt.mv_group_tiles = mv_group_tiles
         opt.device = device
         self.opt = opt
         with torch.cuda.device(self.device):

@@ -305,6 +305,33 @@ def test_staged_columns_same_result(precision):
         assert _rel(out[32][1].cpu().numpy(), b.apply(rr)) < RTOL64
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mv_group_tiles_same_result(precision):
+    """The large tile products (S^, the level-1 local operators) take one or
+    two stored tiles per workgroup with the same per-tile arithmetic: the
+    operators and the solve agree bitwise."""
+    from paper_1201_5991_amd import Problem, Solver
+    _say(f"[parity] tiles per workgroup 1 / 2, {precision}")
+    # 3^3 subdomains of 8^3 elements: interface blocks of 10-19 tiles, odd tile counts per block
+    w = _cube(3, 8, young=10 ** (2 * np.random.default_rng(11).random(24 ** 3)))
+    prob = Problem(w)
+    f = torch.tensor(prob.load_vector(), device="cuda")
+    out = {}
+    r = None
+    for tpw in (1, 2):
+        s = Solver(precision=precision, mv_group_tiles=tpw, use_graph=True).setup(prob)
+        if r is None:
+            r = torch.tensor(np.random.default_rng(12).standard_normal(s.n_iface), device="cuda")
+        u, st = s.solve(f)
+        out[tpw] = (s.apply_schur(r), s.apply(r), u, st["iterations"])
+        s.destroy()
+    assert out[1][3] == out[2][3]
+    for a, b in zip(out[1][:3], out[2][:3]):
+        assert torch.equal(a, b)
+    b = MultilevelBDDC(w)
+    assert _rel(out[2][0].cpu().numpy(), b.schur_apply(r.cpu().numpy())) < RTOL64
+
+
 def test_side_stream_same_result():
     """Mixed precision at 48^3 (the G product takes the side stream there):
     the level-1 G product beside the coarse levels (fork / join on a second
