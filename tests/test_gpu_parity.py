@@ -332,6 +332,31 @@ def test_mv_group_tiles_same_result(precision):
     assert _rel(out[2][0].cpu().numpy(), b.schur_apply(r.cpu().numpy())) < RTOL64
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_update_coefficients_matches_fresh_setup(precision):
+    """A numeric re-set-up with new element moduli (the plan, layouts and
+    schedules kept) gives bitwise the operators and solve of a set-up from
+    scratch with those moduli, on dissection-ordered, tile-mapped factors."""
+    from paper_1201_5991_amd import Problem, Solver
+    _say(f"[parity] update_coefficients vs fresh set-up, {precision}")
+    rng = np.random.default_rng(13)
+    w1 = _cube(2, 8, young=10 ** (2 * rng.random(16 ** 3)))
+    w2 = _cube(2, 8, young=10 ** (2 * rng.random(16 ** 3)))
+    p1, p2 = Problem(w1), Problem(w2)
+    f = torch.tensor(p2.load_vector(), device="cuda")
+    s1 = Solver(precision=precision).setup(p1)
+    s1.update_coefficients(torch.tensor(w2.young, device="cuda"))
+    s2 = Solver(precision=precision).setup(p2)
+    r = torch.tensor(np.random.default_rng(14).standard_normal(s1.n_iface), device="cuda")
+    assert torch.equal(s1.apply_schur(r), s2.apply_schur(r))
+    assert torch.equal(s1.apply(r), s2.apply(r))
+    u1, st1 = s1.solve(f)
+    u2, st2 = s2.solve(f)
+    assert st1["iterations"] == st2["iterations"] and torch.equal(u1, u2)
+    b = MultilevelBDDC(w2)
+    assert _rel(s1.apply_schur(r).cpu().numpy(), b.schur_apply(r.cpu().numpy())) < RTOL64
+
+
 def test_side_stream_same_result():
     """Mixed precision at 48^3 (the G product takes the side stream there):
     the level-1 G product beside the coarse levels (fork / join on a second
