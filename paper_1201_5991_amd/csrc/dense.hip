@@ -102,17 +102,25 @@ __device__ inline void for_acc(typename Mfma<T>::acc_t (&acc)[2][2], F f) {
 }
 
 // ------------------------------------------------------------------ assembly
-// One workgroup per element: A += scale * Ke on the lower tiles of the
-// owning subdomain's matrix.  el_local holds, per element node, the local
-// index of the node's first DOF (its nd DOFs are consecutive) or -1.
+// One wavefront per element (four per workgroup): A += scale * Ke on the
+// lower tiles of the owning subdomain's matrix.  el_local holds, per element
+// node, the local index of the node's first DOF (its nd DOFs are consecutive)
+// or -1.  Consecutive lanes take consecutive rows of one element column, so a
+// node's nd rows are one contiguous run of a tile column.  An entry that falls
+// in a tile the map does not store is skipped and raises *err.
 template <typename T>
-__global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ elems, const int32_t* __restrict__ el_local_ptr,
+__global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ elems, int64_t n,
+                                                  const int32_t* __restrict__ el_local_ptr,
                                                   const int32_t* __restrict__ el_local, int nd, const int32_t* __restrict__ el_sub,
                                                   const int64_t* __restrict__ sub_off, const int32_t* __restrict__ sub_nt,
                                                   const double* __restrict__ Kref, const double* __restrict__ scale,
                                                   const int64_t* __restrict__ ekc_off, const double* __restrict__ ekc, T* A,
-                                                  const int32_t* __restrict__ tmap, const int64_t* __restrict__ tmap_off) {
-  const int64_t e = elems[blockIdx.x];
+                                                  const int32_t* __restrict__ tmap, const int64_t* __restrict__ tmap_off,
+                                                  int32_t* err) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = elems[i];
   const int b = el_sub[e];
   const int32_t base = el_local_ptr[e];
   const int nloc = (el_local_ptr[e + 1] - base) * nd;
@@ -120,15 +128,26 @@ __global__ void __launch_bounds__(256) k_assemble(const int64_t* __restrict__ el
   const int nt = sub_nt[b];
   const double sc = Kref ? scale[e] : 1.0;
   const double* M = Kref ? Kref : ekc + ekc_off[e];
-  for (int idx = threadIdx.x; idx < nloc * nloc; idx += blockDim.x) {
-    const int a = idx / nloc, c = idx - a * nloc;
+  for (int idx = lane; idx < nloc * nloc; idx += 64) {
+    const int c = idx / nloc, a = idx - c * nloc;
     const int na = a / nd, nc = c / nd;
     const int ka = el_local[base + na], kc = el_local[base + nc];
     if (ka < 0 || kc < 0) continue;
     const int p = ka + (a - na * nd), q = kc + (c - nc * nd);
     if (p / TS < q / TS) continue;
-    A[off + tile_slot(tmap, tmap_off, b, p / TS, q / TS, nt) * TE + (q % TS) * TS + (p % TS)] += (T)(sc * M[idx]);
+    const int64_t slot = tile_slot(tmap, tmap_off, b, p / TS, q / TS, nt);
+    if (slot < 0) {
+      atomicOr(err, 1);
+      continue;
+    }
+    A[off + slot * TE + (q % TS) * TS + (p % TS)] += (T)(sc * M[a * nloc + c]);
   }
+}
+
+// Zero n16 16-byte words.
+__global__ void __launch_bounds__(256) k_zero16(uint4* __restrict__ p, int64_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256) p[i] = z;
 }
 
 template <typename T>
@@ -590,10 +609,17 @@ template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr, const int32_t* el_local,
                      int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt, const double* Kref,
                      const double* scale, const int64_t* ekc_off, const double* ekc, T* A, const int32_t* tmap,
-                     const int64_t* tmap_off) {
+                     const int64_t* tmap_off, int32_t* err) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)n), dim3(256), 0, st, elems, el_local_ptr, el_local, nd, el_sub, sub_off,
-                     sub_nt, Kref, scale, ekc_off, ekc, A, tmap, tmap_off);
+  hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, elems, n, el_local_ptr, el_local, nd,
+                     el_sub, sub_off, sub_nt, Kref, scale, ekc_off, ekc, A, tmap, tmap_off, err);
+}
+
+void launch_zero(hipStream_t st, void* p, size_t bytes, int max_blocks) {
+  if (bytes == 0) return;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, std::max(1, max_blocks));
+  hipLaunchKernelGGL(k_zero16, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, (uint4*)p, n16);
 }
 
 template <typename T>
@@ -657,7 +683,7 @@ void launch_coarse_matrix(hipStream_t st, const KcDesc* d, int32_t nitems, int32
 #define INST_T(T)                                                                                                         \
   template void launch_assemble<T>(hipStream_t, const int64_t*, int64_t, const int32_t*, const int32_t*, int, const int32_t*, \
                                    const int64_t*, const int32_t*, const double*, const double*, const int64_t*,        \
-                                   const double*, T*, const int32_t*, const int64_t*);                                  \
+                                   const double*, T*, const int32_t*, const int64_t*, int32_t*);                        \
   template void launch_set_diag<T>(hipStream_t, const DiagSeg*, int64_t, int32_t, T*, const int32_t*, const int64_t*); \
   template void launch_factor_step<T>(hipStream_t, int, int, const FactorArgs&, int64_t, int64_t, T*, T*);             \
 

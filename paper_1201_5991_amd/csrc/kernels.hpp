@@ -16,12 +16,16 @@ namespace mlbddc {
 // e of subdomain el_sub[e] adds entry (a, c) of its matrix at local position
 // (el_local[ptr+a], el_local[ptr+c]).  The element matrix is
 // scale[e] * Kref (Kref != null) or ekc[ekc_off[e] ...] (row-major, nloc^2).
-// Subdomain b's matrix is tile-mapped when tmap is set and tmap_off[b] >= 0.
+// Subdomain b's matrix is tile-mapped when tmap is set and tmap_off[b] >= 0;
+// an entry in a tile the map does not store is skipped and sets *err to 1.
 template <typename T>
 void launch_assemble(hipStream_t st, const int64_t* elems, int64_t n, const int32_t* el_local_ptr,
                      const int32_t* el_local, int nd, const int32_t* el_sub, const int64_t* sub_off, const int32_t* sub_nt,
                      const double* Kref, const double* scale, const int64_t* ekc_off, const double* ekc, T* A,
-                     const int32_t* tmap, const int64_t* tmap_off);
+                     const int32_t* tmap, const int64_t* tmap_off, int32_t* err);
+// Zero `bytes` bytes at p (16-byte aligned, bytes a multiple of 16) with at
+// most max_blocks workgroups (fewer leave HBM bandwidth to concurrent work).
+void launch_zero(hipStream_t st, void* p, size_t bytes, int max_blocks = 16384);
 
 // Set entries A[row0+i][col0+i] = val for every segment (tile-packed
 // matrices; `item` indexes the tile map, -1 = dense packed-lower).

@@ -644,7 +644,8 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
 
   // --- subdomain node sets and elements
   std::vector<std::vector<int64_t>> sub_nodes(ns);
-  L.subs.assign(ns, SubPlan());
+  L.subs.resize(ns);  // a previous plan's subdomains keep their storage
+  for (SubPlan& S : L.subs) S.reset();
   {
     std::vector<int64_t> cnt(ns, 0);
     for (int64_t e = 0; e < ne; ++e) {
@@ -1067,6 +1068,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
       L.el_local_ptr.swap(old[i].el_local_ptr);
       L.el_local.swap(old[i].el_local);
       L.el_color.swap(old[i].el_color);
+      L.subs.swap(old[i].subs);
       L.el_nodes.clear();
     }
     return L;
@@ -1118,6 +1120,7 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
   mlbddc_status st = build_level(L1, in.constraints, err, plan, in.reuse_layouts);
   if (st != MLBDDC_OK) return st;
   plan.levels.push_back(std::move(L1));
+  mark("level 1 done");
 
   // ---- levels 2..L-1 and the top level from the pseudo-mesh
   for (int l = 2; l <= in.n_levels; ++l) {
@@ -1155,6 +1158,9 @@ mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err) {
     if (st != MLBDDC_OK) return st;
     plan.levels.push_back(std::move(L));
   }
+  mark("levels 2..L");
+  old.clear();
+  mark("release previous plan");
   return MLBDDC_OK;
 }
 

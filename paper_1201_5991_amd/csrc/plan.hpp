@@ -63,6 +63,13 @@ struct SubPlan {
   std::vector<int64_t> elems;
   // tile envelope (first nonzero tile column per tile row) of the local K matrix
   std::vector<int32_t> envK;
+  // empty every field, keeping the vectors' storage for the next plan
+  void reset() {
+    nI = nG = nIp = nGp = 0;
+    nc = ncp = 0;
+    for (auto* v : {&dofI, &dofG, &elems}) v->clear();
+    for (auto* v : {&padI, &gtile, &sptr, &srow, &gheight, &iface, &coarse, &crow_ptr, &crow_col, &envK}) v->clear();
+  }
 };
 
 struct LevelPlan {

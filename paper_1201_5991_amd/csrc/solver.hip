@@ -34,6 +34,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <atomic>
 #include <fstream>
 #include <future>
 #include <map>
@@ -285,12 +286,15 @@ struct Handle {
   int panel_nt[2] = {0, 0};  // largest matrix (tiles per side) of each job kind in this set-up
   std::vector<hipEvent_t> events;
 
+  std::mutex err_mu;  // set-up threads (checks, queueing) may fail together
   mlbddc_status herr(const char* what, hipError_t e) {
+    std::lock_guard<std::mutex> g(err_mu);
     err.status = MLBDDC_E_HIP;
     err.message = std::string(what) + ": " + hipGetErrorString(e);
     return err.status;
   }
   mlbddc_status fail(mlbddc_status st, const std::string& m, int level = 0, int sub = -1, int col = -1) {
+    std::lock_guard<std::mutex> g(err_mu);
     err.status = st;
     err.message = m;
     err.level = level;
@@ -412,6 +416,28 @@ struct Handle {
         std::memcpy(h, src, bytes);
       HIPCHK(hipMemcpyAsync(*p, h, bytes, hipMemcpyHostToDevice, ustream));
     }
+    return MLBDDC_OK;
+  }
+  // Like upload, for an array that fill(dst) writes straight into the pinned
+  // staging memory (no host copy of it is kept)
+  template <typename T, typename F>
+  mlbddc_status upload_fill(T** p, int64_t n, F&& fill) {
+    mlbddc_status st = dalloc(p, n);
+    if (st || n <= 0) return st;
+    if ((st = ensure_ustream())) return st;
+    char* h = nullptr;
+    const size_t bytes = sizeof(T) * (size_t)n;
+    if ((st = stage(bytes, &h))) return st;
+    if ((st = fill(reinterpret_cast<T*>(h)))) return st;
+    HIPCHK(hipMemcpyAsync(*p, h, bytes, hipMemcpyHostToDevice, ustream));
+    return MLBDDC_OK;
+  }
+  // Zero device memory with the wide fill kernel (16-byte stores over many
+  // workgroups), or hipMemsetAsync for an unaligned block.
+  mlbddc_status zero_async(void* p, size_t bytes, hipStream_t s) {
+    if (((uintptr_t)p % 16) == 0 && bytes % 16 == 0) launch_zero(s, p, bytes);
+    else HIPCHK(hipMemsetAsync(p, 0, bytes, s));
+    HIPCHK(hipGetLastError());
     return MLBDDC_OK;
   }
   mlbddc_status upload_fence() {
@@ -880,7 +906,7 @@ mlbddc_status Handle::reserve_job(Job& J, bool fp32) {
   J.buf = b;
   J.inv = iv;
   if ((st = ensure_ustream())) return st;
-  if (tot > 0) HIPCHK(hipMemsetAsync(J.buf, 0, (size_t)tot * esz, ustream));
+  if (tot > 0 && (st = zero_async(J.buf, (size_t)tot * esz, ustream))) return st;
   if (msz > 0) {
     if ((st = upload(&J.d_tmap, J.tmap))) return st;
     if ((st = upload(&J.d_tmap_off, J.tmap_off))) return st;
@@ -914,7 +940,9 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   if ((st = upload(&J.d_inv_off, J.inv_off))) return st;
   if ((st = upload(&J.d_nt, J.nt))) return st;
   if ((st = upload(&J.d_tasks, J.sched.tasks))) return st;
-  if ((st = dalloc(&J.d_err, 2))) return st;
+  // [0] item + 1 and [1] column of the first non-positive pivot; [2] set by
+  // an assembly entry that falls in an unstored tile
+  if ((st = dalloc(&J.d_err, 3))) return st;
   mark("uploads");
   return MLBDDC_OK;
 }
@@ -1077,6 +1105,23 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     D.kfp32 = mixed && li > 0 && !P.top;
     D.mfp32 = mixed;
     const int ns = P.n_sub;
+    // ---- storage of the constrained problems first: zeroing it on the upload
+    // stream (at full bandwidth) starts while the host lays out the K job, and
+    // no zeroing runs beside a factorization
+    if (!P.top) {
+      D.M.nt.resize(ns);
+      D.M.items.resize(ns);
+      for (int b = 0; b < ns; ++b) {
+        const SubPlan& S = P.subs[b];
+        const int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
+        D.M.nt[b] = 2 * (tG + tC);
+        D.M.items[b].nt = D.M.nt[b];
+        D.M.items[b].e1 = tG;
+        D.M.items[b].e2 = tC;
+      }
+      if ((st = reserve_job(D.M, D.mfp32))) return st;
+      mark("  M job storage");
+    }
     // ---- K job
     D.K.nt.resize(ns);
     D.K.items.resize(ns);
@@ -1099,21 +1144,6 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     }
     if ((st = prepare_job(D.K, D.kfp32))) return st;
     flops_K += D.K.sched.flops;
-    // storage of the constrained problems now, so that zeroing it does not
-    // run beside the factorization of K
-    if (!P.top) {
-      D.M.nt.resize(ns);
-      D.M.items.resize(ns);
-      for (int b = 0; b < ns; ++b) {
-        const SubPlan& S = P.subs[b];
-        const int tG = (int)(S.nGp / TS), tC = S.ncp / TS;
-        D.M.nt[b] = 2 * (tG + tC);
-        D.M.items[b].nt = D.M.nt[b];
-        D.M.items[b].e1 = tG;
-        D.M.items[b].e2 = tC;
-      }
-      if ((st = reserve_job(D.M, D.mfp32))) return st;
-    }
     mark("  K job layout + schedule");
 
     // diagonal segments of the K matrices: padding and identity block
@@ -1133,19 +1163,36 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     // another thread while this one builds the assembly and flat layouts
     // (they read only the plan, the K job and the segments above)
     std::future<mlbddc_status> checked = std::async(std::launch::async, [this, li] { return validate_level(li, 0); });
+    std::future<mlbddc_status> checked_job = std::async(std::launch::async, [this, li] { return validate_level(li, 2); });
 
     // assembly data
     {
-      // elements grouped by colour (counting sort, element order kept within a colour)
-      D.color_ptr.assign(P.n_colors + 1, 0);
-      for (int32_t c : P.el_color) D.color_ptr[c + 1]++;
-      for (int c = 0; c < P.n_colors; ++c) D.color_ptr[c + 1] += D.color_ptr[c];
-      std::vector<int64_t> byc(P.el_color.size());
-      {
-        std::vector<int64_t> pos(D.color_ptr.begin(), D.color_ptr.end() - 1);
-        for (size_t el = 0; el < P.el_color.size(); ++el) byc[pos[P.el_color[el]]++] = (int64_t)el;
-      }
-      if ((st = upload(&D.d_elems_by_color, byc))) return st;
+      // elements grouped by colour, within a colour by subdomain (each matrix
+      // entry gets at most one contribution per colour, so the order inside a
+      // colour does not change the sums); counts per (colour, subdomain) on
+      // threads, then every subdomain places its elements
+      const int nc = P.n_colors;
+      std::vector<int64_t> cnt((size_t)nc * ns + 1, 0);  // [colour][subdomain]
+      const int T = std::min(16, std::max(1, ns / 16));
+      parallel_run(T, [&](int t) {
+        for (int b = ns * t / T; b < ns * (t + 1) / T; ++b)
+          for (int64_t e : P.subs[b].elems) cnt[(size_t)P.el_color[e] * ns + b + 1]++;
+      });
+      for (size_t q = 1; q < cnt.size(); ++q) cnt[q] += cnt[q - 1];
+      D.color_ptr.assign(nc + 1, 0);
+      for (int c = 0; c <= nc; ++c) D.color_ptr[c] = cnt[(size_t)c * ns];
+      if ((st = upload_fill(&D.d_elems_by_color, (int64_t)P.el_color.size(), [&](int64_t* byc) {
+             parallel_run(T, [&](int t) {
+               std::vector<int64_t> pos(nc);
+               for (int b = ns * t / T; b < ns * (t + 1) / T; ++b) {
+                 for (int c = 0; c < nc; ++c) pos[c] = cnt[(size_t)c * ns + b];
+                 for (int64_t e : P.subs[b].elems) byc[pos[P.el_color[e]]++] = e;
+               }
+             });
+             return MLBDDC_OK;
+           })))
+        return st;
+      mark("    colour order");
       if ((st = upload(&D.d_el_local_ptr, P.el_local_ptr))) return st;
       if ((st = upload(&D.d_el_local, P.el_local))) return st;
       if ((st = upload(&D.d_el_sub, P.el_sub))) return st;
@@ -1154,6 +1201,7 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
       if (li > 0) {
         if ((st = upload(&D.d_ekc_off, lev[li - 1].kc_off))) return st;
       }
+      mark("    element uploads");
     }
 
     // flat offsets and the positions of the interface diagonal in the K
@@ -1170,30 +1218,38 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
     D.nI_flat = D.iofs[ns];
     D.nC_flat = D.cofs[ns];
     if (!P.top) {
-      std::vector<int64_t> gdiag(D.nG_flat, 0);
-      parallel_run(std::min(16, ns), [&](int t) {
-        for (int b = t; b < ns; b += std::min(16, ns)) {
-          const SubPlan& S = P.subs[b];
-          int64_t o;
-          int32_t n, f;
-          D.K.trailing(b, (int)(S.nIp / TS), o, n, f);
-          for (int64_t k = 0; k < S.nGp; ++k) gdiag[D.gofs[b] + k] = o + packed_offset(f * TS + k, f * TS + k, n);
-        }
-      });
-      for (int64_t v : gdiag)
-        if (v < 0 || v >= D.K.elems) return fail(MLBDDC_E_ARG, "internal layout check failed: interface diagonal position");
-      if ((st = upload(&D.d_gdiag_pos, gdiag))) return st;
+      std::atomic<bool> gbad{false};
+      if ((st = upload_fill(&D.d_gdiag_pos, D.nG_flat, [&](int64_t* gdiag) {
+             parallel_run(std::min(16, ns), [&](int t) {
+               for (int b = t; b < ns; b += std::min(16, ns)) {
+                 const SubPlan& S = P.subs[b];
+                 int64_t o;
+                 int32_t n, f;
+                 D.K.trailing(b, (int)(S.nIp / TS), o, n, f);
+                 for (int64_t k = 0; k < S.nGp; ++k) {
+                   const int64_t v = o + packed_offset(f * TS + k, f * TS + k, n);
+                   gdiag[D.gofs[b] + k] = v;
+                   if (v < 0 || v >= D.K.elems) gbad = true;
+                 }
+               }
+             });
+             return gbad ? fail(MLBDDC_E_ARG, "internal layout check failed: interface diagonal position") : MLBDDC_OK;
+           })))
+        return st;
     }
     if ((st = dalloc(&D.gd, std::max<int64_t>(D.nG_flat, 1)))) return st;
 
     mark("  assembly maps");
-    // the device assembles and factorizes K while the host builds the flat layouts
+    // the device assembles and factorizes K while the host builds the flat
+    // layouts; the factorization is queued once its own checks are done
     if ((st = checked.get())) return st;
-    mark("  validate (K job)");
+    mark("  validate (assembly)");
     if ((st = join())) return st;
     if ((st = upload_fence())) return st;
     enqueue_async(li, 0);
     if ((st = join())) return st;
+    if ((st = checked_job.get())) return st;
+    mark("  validate (K job)");
     enqueue_async(li, 1);
     // flat layouts
     {
@@ -1478,12 +1534,20 @@ mlbddc_status Handle::setup(const mlbddc_mesh* mesh, const mlbddc_partition* par
 }
 
 // Host check of every index the kernels will use against the buffers they
-// address, run once per set-up before any kernel touches the data.
+// address, run once per set-up before any kernel touches the data: part 0
+// what the assembly and the weights use, part 2 the K job, part 1 the rest
+// (whether every element entry falls in a stored tile the assembly kernel
+// checks itself: it skips such an entry and raises the K job's error word).
 mlbddc_status Handle::validate_level(int li, int part) {
   auto bad = [&](const std::string& what) { return fail(MLBDDC_E_ARG, "internal layout check failed: " + what); };
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   const std::string L = "level " + std::to_string(li + 1) + ": ";
+  double t_v = now();
+  auto vmark = [&](const char* what) {
+    if (verbose) std::fprintf(stderr, "[mlbddc check L%d] %-24s %8.2f ms\n", li + 1, what, (now() - t_v) * 1e3);
+    t_v = now();
+  };
   auto job_ok = [&](const Job& J) -> mlbddc_status {
     if (J.nt.empty()) return MLBDDC_OK;
     const size_t ni = J.nt.size();
@@ -1514,6 +1578,7 @@ mlbddc_status Handle::validate_level(int li, int part) {
         if (J.off[i] + J.tslot0[i] * TE < lead_end) return bad(L + "tile map trailing block");
         break;
       }
+    vmark("job extents");
     // per matrix (on several threads): map entries in range, the trailing block
     // packed on its own, every tile of the structure stored, and a column's rows
     // below the diagonal in its own dissection group or in higher groups
@@ -1564,6 +1629,7 @@ mlbddc_status Handle::validate_level(int li, int part) {
       for (const char* w : whys)
         if (w) return bad(L + w);
     }
+    vmark("job matrices");
     if ((int64_t)ni >= MAX_TASK_ITEMS) return bad(L + "too many matrices for the task encoding");
     // every task against its launch kind and its matrix (launches split over threads)
     auto check = [&](size_t l0, size_t l1) -> const char* {
@@ -1604,6 +1670,7 @@ mlbddc_status Handle::validate_level(int li, int part) {
     parallel_run(T, [&](int t) { whys[t] = check(nl * t / T, nl * (t + 1) / T); });
     for (const char* w : whys)
       if (w) return bad(L + w);
+    vmark("job tasks");
     return MLBDDC_OK;
   };
   auto seg_ok = [&](const std::vector<DiagSeg>& v) {
@@ -1616,32 +1683,20 @@ mlbddc_status Handle::validate_level(int li, int part) {
     return true;
   };
   mlbddc_status st;
-  if (part == 0) {  // what assembly, weights and the K job use
-    if ((st = job_ok(D.K))) return st;
-    // element maps and subdomain maps, split over threads
+  if (part == 2) return job_ok(D.K);  // the K job's matrices and tasks
+  if (part == 0) {  // what assembly and weights use
+    // element maps and subdomain maps, split over threads (that every entry
+    // falls in a stored tile is checked by the assembly kernel itself)
     const int64_t ne = (int64_t)P.el_local_ptr.size() - 1, ns = (int64_t)P.subs.size();
     const int T = (int)std::min<int64_t>(16, std::max<int64_t>(1, ne / 4096));
     std::vector<const char*> whys(T, nullptr);
     parallel_run(T, [&](int t) {
-      std::vector<int32_t> tl;  // distinct tiles of an element's DOFs
       for (int64_t e = ne * t / T; e < ne * (t + 1) / T; ++e) {
         int b = P.el_sub[e];
         if (b < 0 || b >= (int64_t)P.subs.size()) { whys[t] = "element subdomain"; return; }
         int64_t nK = (int64_t)D.K.nt[b] * TS;
         for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
           if (P.el_local[j] < -1 || (int64_t)P.el_local[j] + P.ndof > nK) { whys[t] = "element map"; return; }
-        if (D.K.tmap_off[b] >= 0) {  // every tile the element's entries fall in is stored
-          tl.clear();
-          for (int32_t j = P.el_local_ptr[e]; j < P.el_local_ptr[e + 1]; ++j)
-            if (P.el_local[j] >= 0)
-              for (int32_t q : {P.el_local[j] / TS, (P.el_local[j] + P.ndof - 1) / TS})  // a node's DOFs span <= 2 tiles
-                if (std::find(tl.begin(), tl.end(), q) == tl.end()) tl.push_back(q);
-          const int32_t* m = D.K.tmap.data() + D.K.tmap_off[b];
-          const int nt = D.K.nt[b];
-          for (int32_t a : tl)
-            for (int32_t c : tl)
-              if (a >= c && m[tile_index(a, c, nt)] < 0) { whys[t] = "element tile not stored"; return; }
-        }
         if (li > 0) {
           const LevelPlan& PP = *lev[li - 1].P;
           int64_t nloc = (int64_t)(P.el_local_ptr[e + 1] - P.el_local_ptr[e]) * P.ndof;
@@ -1665,6 +1720,7 @@ mlbddc_status Handle::validate_level(int li, int part) {
     if (!seg_ok(D.ksegs_h)) return bad(L + "diagonal segment");
     for (int64_t d : P.iface_dofs)
       if (d < 0 || d >= P.n_dofs) return bad(L + "interface DOF");
+    vmark("elements, subdomain maps");
     return MLBDDC_OK;
   }
   // M job, products of the apply, coarse matrices
@@ -1774,10 +1830,12 @@ mlbddc_status Handle::enqueue_K(int li, bool zero) {
 }
 
 mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
+  mlbddc_status st;
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
   // assemble K
-  if (zero) HIPCHK(hipMemsetAsync(D.K.buf, 0, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream));
+  if (zero && (st = zero_async(D.K.buf, (size_t)D.K.elems * (D.kfp32 ? 4 : 8), stream))) return st;
+  HIPCHK(hipMemsetAsync(D.K.d_err + 2, 0, sizeof(int32_t), stream));
   for (int c = 0; c < P.n_colors; ++c) {
     int64_t n = D.color_ptr[c + 1] - D.color_ptr[c];
     const int64_t* el = D.d_elems_by_color + D.color_ptr[c];
@@ -1785,11 +1843,11 @@ mlbddc_status Handle::enqueue_K_assembly(int li, bool zero) {
     const double* ekc = li == 0 ? nullptr : lev[li - 1].kc_compact;
     if (D.kfp32)
       launch_assemble<float>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                             d_scale, D.d_ekc_off, ekc, (float*)D.K.buf, D.K.d_tmap, D.K.d_tmap_off);
+                             d_scale, D.d_ekc_off, ekc, (float*)D.K.buf, D.K.d_tmap, D.K.d_tmap_off, D.K.d_err + 2);
     else
       launch_assemble<double>(stream, el, n, D.d_el_local_ptr, D.d_el_local, P.ndof, D.d_el_sub, D.d_sub_off, D.d_sub_nt, kref,
-                              d_scale, D.d_ekc_off, ekc, (double*)D.K.buf, D.K.d_tmap,
-                              D.K.d_tmap_off);
+                              d_scale, D.d_ekc_off, ekc, (double*)D.K.buf, D.K.d_tmap, D.K.d_tmap_off,
+                              D.K.d_err + 2);
   }
   if (D.kfp32)
     launch_set_diag<float>(stream, D.d_ksegs, (int64_t)D.ksegs_h.size(), D.kseg_max, (float*)D.K.buf, D.K.d_tmap,
@@ -1835,7 +1893,7 @@ mlbddc_status Handle::enqueue_rest(int li, bool zero) {
   LevelPlan& P = *D.P;
   if (P.top) return MLBDDC_OK;
   // preconditioner matrices
-  if (zero) HIPCHK(hipMemsetAsync(D.M.buf, 0, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream));
+  if (zero && (st = zero_async(D.M.buf, (size_t)D.M.elems * (D.mfp32 ? 4 : 8), stream))) return st;
   if (D.kfp32) {  // K is FP32 only when M is FP32
     launch_copy_block<float, float>(stream, D.d_copy, P.n_sub, D.copy_max, (const float*)D.K.buf, (float*)D.M.buf);
     launch_constraints<float, float>(stream, D.d_cons, (int64_t)D.cons_h.size(), D.d_ccols, (const float*)D.K.buf,
@@ -1865,7 +1923,7 @@ mlbddc_status Handle::enqueue_rest(int li, bool zero) {
 // that met a non-positive pivot (levels in order, K job before M job).
 mlbddc_status Handle::finish_numeric() {
   // every job's error words copied behind the last job, then one wait
-  const size_t nw = 4 * lev.size();
+  const size_t nw = 6 * lev.size();
   if (h_err_cap < nw) {
     if (h_err) (void)hipHostFree(h_err);
     h_err = nullptr;
@@ -1875,14 +1933,17 @@ mlbddc_status Handle::finish_numeric() {
   for (size_t li = 0; li < lev.size(); ++li)
     for (int j = 0; j < 2; ++j) {
       const Job& J = j == 0 ? lev[li].K : lev[li].M;
-      int32_t* e = h_err + 4 * li + 2 * j;
-      e[0] = e[1] = 0;
-      if (J.d_err) HIPCHK(hipMemcpyAsync(e, J.d_err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      int32_t* e = h_err + 6 * li + 3 * j;
+      e[0] = e[1] = e[2] = 0;
+      if (J.d_err) HIPCHK(hipMemcpyAsync(e, J.d_err, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     }
   HIPCHK(hipStreamSynchronize(stream));
   for (size_t li = 0; li < lev.size(); ++li)
     for (int j = 0; j < 2; ++j) {
-      const int32_t* e = h_err + 4 * li + 2 * j;
+      const int32_t* e = h_err + 6 * li + 3 * j;
+      if (j == 0 && e[2] != 0)
+        return fail(MLBDDC_E_ARG, "internal layout check failed: level " + std::to_string(lev[li].P->level) +
+                                      ": element entry in an unstored tile");
       if (e[0] != 0) {
         const int level = lev[li].P->level, sub = e[0] - 1;
         if (j == 1) return fail(MLBDDC_E_SINGULAR_CONSTRAINTS, "constrained local problem is singular", level, sub, e[1]);
