@@ -591,7 +591,7 @@ struct LayoutCache {
     std::vector<int32_t> gperm;                              // interface order (positions in node order)
     std::vector<int32_t> elocal, envK, ecolor;               // element maps, envelope, element colours
     int32_t ncolor = 0;
-    bool ready = false;  // guarded by the cache's mutex
+    std::atomic<bool> ready{false};  // set under the cache's mutex
   };
   std::mutex mx;
   std::condition_variable cv;
@@ -603,17 +603,36 @@ struct LayoutCache {
   }
   // The entry of key k, waiting while another thread computes it; or a new
   // entry that the caller computes and then publishes (claimed = true).
+  // Keys are compared outside the lock (an entry's key never changes; a
+  // hash's entry list only grows), so threads do not queue behind compares.
   std::shared_ptr<Entry> get(std::vector<int32_t>& k, uint64_t h, bool& claimed) {
+    std::vector<std::shared_ptr<Entry>> seen;
+    {
+      std::lock_guard<std::mutex> g(mx);
+      auto it = map.find(h);
+      if (it != map.end()) seen = it->second;
+    }
+    auto take = [&](const std::shared_ptr<Entry>& e) {
+      if (!e->ready) {
+        std::unique_lock<std::mutex> g(mx);
+        cv.wait(g, [&] { return e->ready.load(); });
+      }
+      claimed = false;
+      return e;
+    };
+    for (const auto& e : seen)
+      if (e->key == k) return take(e);
     std::unique_lock<std::mutex> g(mx);
-    for (const auto& e : map[h])
-      if (e->key == k) {
-        cv.wait(g, [&] { return e->ready; });
-        claimed = false;
-        return e;
+    auto& list = map[h];
+    for (size_t q = seen.size(); q < list.size(); ++q)  // entries added meanwhile
+      if (list[q]->key == k) {
+        std::shared_ptr<Entry> e = list[q];
+        g.unlock();
+        return take(e);
       }
     auto e = std::make_shared<Entry>();
     e->key = std::move(k);
-    map[h].push_back(e);
+    list.push_back(e);
     claimed = true;
     return e;
   }
@@ -800,13 +819,23 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     std::shared_ptr<LayoutCache::Entry> mine, hit;  // the entry this subdomain computes, or reuses
     if (keyed) {
       const int32_t ni = (int32_t)inodes.size();
-      skey = {ni, (int32_t)gnodes.size(), nd, (int32_t)S.elems.size()};
+      size_t nel = 0, nnb = 0;  // element node entries; other subdomains of the interface nodes and separators
+      for (int64_t e : S.elems) nel += (size_t)(L.el_ptr[e + 1] - L.el_ptr[e]);
+      for (int64_t v : gnodes) nnb += (size_t)(nptr[v + 1] - nptr[v]);
+      skey.reserve(4 + nel + nnb);
+      skey.resize(4 + nel);
+      skey[0] = ni;
+      skey[1] = (int32_t)gnodes.size();
+      skey[2] = nd;
+      skey[3] = (int32_t)S.elems.size();
+      int32_t* kp = skey.data() + 4;
       for (int64_t e : S.elems)
         for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
           const int64_t v = L.el_nodes[j];
-          skey.push_back(v < 0 ? -1 : node_is_g[v] ? ni + node_local[v] : node_local[v]);
+          *kp++ = v < 0 ? -1 : node_local[v] + (node_is_g[v] ? ni : 0);
         }
       std::vector<int32_t> nb;
+      nb.reserve(nnb);
       for (int64_t v : gnodes)
         for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
           if (nsub[q] != b) nb.push_back(nsub[q]);
