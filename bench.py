@@ -69,7 +69,7 @@ def algorithmic_apply_bytes(s, precision: str) -> dict:
 # Source sections whose PMC traffic figures are valid only for the code they were measured on.
 KERNEL_SOURCES = {
     "k_tile_mm": ("dense.hip", "// Register staging of NE consecutive elements",
-                  "template <typename T>\n__global__ void __launch_bounds__(256) k_negate("),
+                  "// ----------------------------------------------------- preconditioner set-up"),
     "k_mv_tiles": ("apply.hip", "// ---------------------------------------------------------------- tile mv",
                    "// Sum of the partial tiles of one output tile"),
 }

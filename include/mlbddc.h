@@ -253,7 +253,8 @@ enum {
   MLBDDC_PROF_UPDATE_FP32 = 1,  /* trailing / in-panel tile updates, FP32 MFMA */
   MLBDDC_PROF_PANEL = 2,        /* panel solves with inverted diagonal tiles */
   MLBDDC_PROF_DIAG = 3,         /* diagonal tile factor + inverse */
-  MLBDDC_PROF_NEGATE = 4,       /* sign flips between elimination phases */
+  MLBDDC_PROF_NEGATE = 4,       /* sign flips between elimination phases (none are launched: the second
+                                   phase reads the first phase's trailing block with the opposite sign) */
   MLBDDC_PROF_SCHUR_MV = 5,     /* S^ tile products (k_mv_tiles, FP64) */
   MLBDDC_PROF_PRECOND_MV = 6,   /* level-1 G_i tile products (k_mv_tiles, FP32 or FP64) */
   MLBDDC_PROF_N = 8

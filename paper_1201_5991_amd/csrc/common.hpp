@@ -57,8 +57,16 @@ __host__ __device__ inline int task_r(uint64_t t) { return (int)((t >> 16) & 0x1
 __host__ __device__ inline int task_s(uint64_t t) { return (int)((t >> 29) & 0x1FFF); }
 __host__ __device__ inline int task_kf(uint64_t t) { return (int)((t >> 42) & 0x1FFF); }
 __host__ __device__ inline int task_nk(uint64_t t) { return (int)((t >> 55) & 0xFF); }
+// Bit 63: a task of the second elimination phase of a two-phase item, whose
+// trailing block the first phase leaves as the negative of the matrix the
+// second phase factors.  Such tasks read that block with the opposite sign:
+// the diagonal factor negates its tile on load, a panel product stores
+// -(T W^T), an update adds its product instead of subtracting it.  Tiles the
+// second phase does not factor keep the opposite sign to the end.
+constexpr uint64_t TASK_NEG = 1ull << 63;
+__host__ __device__ inline bool task_neg(uint64_t t) { return (t >> 63) != 0; }
 
-// Kinds of factorization steps (one launch each).
+// Kinds of factorization steps (one launch each; L_NEGATE is no longer scheduled).
 enum LaunchKind { L_NEGATE = 0, L_INPANEL = 1, L_DIAG = 2, L_PANEL = 3, L_TRAIL = 4 };
 
 struct Error {

@@ -268,6 +268,8 @@ __global__ void __launch_bounds__(256) k_diag(const uint64_t* __restrict__ tasks
   T* gA = A + off[item] + tile_slot(tmap, tmap_off, item, k, k, nt) * TE;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   stage_tile<T, T>(sA, gA, false);
+  if (task_neg(t))  // second phase: the stored block is the negative of the matrix factored (own entries only)
+    for (int idx = tid; idx < TE; idx += 256) sA[(idx >> 6) * LDT + (idx & (TS - 1))] = -sA[(idx >> 6) * LDT + (idx & (TS - 1))];
   __syncthreads();
   int badcol = -1;
 #pragma unroll 1
@@ -526,18 +528,9 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
   }
   tile_nt_ld<T, LDU, KS>(acc, sR, same ? sR : sS);
   int n = 0;
-  if (PANEL) for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = v; });
-  else for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - v; });
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_negate(const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off,
-                                                const int32_t* __restrict__ ntv, T* A, const int32_t* __restrict__ tmap,
-                                                const int64_t* __restrict__ tmap_off) {
-  const uint64_t t = tasks[blockIdx.x];
-  const int item = task_item(t), r = task_r(t), s = task_s(t);
-  T* g = A + off[item] + tile_slot(tmap, tmap_off, item, r, s, ntv[item]) * TE;
-  for (int idx = threadIdx.x; idx < TE; idx += blockDim.x) g[idx] = -g[idx];
+  const T sg = task_neg(t) ? (T)-1 : (T)1;  // second-phase task: the block is stored negated
+  if (PANEL) for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = sg * v; });
+  else for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - sg * v; });
 }
 
 // ----------------------------------------------------- preconditioner set-up
@@ -584,9 +577,11 @@ __global__ void __launch_bounds__(256) k_constraints(const ConsDesc* __restrict_
 }
 
 // K_Ci = A_i^{-1} - W_i: after both elimination phases the coarse block of
-// the constrained-problem matrix holds -A_i^{-1} (A_i = C S~^{-1} C^T); since
-// C Psi = I, Psi^T S Psi = Psi^T S~ Psi - W = A^{-1} - W.  Lower triangle
-// read, full row-major block written.
+// the constrained-problem matrix holds A_i^{-1} (A_i = C S~^{-1} C^T; the
+// second phase leaves the blocks it does not factor with the opposite sign
+// of the eliminated matrix's -A_i^{-1}); since C Psi = I,
+// Psi^T S Psi = Psi^T S~ Psi - W = A^{-1} - W.  Lower triangle read, full
+// row-major block written.
 template <typename TP>
 __global__ void k_coarse_from_M(const KcDesc* __restrict__ d, const TP* __restrict__ P, const double* __restrict__ rho,
                                 double* __restrict__ out) {
@@ -596,7 +591,7 @@ __global__ void k_coarse_from_M(const KcDesc* __restrict__ d, const TP* __restri
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nc * nc; idx += gridDim.x * blockDim.x) {
     const int a = idx / nc, b = idx - a * nc;
     const int hi = a > b ? a : b, lo = a > b ? b : a;
-    double v = -(double)P[c.p_off + packed_offset(c0 + hi, c0 + lo, c.p_nt)];
+    double v = (double)P[c.p_off + packed_offset(c0 + hi, c0 + lo, c.p_nt)];
     if (a == b) v -= rho[c.rho_off + a];
     out[c.out_off + idx] = v;
   }
@@ -649,7 +644,6 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
     }
   };
   switch (kind) {
-    case L_NEGATE: hipLaunchKernelGGL(k_negate<T>, grid, blk, 0, st, tk, a.off, a.nt, A, a.tmap, a.tmap_off); break;
     case L_INPANEL: mm(false); break;
     case L_DIAG:
       hipLaunchKernelGGL(k_diag<T>, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, a.err, A, Inv, a.tmap, a.tmap_off);

@@ -1200,7 +1200,7 @@ namespace {
 // SK_NXT for the first sibling and SK_SIB + j for sibling j: siblings update
 // shared separator and interface tiles, so they must not share a launch.
 constexpr int MAX_SIBLINGS = 32;
-enum { SK_NEG = 0, SK_INP = 1, SK_DIA = 2, SK_PAN = 3, SK_NXT = 4, SK_RST = 5, SK_SIB = 5, SK_N = 5 + MAX_SIBLINGS };
+enum { SK_INP = 0, SK_DIA = 1, SK_PAN = 2, SK_NXT = 3, SK_RST = 4, SK_SIB = 4, SK_N = 4 + MAX_SIBLINGS };
 
 // Step layout of a tile-structured item: first step of every group and the
 // sibling index of the group among the groups of its height; false when the
@@ -1318,26 +1318,28 @@ void enumerate_item(const FactorItemDesc& it, uint64_t b, int panel, bool lookah
     int ph0 = k < e1 ? 0 : e1, ph1 = k < e1 ? e1 : e1 + e2;
     int k0 = ph0 + ((k - ph0) / panel) * panel;
     int kend = std::min(k0 + panel, ph1);
-    if (k == e1 && e2 > 0)
-      for (int s = e1; s < nt; ++s)
-        for (int r = s; r < nt; ++r) emit(k, SK_NEG, pack_task(b, r, s, 0), 0.0);
+    // second phase: the trailing block after the first is the negative of the
+    // matrix it factors; its tasks carry TASK_NEG instead of a negation pass
+    const uint64_t neg = k >= e1 ? TASK_NEG : 0;
     // act holds the rows with env <= k - 1 here
     if (k > k0 && env[k] <= k - 1)
       for (auto q = std::lower_bound(act.begin(), act.end(), k); q != act.end(); ++q)
-        emit(k, SK_INP, pack_task(b, *q, k, k0, k - 1 - k0), 2.0 * t3 * (k - k0));
+        emit(k, SK_INP, pack_task(b, *q, k, k0, k - 1 - k0) | neg, 2.0 * t3 * (k - k0));
     if (k > 0) admit(k);  // now env <= k
-    emit(k, SK_DIA, pack_task(b, k, k, 0), 2.0 * t3 / 3.0);
+    emit(k, SK_DIA, pack_task(b, k, k, 0) | neg, 2.0 * t3 / 3.0);
     const auto first_after_k = std::upper_bound(act.begin(), act.end(), k);
-    for (auto q = first_after_k; q != act.end(); ++q) emit(k, SK_PAN, pack_task(b, *q, k, 0), 2.0 * t3);
+    for (auto q = first_after_k; q != act.end(); ++q) emit(k, SK_PAN, pack_task(b, *q, k, 0) | neg, 2.0 * t3);
     if (k == kend - 1) {
       // columns of the item's next panel (same phase): with look-ahead they are
       // updated first, on the critical stream
       int nxt_end = k + 1;
       if (lookahead && k + 1 < ph1) nxt_end = std::min(k + 1 + panel, ph1);
+      else if (lookahead && k + 1 == e1 && e2 > 0) nxt_end = nt;  // the second phase starts on this block next
       for (auto qs = first_after_k; qs != act.end(); ++qs) {
         const int s = *qs;
         const int dst = (!lookahead || s < nxt_end) ? SK_NXT : SK_RST;
-        for (auto qr = qs; qr != act.end(); ++qr) emit(k, dst, pack_task(b, *qr, s, k0, k - k0), 2.0 * t3 * (k - k0 + 1));
+        for (auto qr = qs; qr != act.end(); ++qr)
+          emit(k, dst, pack_task(b, *qr, s, k0, k - k0) | neg, 2.0 * t3 * (k - k0 + 1));
       }
     }
   }
@@ -1380,8 +1382,7 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
   // offsets: slot-major, thread-minor (= item order within a slot)
   std::vector<std::vector<int64_t>> off(T, std::vector<int64_t>(slots, 0));
   int64_t total = 0;
-  auto kind_of = [](int l) { return l == SK_NEG ? L_NEGATE : l == SK_INP ? L_INPANEL : l == SK_DIA ? L_DIAG
-                                 : l == SK_PAN ? L_PANEL : L_TRAIL; };
+  auto kind_of = [](int l) { return l == SK_INP ? L_INPANEL : l == SK_DIA ? L_DIAG : l == SK_PAN ? L_PANEL : L_TRAIL; };
   for (size_t sl = 0; sl < slots; ++sl) {
     int64_t n = 0;
     double f = 0.0;
@@ -1395,7 +1396,7 @@ void build_factor_schedule(const std::vector<FactorItemDesc>& items, int panel, 
       FactorLaunch L{kind_of(l), k, total, n, f, 0, false};
       if (lookahead) {
         if (l == SK_RST) { L.stream = 1; L.wait = true; }   // after the panel and the next-panel update
-        if (l == SK_NXT || l == SK_NEG) L.wait = true;     // after the previous bulk update
+        if (l == SK_NXT) L.wait = true;                    // after the previous bulk update
       }
       if (L.kind == L_TRAIL || L.kind == L_INPANEL) out.update_tasks += n;
       out.flops += f;

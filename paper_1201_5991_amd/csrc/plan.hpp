@@ -140,7 +140,8 @@ struct Plan {
 mlbddc_status build_plan(const PlanInput& in, Plan& plan, Error& err);
 
 // Factorization schedule of a batch of tile-packed matrices, each eliminated
-// in one or two phases (the trailing block is negated between the phases).
+// in one or two phases (the second factors the negative of the first phase's
+// trailing block: its tasks carry TASK_NEG).
 struct FactorItemDesc {
   int32_t nt = 0;                       // tiles per side
   int32_t e1 = 0, e2 = 0;               // tile columns eliminated per phase

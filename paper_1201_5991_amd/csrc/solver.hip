@@ -13,8 +13,9 @@
 //              [ C           0     0    I  ]
 //              [ I           0     0    0  ]
 //              [ 0           I     0    0  ]
-//            is eliminated in two phases (the trailing block is negated in
-//            between).  The result holds G_i = S~^{-1} - S~^{-1}C^T A^{-1} C S~^{-1}
+//            is eliminated in two phases (the second factors the negative of
+//            the first phase's trailing block, reading it with the opposite
+//            sign, so the blocks it leaves hold -G_i, -Psi_i and A^{-1}).  The result holds G_i = S~^{-1} - S~^{-1}C^T A^{-1} C S~^{-1}
 //            (A = C S~^{-1} C^T), the operator of the constrained local problem
 //            of Eq. (2) restricted to the interface, and Psi_i^T, the coarse basis
 //            of Eq. (1); the penalty W (rho = sum of the glob's diagonal entries
@@ -1657,7 +1658,6 @@ mlbddc_status Handle::validate_level(int li, int part) {
             case L_PANEL: if (r <= c || c >= ee) return "panel task"; break;
             case L_INPANEL: if (kl != c - 1 || kf > kl) return "in-panel task"; break;
             case L_TRAIL: if (c <= kl || kl >= ee) return "trailing task"; break;
-            case L_NEGATE: if (c < J.items[it].e1) return "negate task"; break;
             default: return "task kind";
           }
         }
@@ -1969,6 +1969,12 @@ mlbddc_status Handle::numeric() {
 }
 
 // --------------------------------------------------------------------- apply
+// The elimination of the constrained problems leaves -G_i and -Psi_i in the
+// M job (its second phase reads the first phase's trailing block with the
+// opposite sign instead of negating it): every product with those blocks
+// takes alpha = MSIGN.
+constexpr double MSIGN = -1.0;
+
 mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, const DotFinish* ds, bool r_copied) {
   LevelDev& D = lev[li];
   LevelPlan& P = *D.P;
@@ -1992,15 +1998,15 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
     HIPCHK(hipStreamWaitEvent(gstream, ev_gfork, 0));
     const int gcls = li == 0 ? MLBDDC_PROF_PRECOND_MV : -1;
     if (D.mfp32)
-      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial_g, gstream, gcls, alg_bytes_G);
+      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, MSIGN, false, D.partial_g, gstream, gcls, alg_bytes_G);
     else
-      run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial_g, gstream, gcls,
+      run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, MSIGN, false, D.partial_g, gstream, gcls,
                                      alg_bytes_G);
     HIPCHK(hipEventRecord(ev_gjoin, gstream));
   }
   // r_C = sum R_Ci^T Psi_i^T r_i
-  if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, 1.0, false, D.partial);
-  else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, 1.0, false, D.partial);
+  if (D.mfp32) run_mv<float, float, double>(D.mvPsiN, D.M, (const float*)D.rl, D.rcl, MSIGN, false, D.partial);
+  else run_mv<double, double, double>(D.mvPsiN, D.M, (const double*)D.rl, D.rcl, MSIGN, false, D.partial);
   launch_seg_reduce<double>(stream, P.n_coarse, D.d_cptr, D.d_clist, nullptr, D.rcl, D.rC, 0.0);
   // coarse correction: the next level
   if ((st = apply_full(li + 1, D.rC, D.zC))) return st;
@@ -2009,20 +2015,20 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
     launch_gather<double, float>(stream, D.nC_flat, D.d_cidx, nullptr, D.zC, (float*)D.zcl);
     if (D.g_psi_sum) {
       launch_tile_mv_sum<float, float, float>(stream, MV_SYM, D.mvG.d, MV_T, D.mvPsiT.d, (int32_t)D.mvG.h.size(), D.mvG.max_out,
-                                              (const float*)D.M.buf, (const float*)D.rl, (const float*)D.zcl, (float*)D.yl, 1.0,
+                                              (const float*)D.M.buf, (const float*)D.rl, (const float*)D.zcl, (float*)D.yl, MSIGN,
                                               false);
     } else if (D.yl2) {
       // Psi_i z_Ci into a buffer of its own (while the G product may still
       // run beside); the averaging below sums both
-      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl2, 1.0, false, D.partial);
+      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl2, MSIGN, false, D.partial);
       if (g_side) HIPCHK(hipStreamWaitEvent(stream, ev_gjoin, 0));
       else
-        run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial, nullptr,
+        run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, MSIGN, false, D.partial, nullptr,
                                     li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
     } else {
-      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, 1.0, false, D.partial, nullptr,
+      run_mv<float, float, float>(D.mvG, D.M, (const float*)D.rl, (float*)D.yl, MSIGN, false, D.partial, nullptr,
                                   li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
-      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, 1.0, true, D.partial);
+      run_mv<float, float, float>(D.mvPsiT, D.M, (const float*)D.zcl, (float*)D.yl, MSIGN, true, D.partial);
     }
     const float* y2 = D.yl2 ? (const float*)D.yl2 : nullptr;
     if (ds)  // with rhat.zhat and its scalar step
@@ -2036,13 +2042,13 @@ mlbddc_status Handle::apply_interface(int li, const double* rhat, double* zhat, 
     if (D.g_psi_sum) {
       launch_tile_mv_sum<double, double, double>(stream, MV_SYM, D.mvG.d, MV_T, D.mvPsiT.d, (int32_t)D.mvG.h.size(),
                                                  D.mvG.max_out, (const double*)D.M.buf, (const double*)D.rl,
-                                                 (const double*)D.zcl, (double*)D.yl, 1.0, false);
+                                                 (const double*)D.zcl, (double*)D.yl, MSIGN, false);
     } else {
       if (g_side) HIPCHK(hipStreamWaitEvent(stream, ev_gjoin, 0));
       else
-        run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, 1.0, false, D.partial, nullptr,
+        run_mv<double, double, double>(D.mvG, D.M, (const double*)D.rl, (double*)D.yl, MSIGN, false, D.partial, nullptr,
                                        li == 0 ? MLBDDC_PROF_PRECOND_MV : -1, alg_bytes_G);
-      run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, 1.0, true, D.partial);
+      run_mv<double, double, double>(D.mvPsiT, D.M, (const double*)D.zcl, (double*)D.yl, MSIGN, true, D.partial);
     }
     if (ds)
       launch_seg_reduce_dot<double>(stream, (int64_t)P.iface_dofs.size(), D.d_gptr, D.d_glist, D.d_w, (const double*)D.yl,
