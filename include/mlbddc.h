@@ -67,8 +67,9 @@ typedef struct {
   int32_t device;      /* HIP device ordinal */
   int32_t panel_tiles_precond; /* same for the constrained local problems (0 = tune table / 4) */
   const char* tune_table;      /* path of a tune table written by the autotuner, or NULL;
-                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]"
-                                  and "MV <f64|f32> 0 <tiles per workgroup>" */
+                                  lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]",
+                                  "MV <f64|f32> 0 <tiles per workgroup>" and "PANEL <f64|f32> 0 <stage>"
+                                  (staged columns of the panel products; else the job's) */
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */

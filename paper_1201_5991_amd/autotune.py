@@ -10,6 +10,7 @@ tune table that the library reads at set-up:
 
     <K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> <stage>
     MV <f64|f32> 0 <tiles per workgroup of the tile matrix-vector products>
+    PANEL <f64|f32> 0 <staged columns of the panel products>
 
 The staged columns do not change the results (the products accumulate in the
 same order); the panel width changes only the order of independent updates.
@@ -103,11 +104,46 @@ def tune(configs, reps: int = 2, log=print):
                 log(f"config {k} {prec} tiles per workgroup {tpw}: S^ product {t_s*1e3:.3f} ms, "
                     f"G product {t_g*1e3:.3f} ms")
     agg.update(mv)
+    # staged columns of the panel products per precision, with the panel
+    # widths and staged columns chosen above: K and M job times (profiled,
+    # device) of FP64 panels (both modes' K jobs, the FP64 mode's M jobs) and
+    # FP32 panels (the mixed mode's M jobs), summed over the workloads
+    import tempfile
+    best = {key: min(cand, key=lambda q: cand[q]) for key, cand in agg.items() if key[0] != "MV"}
+    pan = {("PANEL", "f64", 0): {}, ("PANEL", "f32", 0): {}}
+    for ps in STAGES:
+        with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as fh:
+            for (job, prec, b), v in sorted(best.items()):
+                fh.write(f"{job} {prec} {b} {v[0]} {v[1]}\n")
+            fh.write(f"PANEL f64 0 {ps}\nPANEL f32 0 {ps}\n")
+            path = fh.name
+        for k in configs:
+            prob = Problem(config(k))
+            for prec in ("fp64", "mixed"):
+                s = Solver(precision=prec, tune_table=path)
+                s.setup(prob)
+                t = {"K": 0.0, "M": 0.0}
+                for _ in range(reps):
+                    s.set_profiling(True)
+                    s.setup(prob)
+                    torch.cuda.synchronize()
+                    j = s.profile()["jobs"]
+                    s.set_profiling(False)
+                    t["K"] += j["K_time_s"] / reps
+                    t["M"] += j["M_time_s"] / reps
+                s.destroy()
+                f64 = t["K"] + (t["M"] if prec == "fp64" else 0.0)
+                pan[("PANEL", "f64", 0)][ps] = pan[("PANEL", "f64", 0)].get(ps, 0.0) + f64
+                if prec == "mixed":
+                    pan[("PANEL", "f32", 0)][ps] = pan[("PANEL", "f32", 0)].get(ps, 0.0) + t["M"]
+                log(f"config {k} {prec} panel products {ps} staged columns: K {t['K']*1e3:.2f} ms, M {t['M']*1e3:.2f} ms")
+        os.unlink(path)
+    agg.update(pan)
     table = {}
     for key, cand in agg.items():
         table[key] = min(cand, key=lambda q: cand[q])
-        if key[0] == "MV":
-            log(f"{' '.join(map(str, key))}: {table[key]} tiles per workgroup "
+        if key[0] in ("MV", "PANEL"):
+            log(f"{' '.join(map(str, key))}: {table[key]} "
                 f"({', '.join(f'{q}: {v*1e3:.3f} ms' for q, v in sorted(cand.items()))} summed)")
         else:
             log(f"{' '.join(map(str, key))}: panel {table[key][0]} stage {table[key][1]} "
@@ -120,7 +156,7 @@ def write_table(table, path):
         fh.write("# panel widths and staged columns chosen by paper_1201_5991_amd/autotune.py on gfx950\n")
         fh.write("# job precision ceil(log2(max tiles per side)) panel stage\n")
         for (job, prec, b), v in sorted(table.items()):
-            fh.write(f"{job} {prec} {b} {v}\n" if job == "MV" else f"{job} {prec} {b} {v[0]} {v[1]}\n")
+            fh.write(f"{job} {prec} {b} {v}\n" if job in ("MV", "PANEL") else f"{job} {prec} {b} {v[0]} {v[1]}\n")
 
 
 if __name__ == "__main__":

@@ -634,8 +634,9 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
   auto mm = [&](bool panel) {
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off); };
     if (panel) {
-      if (a.stage == 16) go(k_tile_mm<T, true, 16>);
-      else if (a.stage == 64) go(k_tile_mm<T, true, 64>);
+      const int ps = a.pstage > 0 ? a.pstage : a.stage;
+      if (ps == 16) go(k_tile_mm<T, true, 16>);
+      else if (ps == 64) go(k_tile_mm<T, true, 64>);
       else go(k_tile_mm<T, true, 32>);
     } else {
       if (a.stage == 16) go(k_tile_mm<T, false, 16>);

@@ -44,6 +44,7 @@ struct FactorArgs {
   const int32_t* tmap;     // tile maps (tile_slot), or null: every matrix dense packed-lower
   const int64_t* tmap_off;
   int stage = 32;          // columns staged per step of the tile products: 16, 32 or 64
+  int pstage = 0;          // the same for the panel products (one tile times W); 0: stage
 };
 template <typename T>
 void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv);

@@ -108,6 +108,7 @@ struct Job {
   int32_t* d_err = nullptr;
   int panel = 4;
   int stage = 32;  // staged columns of the tile products
+  int pstage = 0;  // staged columns of the panel products (0: stage)
   // Tile maps (tile_slot): a matrix with a tile structure stores only the
   // tiles some kernel reads; tmap_off[i] = -1 for a dense packed-lower one.
   // A mapped matrix keeps its eliminated columns at off[i] (nlead[i] tiles)
@@ -482,6 +483,7 @@ struct Handle {
   bool lookahead = false;
   std::vector<std::array<int, 5>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel, staged columns or 0)
   int mv_tpw[2] = {1, 1};                 // tiles per workgroup of the large tile products: [0] FP64, [1] FP32
+  int panel_stage[2] = {0, 0};            // staged columns of the panel products per precision (0: the job's)
   int pick_panel(int job, bool fp32, int ntmax) const;
   int pick_stage(int job, bool fp32, int ntmax) const;
   mlbddc_status reserve_job(Job& J, bool fp32);
@@ -929,6 +931,7 @@ mlbddc_status Handle::prepare_job(Job& J, bool fp32, int job) {
   for (int32_t x : J.nt) ntmax = std::max(ntmax, x);
   J.panel = pick_panel(job, fp32, ntmax);
   J.stage = pick_stage(job, fp32, ntmax);
+  J.pstage = opt.stage_cols > 0 ? opt.stage_cols : panel_stage[fp32 ? 1 : 0];
   if (!J.tmap.empty()) J.panel = std::min(J.panel, 64);  // k_tile_mm holds a task's tile slots in one wavefront
   if (ntmax >= panel_nt[job]) {  // report the panel width of the largest job of the set-up
     panel_nt[job] = ntmax;
@@ -952,7 +955,7 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
   if (prof) HIPCHK(hipStreamSynchronize(stream));  // job time excludes earlier queued work
   const double tj0 = prof ? now() : 0.0;
-  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off, J.stage};
+  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off, J.stage, J.pstage};
   const size_t nl = J.sched.launches.size();
   if (prof)
     while (events.size() < 2 * nl) {
@@ -2498,6 +2501,10 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
       if (!(ls >> job >> prec >> bucket >> panel)) continue;
       if (job == "MV") {  // tiles per workgroup of the tile products
         if (panel == 1 || panel == 2) h->h.mv_tpw[prec == "f32" ? 1 : 0] = panel;
+        continue;
+      }
+      if (job == "PANEL") {  // staged columns of the panel products
+        if (panel == 16 || panel == 32 || panel == 64) h->h.panel_stage[prec == "f32" ? 1 : 0] = panel;
         continue;
       }
       if (panel < 1 || panel > 16) continue;
