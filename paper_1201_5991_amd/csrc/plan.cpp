@@ -8,7 +8,6 @@
 #include <map>
 #include <memory>
 #include <unordered_map>
-#include <unordered_set>
 #include <numeric>
 #include <thread>
 #include <mutex>
@@ -583,67 +582,24 @@ void build_globs(LevelPlan& L, const std::vector<int64_t>& node_iface, const std
 // (interior nodes in node order, then interface nodes) and, per interface
 // node, the ranks of its other subdomains among the subdomain's neighbours,
 // which is everything the nested dissection and the tile structure read.
-// Entries are compared in full; a box division repeats few structures.
-struct LayoutCache {
-  struct Entry {
-    std::vector<int32_t> key;
-    std::vector<int32_t> order, gsize, gheight, sptr, srow;  // dissection and tile structure
-    std::vector<int32_t> gperm;                              // interface order (positions in node order)
-    std::vector<int32_t> elocal, envK, ecolor;               // element maps, envelope, element colours
-    int32_t ncolor = 0;
-    std::atomic<bool> ready{false};  // set under the cache's mutex
-  };
-  std::mutex mx;
-  std::condition_variable cv;
-  std::unordered_map<uint64_t, std::vector<std::shared_ptr<Entry>>> map;
-  static uint64_t hash(const std::vector<int32_t>& k) {
-    uint64_t h = 1469598103934665603ull;
-    for (int32_t v : k) h = (h ^ (uint64_t)(uint32_t)v) * 1099511628211ull;
-    return h;
-  }
-  // The entry of key k, waiting while another thread computes it; or a new
-  // entry that the caller computes and then publishes (claimed = true).
-  // Keys are compared outside the lock (an entry's key never changes; a
-  // hash's entry list only grows), so threads do not queue behind compares.
-  std::shared_ptr<Entry> get(std::vector<int32_t>& k, uint64_t h, bool& claimed) {
-    std::vector<std::shared_ptr<Entry>> seen;
-    {
-      std::lock_guard<std::mutex> g(mx);
-      auto it = map.find(h);
-      if (it != map.end()) seen = it->second;
-    }
-    auto take = [&](const std::shared_ptr<Entry>& e) {
-      if (!e->ready) {
-        std::unique_lock<std::mutex> g(mx);
-        cv.wait(g, [&] { return e->ready.load(); });
-      }
-      claimed = false;
-      return e;
-    };
-    for (const auto& e : seen)
-      if (e->key == k) return take(e);
-    std::unique_lock<std::mutex> g(mx);
-    auto& list = map[h];
-    for (size_t q = seen.size(); q < list.size(); ++q)  // entries added meanwhile
-      if (list[q]->key == k) {
-        std::shared_ptr<Entry> e = list[q];
-        g.unlock();
-        return take(e);
-      }
-    auto e = std::make_shared<Entry>();
-    e->key = std::move(k);
-    list.push_back(e);
-    claimed = true;
-    return e;
-  }
-  void publish(const std::shared_ptr<Entry>& e) {
-    {
-      std::lock_guard<std::mutex> g(mx);
-      e->ready = true;
-    }
-    cv.notify_all();
-  }
+// The keys of all subdomains are built first (on threads); the first
+// subdomain of every key hash computes its layout (the leaders, on threads),
+// then every other subdomain takes its leader's layout after comparing the
+// keys in full (a hash collision falls back to its own dissection), so no
+// thread waits for another.  A box division repeats few structures.
+struct LayoutEntry {
+  std::vector<int32_t> key;
+  std::vector<int32_t> order, gsize, gheight, sptr, srow;  // dissection and tile structure
+  std::vector<int32_t> gperm;                              // interface order (positions in node order)
+  std::vector<int32_t> elocal, envK, ecolor;               // element maps, envelope, element colours
+  int32_t ncolor = 0;
 };
+
+uint64_t key_hash(const std::vector<int32_t>& k) {
+  uint64_t h = 1469598103934665603ull;
+  for (int32_t v : k) h = (h ^ (uint64_t)(uint32_t)v) * 1099511628211ull;
+  return h;
+}
 
 // Build one level from its elements (node lists, -1 = eliminated node) and
 // the subdomain of every element.
@@ -792,8 +748,80 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
   // Per-subdomain work is independent: split the subdomains over threads, each
   // with its own node-indexed scratch (reset only where it was touched).
   if ((int)plan.scratch.size() < plan_threads(ns)) plan.scratch.resize(plan_threads(ns));
-  LayoutCache cache;
   std::atomic<int32_t> reused{0};
+  // structure keys (level 1 with nested dissection), the leader of every key
+  // hash, and the entries the leaders fill
+  const bool keyed_level = L.level == 1 && !L.top && reuse_layouts;
+  std::vector<std::vector<int32_t>>& keys = plan.w_keys;
+  std::vector<std::shared_ptr<LayoutEntry>> entry_of(ns);
+  std::vector<char> is_leader(ns, 0);
+  if (keyed_level) {
+    if ((int32_t)keys.size() < ns) keys.resize(ns);
+    parallel_ranges(ns, [&](int t, int64_t b0, int64_t b1) {
+      PlanScratch& W = plan.scratch[t];
+      W.ensure(L.n_nodes);
+      std::vector<int32_t>& node_local = W.node_local;
+      std::vector<int64_t> gnodes;
+      std::vector<int32_t> nb;
+      for (int32_t b = (int32_t)b0; b < (int32_t)b1; ++b) {
+        std::vector<int32_t>& skey = keys[b];
+        skey.clear();
+        const SubPlan& S = L.subs[b];
+        int32_t ni = 0;
+        gnodes.clear();
+        for (int64_t n : sub_nodes[b]) {
+          if (mult(n) >= 2) { node_local[n] = (int32_t)gnodes.size(); gnodes.push_back(n); }
+          else node_local[n] = ni++;
+        }
+        if ((int64_t)ni * nd >= ND_MIN_DOFS) {
+          size_t nel = 0, nnb = 0;  // element node entries; other subdomains of the interface nodes and separators
+          for (int64_t e : S.elems) nel += (size_t)(L.el_ptr[e + 1] - L.el_ptr[e]);
+          for (int64_t v : gnodes) nnb += (size_t)(nptr[v + 1] - nptr[v]);
+          skey.reserve(4 + nel + nnb);
+          skey.resize(4 + nel);
+          skey[0] = ni;
+          skey[1] = (int32_t)gnodes.size();
+          skey[2] = nd;
+          skey[3] = (int32_t)S.elems.size();
+          int32_t* kp = skey.data() + 4;
+          for (int64_t e : S.elems)
+            for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
+              const int64_t v = L.el_nodes[j];
+              *kp++ = v < 0 ? -1 : node_local[v] + (node_is_g[v] ? ni : 0);
+            }
+          nb.clear();
+          for (int64_t v : gnodes)
+            for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
+              if (nsub[q] != b) nb.push_back(nsub[q]);
+          std::sort(nb.begin(), nb.end());
+          nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+          for (int64_t v : gnodes) {
+            for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
+              if (nsub[q] != b) skey.push_back((int32_t)(std::lower_bound(nb.begin(), nb.end(), nsub[q]) - nb.begin()));
+            skey.push_back(-2);
+          }
+        }
+        for (int64_t n : sub_nodes[b]) node_local[n] = -1;
+      }
+    });
+    std::unordered_map<uint64_t, int32_t> first;
+    std::vector<uint64_t> hsh(ns, 0);
+    parallel_ranges(ns, [&](int, int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b)
+        if (!keys[b].empty()) hsh[b] = key_hash(keys[b]);
+    });
+    for (int32_t b = 0; b < ns; ++b) {
+      if (keys[b].empty()) continue;
+      auto it = first.find(hsh[b]);
+      if (it == first.end()) {
+        first.emplace(hsh[b], b);
+        is_leader[b] = 1;
+        entry_of[b] = std::make_shared<LayoutEntry>();
+      } else {
+        entry_of[b] = entry_of[it->second];
+      }
+    }
+  }
   auto work = [&](int t, int64_t b_begin, int64_t b_end) {
   PlanScratch& W = plan.scratch[t];
   W.ensure(L.n_nodes);
@@ -814,42 +842,14 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     // local position of its first DOF
     std::vector<int32_t> iorder, gsize;
     const bool use_nd = L.level == 1 && !L.top && S.nI >= ND_MIN_DOFS;
-    const bool keyed = use_nd && reuse_layouts;
-    std::vector<int32_t> skey;
-    std::shared_ptr<LayoutCache::Entry> mine, hit;  // the entry this subdomain computes, or reuses
-    if (keyed) {
-      const int32_t ni = (int32_t)inodes.size();
-      size_t nel = 0, nnb = 0;  // element node entries; other subdomains of the interface nodes and separators
-      for (int64_t e : S.elems) nel += (size_t)(L.el_ptr[e + 1] - L.el_ptr[e]);
-      for (int64_t v : gnodes) nnb += (size_t)(nptr[v + 1] - nptr[v]);
-      skey.reserve(4 + nel + nnb);
-      skey.resize(4 + nel);
-      skey[0] = ni;
-      skey[1] = (int32_t)gnodes.size();
-      skey[2] = nd;
-      skey[3] = (int32_t)S.elems.size();
-      int32_t* kp = skey.data() + 4;
-      for (int64_t e : S.elems)
-        for (int64_t j = L.el_ptr[e]; j < L.el_ptr[e + 1]; ++j) {
-          const int64_t v = L.el_nodes[j];
-          *kp++ = v < 0 ? -1 : node_local[v] + (node_is_g[v] ? ni : 0);
-        }
-      std::vector<int32_t> nb;
-      nb.reserve(nnb);
-      for (int64_t v : gnodes)
-        for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
-          if (nsub[q] != b) nb.push_back(nsub[q]);
-      std::sort(nb.begin(), nb.end());
-      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-      for (int64_t v : gnodes) {
-        for (int64_t q = nptr[v]; q < nptr[v + 1]; ++q)
-          if (nsub[q] != b) skey.push_back((int32_t)(std::lower_bound(nb.begin(), nb.end(), nsub[q]) - nb.begin()));
-        skey.push_back(-2);
+    std::shared_ptr<LayoutEntry> mine, hit;  // the entry this subdomain computes, or reuses
+    if (use_nd && entry_of[b]) {
+      if (is_leader[b]) {
+        mine = entry_of[b];
+        mine->key.swap(keys[b]);
+      } else if (entry_of[b]->key == keys[b]) {
+        hit = entry_of[b];
       }
-      const uint64_t h = LayoutCache::hash(skey);
-      bool claimed = false;
-      auto e = cache.get(skey, h, claimed);
-      (claimed ? mine : hit) = std::move(e);
     }
     if (hit) {
       iorder = hit->order;
@@ -1025,7 +1025,6 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     if (mine) {
       for (int64_t e : S.elems) mine->ecolor.push_back(L.el_color[e]);
       mine->ncolor = ncol;
-      cache.publish(mine);
     }
 
     for (int64_t n : sub_nodes[b]) { node_local[n] = -1; node_mask[n] = 0; }
@@ -1038,20 +1037,17 @@ mlbddc_status build_level(LevelPlan& L, int constraints, Error& err, Plan& plan,
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t c) { return sub_nodes[a].size() > sub_nodes[c].size(); });
-    if (reuse_layouts) {  // one subdomain of every (node count, element count) first, so that few wait
-      std::unordered_set<uint64_t> seen;
-      std::vector<int32_t> lead, rest;
-      for (int32_t b : order) {
-        const uint64_t sig = ((uint64_t)sub_nodes[b].size() << 32) ^ (uint64_t)L.subs[b].elems.size();
-        (seen.insert(sig).second ? lead : rest).push_back(b);
-      }
-      order = lead;
-      order.insert(order.end(), rest.begin(), rest.end());
+    // the leaders first, in a pass of their own: the others then find their
+    // entries complete
+    std::vector<int32_t> lead, rest;
+    for (int32_t b : order) (is_leader[b] ? lead : rest).push_back(b);
+    for (const std::vector<int32_t>* part : {&lead, &rest}) {
+      const int32_t np = (int32_t)part->size();
+      std::atomic<int32_t> next{0};
+      parallel_run(plan_threads(np), [&](int t) {
+        for (int32_t i = next++; i < np; i = next++) work(t, (*part)[i], (*part)[i] + 1);
+      });
     }
-    std::atomic<int32_t> next{0};
-    parallel_run(plan_threads(ns), [&](int t) {
-      for (int32_t i = next++; i < ns; i = next++) work(t, order[i], order[i] + 1);
-    });
   }
   if (verbose && reused > 0)
     std::fprintf(stderr, "[mlbddc plan L%d] %d of %d subdomain layouts reuse the dissection of an equal structure\n", L.level,

@@ -134,6 +134,7 @@ struct Plan {
   std::vector<int64_t> w_nptr, w_pos, w_node_iface;
   std::vector<int32_t> w_nsub;
   std::vector<char> w_is_g;
+  std::vector<std::vector<int32_t>> w_keys;  // structure keys of the subdomains (layout reuse)
 };
 
 // Build the whole plan.  Returns MLBDDC_OK or an error with a message.
