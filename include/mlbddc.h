@@ -68,8 +68,9 @@ typedef struct {
   int32_t panel_tiles_precond; /* same for the constrained local problems (0 = tune table / 4) */
   const char* tune_table;      /* path of a tune table written by the autotuner, or NULL;
                                   lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]",
-                                  "MV <f64|f32> 0 <tiles per workgroup>" and "PANEL <f64|f32> 0 <stage>"
-                                  (staged columns of the panel products; else the job's) */
+                                  "MV <f64|f32> 0 <tiles per workgroup>", "PANEL <f64|f32> 0 <stage>"
+                                  (staged columns of the panel products; else the job's) and
+                                  "SHAPE f32 0 <16|32>" (FP32 MFMA shape) */
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */
@@ -82,6 +83,9 @@ typedef struct {
   int32_t mv_group_tiles; /* stored tiles per workgroup of the large tile matrix-vector products (S^,
                           the level-1 local operators): 1 or 2 (0 = from the tune table per precision,
                           else 1).  Both give bitwise the same results */
+  int32_t mfma_f32;    /* MFMA shape of the FP32 tile products of the factorizations: 16 (16x16x4) or 32
+                          (32x32x2) (0 = from the tune table, else 16).  The shapes sum the products
+                          in different orders: results agree to FP32 rounding */
 } mlbddc_options;
 
 typedef struct {

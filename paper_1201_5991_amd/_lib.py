@@ -40,7 +40,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_iter", C.c_int32), ("weights", C.c_int32),
                 ("use_graph", C.c_int32), ("panel_tiles", C.c_int32), ("device", C.c_int32),
                 ("panel_tiles_precond", C.c_int32), ("tune_table", C.c_char_p), ("lookahead", C.c_int32),
-                ("side_stream", C.c_int32), ("stage_cols", C.c_int32), ("mv_group_tiles", C.c_int32)]
+                ("side_stream", C.c_int32), ("stage_cols", C.c_int32), ("mv_group_tiles", C.c_int32),
+                ("mfma_f32", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -11,6 +11,7 @@ tune table that the library reads at set-up:
     <K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> <stage>
     MV <f64|f32> 0 <tiles per workgroup of the tile matrix-vector products>
     PANEL <f64|f32> 0 <staged columns of the panel products>
+    SHAPE f32 0 <MFMA shape of the FP32 tile products: 16 (16x16x4) or 32 (32x32x2)>
 
 The staged columns do not change the results (the products accumulate in the
 same order); the panel width changes only the order of independent updates.
@@ -139,10 +140,39 @@ def tune(configs, reps: int = 2, log=print):
                 log(f"config {k} {prec} panel products {ps} staged columns: K {t['K']*1e3:.2f} ms, M {t['M']*1e3:.2f} ms")
         os.unlink(path)
     agg.update(pan)
+    # MFMA shape of the FP32 tile products: the mixed mode's K and M job times
+    # (its FP32 jobs: the constrained problems and the K jobs above level 1)
+    best_pan = {key: min(cand, key=lambda q: cand[q]) for key, cand in pan.items()}
+    shp = {("SHAPE", "f32", 0): {}}
+    for sh in (16, 32):
+        with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as fh:
+            for (job, prec, b), v in sorted(best.items()):
+                fh.write(f"{job} {prec} {b} {v[0]} {v[1]}\n")
+            for (job, prec, b), v in sorted(best_pan.items()):
+                fh.write(f"{job} {prec} {b} {v}\n")
+            fh.write(f"SHAPE f32 0 {sh}\n")
+            path = fh.name
+        for k in configs:
+            prob = Problem(config(k))
+            s = Solver(precision="mixed", tune_table=path)
+            s.setup(prob)
+            t = 0.0
+            for _ in range(reps):
+                s.set_profiling(True)
+                s.setup(prob)
+                torch.cuda.synchronize()
+                j = s.profile()["jobs"]
+                s.set_profiling(False)
+                t += (j["K_time_s"] + j["M_time_s"]) / reps
+            s.destroy()
+            shp[("SHAPE", "f32", 0)][sh] = shp[("SHAPE", "f32", 0)].get(sh, 0.0) + t
+            log(f"config {k} mixed FP32 MFMA shape {sh}: K + M {t*1e3:.2f} ms")
+        os.unlink(path)
+    agg.update(shp)
     table = {}
     for key, cand in agg.items():
         table[key] = min(cand, key=lambda q: cand[q])
-        if key[0] in ("MV", "PANEL"):
+        if key[0] in ("MV", "PANEL", "SHAPE"):
             log(f"{' '.join(map(str, key))}: {table[key]} "
                 f"({', '.join(f'{q}: {v*1e3:.3f} ms' for q, v in sorted(cand.items()))} summed)")
         else:
@@ -156,7 +186,7 @@ def write_table(table, path):
         fh.write("# panel widths and staged columns chosen by paper_1201_5991_amd/autotune.py on gfx950\n")
         fh.write("# job precision ceil(log2(max tiles per side)) panel stage\n")
         for (job, prec, b), v in sorted(table.items()):
-            fh.write(f"{job} {prec} {b} {v}\n" if job in ("MV", "PANEL") else f"{job} {prec} {b} {v[0]} {v[1]}\n")
+            fh.write(f"{job} {prec} {b} {v}\n" if job in ("MV", "PANEL", "SHAPE") else f"{job} {prec} {b} {v[0]} {v[1]}\n")
 
 
 if __name__ == "__main__":

@@ -435,6 +435,52 @@ __device__ inline void tile_nt_ld(typename Mfma<T>::acc_t (&acc)[2][2], const T*
 
 constexpr int LDU = TS + 16;  // keeps the four k-groups of a fragment read on distinct LDS banks
 
+// Output accumulators of a workgroup's 64x64 tile product, per MFMA shape:
+// SH = 16 takes 2x2 blocks of 16x16x4 per wavefront (FP64 and FP32), SH = 32
+// one 32x32x2 block (FP32; lane l holds rows i0 + l % 32 of the columns
+// j0 + (v % 4) + 8 (v / 4) + 4 (l / 32), v = 0..15).  Wave w owns rows
+// (w & 1) * 32.. and columns (w >> 1) * 32.. of the output either way; each()
+// visits a lane's outputs in a fixed order.
+typedef float f16v __attribute__((ext_vector_type(16)));
+template <typename T, int SH> struct TileAcc;
+template <typename T> struct TileAcc<T, 16> {
+  typename Mfma<T>::acc_t a[2][2];
+  __device__ void zero() {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) a[i][j] = Mfma<T>::zero();
+  }
+  template <int LD, int KN>
+  __device__ void mul(const T* __restrict__ sR, const T* __restrict__ sS) { tile_nt_ld<T, LD, KN>(a, sR, sS); }
+  template <typename F>
+  __device__ void each(F f) { for_acc<T>(a, f); }
+};
+template <> struct TileAcc<float, 32> {
+  f16v a;
+  __device__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) a[v] = 0.f;
+  }
+  // acc(i, j) += sum_k R(i, k) S(j, k) over KN staged columns k, two per instruction
+  template <int LD, int KN>
+  __device__ void mul(const float* __restrict__ sR, const float* __restrict__ sS) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
+    const int l32 = lane & 31, kq = lane >> 5;
+#pragma unroll
+    for (int k0 = 0; k0 < KN; k0 += 2) {
+      const int kk = k0 + kq;
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(sS[kk * LD + jw + l32], sR[kk * LD + iw + l32], a, 0, 0, 0);
+    }
+  }
+  template <typename F>
+  __device__ void each(F f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) f(iw + (lane & 31), jw + (v & 3) + 8 * (v >> 2) + 4 * (lane >> 5), a[v]);
+  }
+};
+
 // Workgroups are dealt to the 8 XCDs of the chip round-robin by launch
 // index; this maps launch index b to a task index so that each XCD receives
 // one contiguous slice of the task list (tasks of the same matrix, which
@@ -457,7 +503,7 @@ __device__ inline int64_t xcd_slice(int64_t b, int64_t n) {
 template <int KS> struct StageOcc { static constexpr int blocks = 4; };
 template <> struct StageOcc<64> { static constexpr int blocks = 2; };  // twice the LDS and staging registers
 
-template <typename T, bool PANEL, int KS>
+template <typename T, bool PANEL, int KS, int SH = 16>
 __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
     const uint64_t* __restrict__ tasks, const int64_t* __restrict__ off, const int32_t* __restrict__ ntv,
     const int64_t* __restrict__ inv_off, T* A, const T* __restrict__ Inv, const int32_t* __restrict__ tmap,
@@ -493,9 +539,8 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
     return PANEL ? Inv + inv_off[item] + (int64_t)s * TE + (q % SPT) * (TE / SPT)
                  : base + stile(q / SPT) * TE + (q % SPT) * (TE / SPT);
   };
-  typename Mfma<T>::acc_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::zero();
+  TileAcc<T, SH> acc;
+  acc.zero();
   ChunkRegs<T, KS * TS> pr, ps;
   pr.load(rsrc(0));
   if (!same) ps.load(ssrc(0));
@@ -505,7 +550,7 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
     __syncthreads();
     pr.load(rsrc(q + 1));
     if (!same) ps.load(ssrc(q + 1));
-    tile_nt_ld<T, LDU, KS>(acc, sR, same ? sR : sS);
+    acc.template mul<LDU, KS>(sR, same ? sR : sS);
     __syncthreads();
   }
   pr.template store<LDU>(sR);
@@ -514,23 +559,13 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
   T creg[16];
   if (!PANEL) {
     int n = 0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = iw + bi * 16 + (lane & 15), j = jw + bj * 16 + Mfma<T>::row(lane >> 4, v);
-          creg[n++] = g[j * TS + i];
-        }
+    acc.each([&](int i, int j, T) { creg[n++] = g[j * TS + i]; });
   }
-  tile_nt_ld<T, LDU, KS>(acc, sR, same ? sR : sS);
+  acc.template mul<LDU, KS>(sR, same ? sR : sS);
   int n = 0;
   const T sg = task_neg(t) ? (T)-1 : (T)1;  // second-phase task: the block is stored negated
-  if (PANEL) for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = sg * v; });
-  else for_acc<T>(acc, [&](int i, int j, T v) { g[j * TS + i] = creg[n++] - sg * v; });
+  if (PANEL) acc.each([&](int i, int j, T v) { g[j * TS + i] = sg * v; });
+  else acc.each([&](int i, int j, T v) { g[j * TS + i] = creg[n++] - sg * v; });
 }
 
 // ----------------------------------------------------- preconditioner set-up
@@ -633,15 +668,25 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
   dim3 grid((unsigned)count), blk(256);
   auto mm = [&](bool panel) {
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, blk, 0, st, tk, a.off, a.nt, a.inv_off, A, Inv, a.tmap, a.tmap_off); };
+    auto shape = [&](auto pnl, auto ks) {
+      constexpr bool P = decltype(pnl)::value;
+      constexpr int K = decltype(ks)::value;
+      if constexpr (std::is_same<T, float>::value) {
+        if (a.shape == 32) { go(k_tile_mm<T, P, K, 32>); return; }
+      }
+      go(k_tile_mm<T, P, K, 16>);
+    };
+    using PT = std::true_type;
+    using PF = std::false_type;
     if (panel) {
       const int ps = a.pstage > 0 ? a.pstage : a.stage;
-      if (ps == 16) go(k_tile_mm<T, true, 16>);
-      else if (ps == 64) go(k_tile_mm<T, true, 64>);
-      else go(k_tile_mm<T, true, 32>);
+      if (ps == 16) shape(PT{}, std::integral_constant<int, 16>{});
+      else if (ps == 64) shape(PT{}, std::integral_constant<int, 64>{});
+      else shape(PT{}, std::integral_constant<int, 32>{});
     } else {
-      if (a.stage == 16) go(k_tile_mm<T, false, 16>);
-      else if (a.stage == 64) go(k_tile_mm<T, false, 64>);
-      else go(k_tile_mm<T, false, 32>);
+      if (a.stage == 16) shape(PF{}, std::integral_constant<int, 16>{});
+      else if (a.stage == 64) shape(PF{}, std::integral_constant<int, 64>{});
+      else shape(PF{}, std::integral_constant<int, 32>{});
     }
   };
   switch (kind) {

@@ -45,6 +45,7 @@ struct FactorArgs {
   const int64_t* tmap_off;
   int stage = 32;          // columns staged per step of the tile products: 16, 32 or 64
   int pstage = 0;          // the same for the panel products (one tile times W); 0: stage
+  int shape = 16;          // FP32 MFMA shape of the tile products: 16 (16x16x4) or 32 (32x32x2)
 };
 template <typename T>
 void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, int64_t first, int64_t count, T* A, T* Inv);

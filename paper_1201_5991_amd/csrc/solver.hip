@@ -484,6 +484,7 @@ struct Handle {
   std::vector<std::array<int, 5>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel, staged columns or 0)
   int mv_tpw[2] = {1, 1};                 // tiles per workgroup of the large tile products: [0] FP64, [1] FP32
   int panel_stage[2] = {0, 0};            // staged columns of the panel products per precision (0: the job's)
+  int mfma_f32 = 16;                      // FP32 MFMA shape of the tile products: 16 (16x16x4) or 32 (32x32x2)
   int pick_panel(int job, bool fp32, int ntmax) const;
   int pick_stage(int job, bool fp32, int ntmax) const;
   mlbddc_status reserve_job(Job& J, bool fp32);
@@ -955,7 +956,8 @@ mlbddc_status Handle::factor(Job& J, int level, bool precond) {
   HIPCHK(hipMemsetAsync(J.d_err, 0, 2 * sizeof(int32_t), stream));
   if (prof) HIPCHK(hipStreamSynchronize(stream));  // job time excludes earlier queued work
   const double tj0 = prof ? now() : 0.0;
-  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off, J.stage, J.pstage};
+  FactorArgs a{J.d_tasks, J.d_off, J.d_nt, J.d_inv_off, J.d_err, J.d_tmap, J.d_tmap_off, J.stage, J.pstage,
+               J.fp32 ? mfma_f32 : 16};
   const size_t nl = J.sched.launches.size();
   if (prof)
     while (events.size() < 2 * nl) {
@@ -2446,6 +2448,7 @@ void mlbddc_default_options(mlbddc_options* o) {
   o->side_stream = 1;
   o->stage_cols = 0;
   o->mv_group_tiles = 0;
+  o->mfma_f32 = 0;
 }
 
 mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbddc_allocator* alloc, void* stream) {
@@ -2469,6 +2472,7 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
   if (o.device < 0 || o.device >= ndev || !(o.rtol > 0) || o.max_iter < 1 ||
       (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED) ||
       (o.stage_cols != 0 && o.stage_cols != 16 && o.stage_cols != 32 && o.stage_cols != 64) ||
+      (o.mfma_f32 != 0 && o.mfma_f32 != 16 && o.mfma_f32 != 32) ||
       (o.mv_group_tiles != 0 && o.mv_group_tiles != 1 && o.mv_group_tiles != 2)) {
     g_create_error.status = MLBDDC_E_ARG;
     g_create_error.message = "invalid options";
@@ -2507,6 +2511,10 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
         if (panel == 16 || panel == 32 || panel == 64) h->h.panel_stage[prec == "f32" ? 1 : 0] = panel;
         continue;
       }
+      if (job == "SHAPE") {  // FP32 MFMA shape of the tile products
+        if (prec == "f32" && (panel == 16 || panel == 32)) h->h.mfma_f32 = panel;
+        continue;
+      }
       if (panel < 1 || panel > 16) continue;
       if (!(ls >> stage) || (stage != 16 && stage != 32 && stage != 64)) stage = 0;
       h->h.tune.push_back({job == "M" ? 1 : 0, prec == "f32" ? 1 : 0, bucket, panel, stage});
@@ -2514,6 +2522,7 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
     h->h.opt.tune_table = nullptr;  // the path is not kept
   }
   if (o.mv_group_tiles > 0) h->h.mv_tpw[0] = h->h.mv_tpw[1] = o.mv_group_tiles;
+  if (o.mfma_f32 > 0) h->h.mfma_f32 = o.mfma_f32;
   h->h.stream = (hipStream_t)stream;
   if (alloc) {
     h->h.ext_alloc = *alloc;

@@ -142,7 +142,7 @@ class Solver:
     def __init__(self, precision: str = "fp64", rtol: float = 1e-8, max_iter: int = 1000, weights: str = "stiffness",
                  device: int = 0, panel_tiles: int = 0, use_graph: bool = False, panel_tiles_precond: int = 0,
                  tune_table: Optional[str] = TUNE_TABLE, lookahead: bool = False, side_stream: bool = True,
-                 stage_cols: int = 0, mv_group_tiles: int = 0):
+                 stage_cols: int = 0, mv_group_tiles: int = 0, mfma_f32: int = 0):
         lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the BDDC library needs a HIP device")
@@ -163,6 +163,7 @@ class Solver:
         opt.side_stream = 1 if side_stream else 0
         opt.stage_cols = stage_cols
         opt.mv_group_tiles = mv_group_tiles
+        opt.mfma_f32 = mfma_f32
         opt.device = device
         self.opt = opt
         with torch.cuda.device(self.device):
