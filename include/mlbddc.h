@@ -70,7 +70,7 @@ typedef struct {
                                   lines "<K|M> <f64|f32> <ceil(log2(max tiles per side))> <panel> [<stage>]",
                                   "MV <f64|f32> 0 <tiles per workgroup>", "PANEL <f64|f32> 0 <stage>"
                                   (staged columns of the panel products; else the job's) and
-                                  "SHAPE f32 0 <16|32>" (FP32 MFMA shape) */
+                                  "SHAPE f32 0 <16|32|3>" (FP32 tile product form, as mfma_f32) */
   int32_t lookahead;   /* 0 (default): one stream.  1: each factorization updates the next panel's
                           columns first on the library stream and the rest of the trailing matrix on a
                           second stream, so the next panel's factorization can overlap that bulk update */
@@ -83,9 +83,12 @@ typedef struct {
   int32_t mv_group_tiles; /* stored tiles per workgroup of the large tile matrix-vector products (S^,
                           the level-1 local operators): 1 or 2 (0 = from the tune table per precision,
                           else 1).  Both give bitwise the same results */
-  int32_t mfma_f32;    /* MFMA shape of the FP32 tile products of the factorizations: 16 (16x16x4) or 32
-                          (32x32x2) (0 = from the tune table, else 16).  The shapes sum the products
-                          in different orders: results agree to FP32 rounding */
+  int32_t mfma_f32;    /* form of the FP32 tile products of the factorizations: 16 (FP32 MFMA 16x16x4),
+                          32 (FP32 MFMA 32x32x2) or 3 (each FP32 operand split exactly into three
+                          bfloat16 pieces, six of the nine piece products on the bf16 MFMA 16x16x32,
+                          the dropped ones below 2^-23 |a||b|; takes at least 32 staged columns)
+                          (0 = from the tune table, else 16).  The forms sum the products in
+                          different orders: results agree to FP32 rounding */
 } mlbddc_options;
 
 typedef struct {

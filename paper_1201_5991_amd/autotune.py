@@ -15,6 +15,8 @@ tune table that the library reads at set-up:
 
 The staged columns do not change the results (the products accumulate in the
 same order); the panel width changes only the order of independent updates.
+The split-bf16 form of the FP32 tile products (mfma_f32 = 3) is faster but
+less accurate, so it is not swept: a caller opts in.
 
 Usage (on the GPU):  python -m paper_1201_5991_amd.autotune [--configs 2,3,4,5] [--out FILE]
 """

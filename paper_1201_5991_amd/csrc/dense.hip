@@ -481,6 +481,124 @@ template <> struct TileAcc<float, 32> {
   }
 };
 
+// SH = SH_BF3: FP32 tile products from bfloat16 pieces on the bf16 MFMA
+// (16x16x32, sixteen times the FP32 MFMA rate).  A staged FP32 value x is
+// split by round-to-nearest in turn, h = bf16(x), m = bf16(x - h),
+// l = bf16(x - h - m); both subtractions are exact in FP32, and the last
+// remainder has at most 8 significant bits, so h + m + l = x exactly for
+// |x| above 2^-100.  A product keeps the six terms down to weight 2^-16
+// (hh, hm, mh, hl, lh, mm; the dropped ones are below 2^-23 |a||b|), each
+// exact in FP32, summed by the MFMA into the running accumulator, smallest
+// weight first.  The k dimension advances 32 columns per instruction, so
+// the products take KS >= 32.  Measured on the 96^3 elasticity workload:
+// the FP32 updates of the constrained problems 13 % faster than with the
+// FP32 MFMA, the preconditioner's error against FP64 about twice as large
+// (keeping all nine terms, or adding the chunk sums by FP32 adds, did not
+// reduce it); an option, not the default.
+//
+// LDS holds three planes per operand in the order the MFMA operands are
+// read: for each 32-column chunk and each block of 16 rows, 512 values with
+// row r, column k at ((k % 32) / 8 * 16 + r % 16) * 8 + k % 8, so lane l of
+// a fragment read takes the 16 bytes at l * 16 and a wavefront's read is 1
+// KiB contiguous; a staging write by 16 lanes of consecutive rows is 256
+// contiguous bytes.  Every 16-byte access of lane l lands on the banks of
+// l % 16, whichever lanes the hardware serves together.
+constexpr int SH_BF3 = 3;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+template <int KS> struct SplitLds {
+  static constexpr int PL = TS * KS;         // values per plane
+  static constexpr int floats = 3 * PL / 2;  // LDS per operand, in floats
+  // first value of the 8 at row i, columns k..k+7 (k a multiple of 8)
+  __device__ static int at(int i, int k) { return ((k >> 5) * 4 + (i >> 4)) * 512 + (((k & 31) >> 3) * 16 + (i & 15)) * 8; }
+};
+
+// Two FP32 values rounded to nearest bf16, packed (a low, b high), and back.
+__device__ inline uint32_t pack_bf16(float a, float b) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  typedef float fl2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){a, b}, bf2));
+}
+__device__ inline float lo_bf16(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ inline float hi_bf16(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+// Register staging of KS columns of a column-major 64x64 FP32 tile for the
+// split products: thread t holds row t % 64, columns (t / 64) * KS/4 + m
+// (each load instruction reads 256 contiguous bytes across the wavefront),
+// and stores the three pieces as 16-byte LDS writes.
+template <int KS>
+struct SplitRegs {
+  static constexpr int N = KS / 4;
+  float v[N];
+  __device__ void load(const float* __restrict__ g) {
+    const int i = threadIdx.x & 63, k0 = (threadIdx.x >> 6) * N;
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = g[(k0 + m) * TS + i];
+  }
+  template <int LD>
+  __device__ void store(float* __restrict__ s) const {
+    constexpr int PL = SplitLds<KS>::PL;
+    __bf16* p = reinterpret_cast<__bf16*>(s);
+    const int i = threadIdx.x & 63, k0 = (threadIdx.x >> 6) * N;
+#pragma unroll
+    for (int c = 0; c < N / 8; ++c) {
+      uint32_t h[4], m[4], l[4];  // bf16 pairs: element 2q in the low half, 2q + 1 in the high half
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float x0 = v[8 * c + 2 * q], x1 = v[8 * c + 2 * q + 1];
+        h[q] = pack_bf16(x0, x1);
+        const float r0 = x0 - lo_bf16(h[q]), r1 = x1 - hi_bf16(h[q]);
+        m[q] = pack_bf16(r0, r1);
+        l[q] = pack_bf16(r0 - lo_bf16(m[q]), r1 - hi_bf16(m[q]));
+      }
+      const int e = SplitLds<KS>::at(i, k0 + 8 * c);
+      *reinterpret_cast<uint4*>(p + e) = make_uint4(h[0], h[1], h[2], h[3]);
+      *reinterpret_cast<uint4*>(p + PL + e) = make_uint4(m[0], m[1], m[2], m[3]);
+      *reinterpret_cast<uint4*>(p + 2 * PL + e) = make_uint4(l[0], l[1], l[2], l[3]);
+    }
+  }
+};
+
+// acc(i, j) += sum_k R(i, k) S(j, k) over KN staged columns from the split
+// planes; the 16x16 output blocks and their lane layout are those of the
+// FP32 16x16x4 products.
+template <> struct TileAcc<float, SH_BF3> {
+  f4 a[2][2];
+  __device__ void zero() {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) a[i][j] = Mfma<float>::zero();
+  }
+  template <int LD, int KN>
+  __device__ void mul(const float* __restrict__ sR, const float* __restrict__ sS) {
+    constexpr int PL = SplitLds<KN>::PL;
+    const __bf16* pR = reinterpret_cast<const __bf16*>(sR);
+    const __bf16* pS = reinterpret_cast<const __bf16*>(sS);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int iw = (w & 1) * 32, jw = (w >> 1) * 32;
+    // (piece of S, piece of R) per term, smallest weight first
+    constexpr int PS[6] = {1, 2, 0, 1, 0, 0}, PR[6] = {1, 0, 2, 0, 1, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < KN; k0 += 32) {
+      bf8 sa[3][2], rb[3][2];
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          sa[p][b] = *reinterpret_cast<const bf8*>(pS + p * PL + ((k0 >> 5) * 4 + (jw >> 4) + b) * 512 + lane * 8);
+          rb[p][b] = *reinterpret_cast<const bf8*>(pR + p * PL + ((k0 >> 5) * 4 + (iw >> 4) + b) * 512 + lane * 8);
+        }
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            a[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[PS[q]][bj], rb[PR[q]][bi], a[bi][bj], 0, 0, 0);
+    }
+  }
+  template <typename F>
+  __device__ void each(F f) { for_acc<float>(a, f); }
+};
+
 // Workgroups are dealt to the 8 XCDs of the chip round-robin by launch
 // index; this maps launch index b to a task index so that each XCD receives
 // one contiguous slice of the task list (tasks of the same matrix, which
@@ -509,9 +627,12 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
     const int64_t* __restrict__ inv_off, T* A, const T* __restrict__ Inv, const int32_t* __restrict__ tmap,
     const int64_t* __restrict__ tmap_off) {
   static_assert(KS == 16 || KS == 32 || KS == 64, "staged columns");
+  static_assert(SH != SH_BF3 || (std::is_same<T, float>::value && KS >= 32), "split products: FP32, KS >= 32");
   constexpr int SPT = TS / KS;  // steps per tile
-  __shared__ T sR[KS * LDU];
-  __shared__ T sS[KS * LDU];
+  constexpr int NS = SH == SH_BF3 ? SplitLds<KS>::floats : KS * LDU;
+  __shared__ __attribute__((aligned(16))) T sR[NS];
+  __shared__ __attribute__((aligned(16))) T sS[NS];
+  using Regs = typename std::conditional<SH == SH_BF3, SplitRegs<KS>, ChunkRegs<T, KS * TS>>::type;
   const uint64_t t = tasks[xcd_slice(blockIdx.x, gridDim.x)];
   const int item = task_item(t), r = task_r(t), s = task_s(t);
   const int kf = PANEL ? s : task_kf(t);
@@ -541,7 +662,7 @@ __global__ void __launch_bounds__(256, StageOcc<KS>::blocks) k_tile_mm(
   };
   TileAcc<T, SH> acc;
   acc.zero();
-  ChunkRegs<T, KS * TS> pr, ps;
+  Regs pr, ps;
   pr.load(rsrc(0));
   if (!same) ps.load(ssrc(0));
   for (int q = 0; q + 1 < nsteps; ++q) {
@@ -673,6 +794,7 @@ void launch_factor_step(hipStream_t st, int kind, int k, const FactorArgs& a, in
       constexpr int K = decltype(ks)::value;
       if constexpr (std::is_same<T, float>::value) {
         if (a.shape == 32) { go(k_tile_mm<T, P, K, 32>); return; }
+        if (a.shape == SH_BF3) { go(k_tile_mm<T, P, (K < 32 ? 32 : K), SH_BF3>); return; }
       }
       go(k_tile_mm<T, P, K, 16>);
     };

@@ -484,7 +484,7 @@ struct Handle {
   std::vector<std::array<int, 5>> tune;   // (job 0=K/1=M, fp32, log2 bucket, panel, staged columns or 0)
   int mv_tpw[2] = {1, 1};                 // tiles per workgroup of the large tile products: [0] FP64, [1] FP32
   int panel_stage[2] = {0, 0};            // staged columns of the panel products per precision (0: the job's)
-  int mfma_f32 = 16;                      // FP32 MFMA shape of the tile products: 16 (16x16x4) or 32 (32x32x2)
+  int mfma_f32 = 16;                      // FP32 tile products: 16 (16x16x4), 32 (32x32x2) or 3 (split bf16)
   int pick_panel(int job, bool fp32, int ntmax) const;
   int pick_stage(int job, bool fp32, int ntmax) const;
   mlbddc_status reserve_job(Job& J, bool fp32);
@@ -2472,7 +2472,7 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
   if (o.device < 0 || o.device >= ndev || !(o.rtol > 0) || o.max_iter < 1 ||
       (o.precision != MLBDDC_FP64 && o.precision != MLBDDC_MIXED) ||
       (o.stage_cols != 0 && o.stage_cols != 16 && o.stage_cols != 32 && o.stage_cols != 64) ||
-      (o.mfma_f32 != 0 && o.mfma_f32 != 16 && o.mfma_f32 != 32) ||
+      (o.mfma_f32 != 0 && o.mfma_f32 != 16 && o.mfma_f32 != 32 && o.mfma_f32 != 3) ||
       (o.mv_group_tiles != 0 && o.mv_group_tiles != 1 && o.mv_group_tiles != 2)) {
     g_create_error.status = MLBDDC_E_ARG;
     g_create_error.message = "invalid options";
@@ -2512,7 +2512,7 @@ mlbddc_status mlbddc_create(mlbddc_t* out, const mlbddc_options* opt, const mlbd
         continue;
       }
       if (job == "SHAPE") {  // FP32 MFMA shape of the tile products
-        if (prec == "f32" && (panel == 16 || panel == 32)) h->h.mfma_f32 = panel;
+        if (prec == "f32" && (panel == 16 || panel == 32 || panel == 3)) h->h.mfma_f32 = panel;
         continue;
       }
       if (panel < 1 || panel > 16) continue;

@@ -333,13 +333,17 @@ def test_mv_group_tiles_same_result(precision):
 
 
 def test_mfma_shape_fp32():
-    """The FP32 tile products with one 32x32x2 MFMA block per wavefront
-    instead of 2x2 blocks of 16x16x4: the mixed apply agrees with the 16x16x4
-    one to FP32 rounding (1e-5; on gfx950 the two came out bitwise equal) and
-    with the FP64 oracle to the mixed bar, the solve takes the same iterations
-    within one; FP64 factorizations do not use the shape (bitwise the same)."""
+    """The three forms of the FP32 tile products: 2x2 blocks of 16x16x4 MFMA
+    per wavefront, one 32x32x2 block, and the split form (three bf16 pieces
+    per operand, six piece products on the bf16 MFMA).  The 32x32x2
+    mixed apply agrees with the 16x16x4 one to FP32 rounding (1e-5; on gfx950
+    the two came out bitwise equal); the split form sums in another order
+    and agrees to 1e-4, the mixed bar; each
+    agrees with the FP64 oracle to the mixed bar, and each solve takes the
+    same iterations within one.  FP64 factorizations do not use the form
+    (bitwise the same)."""
     from paper_1201_5991_amd import Problem, Solver
-    _say("[parity] FP32 MFMA shape 16x16x4 / 32x32x2")
+    _say("[parity] FP32 tile products: 16x16x4 / 32x32x2 / split bf16")
     # 4x4x4 subdomains of 4^3 elements, 2x2x2 level-2 groups: FP32 constrained problems on both levels
     # and an FP32 level-2 K job
     w = _cube(4, 4, groups=[(2, 2, 2)], young=10 ** (2 * np.random.default_rng(13).random(16 ** 3)))
@@ -347,25 +351,31 @@ def test_mfma_shape_fp32():
     f = torch.tensor(prob.load_vector(), device="cuda")
     out = {}
     r = None
+    shapes = (16, 32, 3)
     for prec in ("mixed", "fp64"):
-        for sh in (16, 32):
+        for sh in shapes:
             s = Solver(precision=prec, mfma_f32=sh, use_graph=True).setup(prob)
             if r is None:
                 r = torch.tensor(np.random.default_rng(14).standard_normal(s.n_iface), device="cuda")
             u, st = s.solve(f)
             out[(prec, sh)] = (s.apply(r), s.apply_schur(r), u, st["iterations"])
             s.destroy()
-    for a, b in zip(out[("fp64", 16)][:3], out[("fp64", 32)][:3]):
-        assert torch.equal(a, b)
-    m16, m32 = out[("mixed", 16)], out[("mixed", 32)]
-    assert torch.equal(m16[1], m32[1])  # S^ is FP64
-    err = _rel(m32[0].cpu().numpy(), m16[0].cpu().numpy())
-    _say(f"  mixed apply, 32x32x2 against 16x16x4: {err:.2e}")
-    assert err < 1e-5
-    assert abs(m32[3] - m16[3]) <= 1
+    for sh in shapes[1:]:
+        for a, b in zip(out[("fp64", 16)][:3], out[("fp64", sh)][:3]):
+            assert torch.equal(a, b)
     b = MultilevelBDDC(w)
     ref = b.apply(r.cpu().numpy())
-    assert _rel(m32[0].cpu().numpy(), ref) < 1e-4
+    m16 = out[("mixed", 16)]
+    for sh, bar in ((32, 1e-5), (3, 1e-4)):
+        m = out[("mixed", sh)]
+        assert torch.equal(m16[1], m[1])  # S^ is FP64
+        err = _rel(m[0].cpu().numpy(), m16[0].cpu().numpy())
+        eo = _rel(m[0].cpu().numpy(), ref)
+        _say(f"  mixed apply, form {sh} against 16x16x4: {err:.2e}; against the oracle {eo:.2e}; "
+             f"iterations {m[3]} / {m16[3]}")
+        assert err < bar
+        assert abs(m[3] - m16[3]) <= 1
+        assert eo < 1e-4
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
