@@ -257,7 +257,7 @@ def cpu_baseline(w, levels: int, gpu_iterations: int):
     """The FP64 oracle, as it stands, on a bounded sample of the benchmark
     workload, scaled to the whole workload's time-to-solution.
 
-    Sample: the corner block of 3x3x3 of the workload's subdomains (the same
+    Sample: the corner block of 5x5x5 of the workload's subdomains (the same
     subdomain size and the same element moduli, the clamped face included),
     run through the oracle's full pipeline (set-up, condensation, PCG to
     1e-8, recovery) at two levels.  The oracle's work is a loop over
@@ -279,7 +279,7 @@ def cpu_baseline(w, levels: int, gpu_iterations: int):
         cores = os.cpu_count() or 1
     nsub_axis = [len(c) - 1 for c in w.cuts]
     el = [int(np.diff(c)[0]) for c in w.cuts]
-    k = 3
+    k = 5
     n = [k * e for e in el]
     young = w.young.reshape(w.n_el[::-1])[: n[2], : n[1], : n[0]].ravel()
     ws = box_workload("sample", "elasticity", tuple(n), [uniform_cuts(n[d], k) for d in range(3)], young=young)
@@ -304,7 +304,7 @@ def cpu_baseline(w, levels: int, gpu_iterations: int):
     value = scale * (t_setup + t_cond + t_rec + per_it * its_full)
     out = {"value": value, "unit": "s (time-to-solution of the whole workload, scaled from the sample)",
            "cores": int(cores), "kind": "oracle",
-           "sample": (f"FP64 oracle (SciPy SuperLU per subdomain, NumPy) on the corner 3x3x3 block of the workload's "
+           "sample": (f"FP64 oracle (SciPy SuperLU per subdomain, NumPy) on the corner {k}x{k}x{k} block of the workload's "
                       f"subdomains ({n[0]}x{n[1]}x{n[2]} elements, the same 8^3-element subdomains and moduli), 2 levels: "
                       f"set-up {t_setup:.2f} s, condensation {t_cond:.2f} s, {res.iterations} PCG iterations "
                       f"{t_pcg:.2f} s, recovery {t_rec:.2f} s; scaled x{scale:g} subdomains and to {its_full} "
