@@ -155,12 +155,12 @@ def rooflines(R: dict, mode: str, workload: str):
 
 
 def run_mode(prob, f, precision: str, steps: int, warmup: int, applies: int, panel: int = 0, graph: bool = True,
-             lookahead: bool = False):
+             lookahead: bool = False, fp32_form: int = 0):
     import torch
     from paper_1201_5991_amd import Solver
     torch.cuda.synchronize()
     m0 = torch.cuda.memory_allocated()
-    s = Solver(precision=precision, panel_tiles=panel, use_graph=graph, lookahead=lookahead)
+    s = Solver(precision=precision, panel_tiles=panel, use_graph=graph, lookahead=lookahead, mfma_f32=fp32_form)
     mem = None
     t_cold = None
     for _ in range(warmup):
@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--panel", type=int, default=0, help="tile columns per factorization panel (0 = library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG iterations eagerly instead of replaying a HIP graph")
+    ap.add_argument("--fp32-form", type=int, default=0, choices=(0, 16, 32, 3),
+                    help="form of the FP32 tile products: 16 / 32 (FP32 MFMA shape), 3 (split bf16); 0 = tune table")
     ap.add_argument("--lookahead", action="store_true",
                     help="factor on two streams (next panel beside the bulk trailing update)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -352,7 +354,7 @@ def main():
     out = {}
     for m in modes:
         out[m] = run_mode(prob, f, m, args.steps, args.warmup, args.applies, args.panel, not args.no_graph,
-                          args.lookahead)
+                          args.lookahead, args.fp32_form)
     main_mode = "mixed" if "mixed" in out else modes[0]
     R = out[main_mode]
     roof, roof_setup = rooflines(R, main_mode, w.name)
@@ -372,7 +374,8 @@ def main():
         "config": {"workload": w.name, "dofs": int(prob.n_dofs), "levels": int(prob.n_levels),
                    "subdomains": [int(c[0]) for c in counts], "interface": int(counts[0][1]),
                    "coarse": [int(c[2]) for c in counts], "value_mode": main_mode,
-                   "pcg_graph": not args.no_graph, "lookahead": args.lookahead},
+                   "pcg_graph": not args.no_graph, "lookahead": args.lookahead,
+                   **({"fp32_form": args.fp32_form} if args.fp32_form else {})},
         "applies_per_s": R["applies_per_s"],
         "roofline": roof,
         "roofline_setup": roof_setup,
