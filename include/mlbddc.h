@@ -86,7 +86,8 @@ typedef struct {
   int32_t mfma_f32;    /* form of the FP32 tile products of the factorizations: 16 (FP32 MFMA 16x16x4),
                           32 (FP32 MFMA 32x32x2) or 3 (each FP32 operand split exactly into three
                           bfloat16 pieces, six of the nine piece products on the bf16 MFMA 16x16x32,
-                          the dropped ones below 2^-23 |a||b|; takes at least 32 staged columns)
+                          the dropped ones below 2^-23 |a||b|; takes at least 32 staged columns;
+                          faster, but the preconditioner's error grows two to four times)
                           (0 = from the tune table, else 16).  The forms sum the products in
                           different orders: results agree to FP32 rounding */
 } mlbddc_options;

@@ -492,9 +492,10 @@ template <> struct TileAcc<float, 32> {
 // weight first.  The k dimension advances 32 columns per instruction, so
 // the products take KS >= 32.  Measured on the 96^3 elasticity workload:
 // the FP32 updates of the constrained problems 13 % faster than with the
-// FP32 MFMA, the preconditioner's error against FP64 about twice as large
-// (keeping all nine terms, or adding the chunk sums by FP32 adds, did not
-// reduce it); an option, not the default.
+// FP32 MFMA, the preconditioner's error against FP64 two to four times as
+// large (2.5e-3 against 5.6e-4 at four levels; keeping all nine terms, or
+// adding the chunk sums by FP32 adds, did not reduce it); an option, not the
+// default.
 //
 // LDS holds three planes per operand in the order the MFMA operands are
 // read: for each 32-column chunk and each block of 16 rows, 512 values with
